@@ -1,0 +1,153 @@
+/*
+ * FP64 reference ("oracle") for DAS and DMAS confocal imaging.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline of the benchmark may load this library.  It is deliberately plain and
+ * slow: every quantity is computed straight from its definition, in double
+ * precision, with no tiling, no reuse across voxels and no regrouping of sums.
+ * It shares no source, header or constant with the GPU library.
+ *
+ * The method (Section II of the paper):
+ *   delay      Eq. (1), read as the monostatic round trip in samples,
+ *              n_i(r) = (2 |r - a_i| / v - t0) / dt
+ *              (the printed equation divides by 2 c dt; Eq. (2) with the
+ *              transmitter equal to the receiver shows the factor 2 multiplies
+ *              the path length, and v is the speed in the medium).
+ *   alignment  Eq. (3) argument: the trace is advanced by the delay, so the echo
+ *              of a scatterer at r lands at window offset k = 0 for every antenna.
+ *              Fractional delays use linear interpolation; samples outside [0,T)
+ *              are zero.
+ *   DAS        Eq. (3): I(r) = sum_k ( sum_i s_i(r,k) )^2 over a centred window
+ *              k = -h..h of W = 2h+1 samples.
+ *   DMAS       Section II-B (the figure with its equation is not available):
+ *              every pair of aligned signals is multiplied and the products are
+ *              summed, then the windowed energy is taken:
+ *              I(r) = sum_k ( sum_{i<j} s_i(r,k) s_j(r,k) )^2.
+ *              Evaluated here as the literal O(M^2) double loop.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Y_i[m] with zero outside the recorded samples. */
+static double sample_or_zero(const float *trace, int n_samp, long m)
+{
+    if (m < 0 || m >= n_samp)
+        return 0.0;
+    return (double)trace[m];
+}
+
+/* Eq. (1) (monostatic round trip, reading above), in samples. */
+static double round_trip_delay(const double r[3], const float *a, double v, double dt, double t0)
+{
+    double dx = r[0] - (double)a[0];
+    double dy = r[1] - (double)a[1];
+    double dz = r[2] - (double)a[2];
+    double dist = sqrt(dx * dx + dy * dy + dz * dz);
+    return (2.0 * dist / v - t0) / dt;
+}
+
+/* Eq. (3) argument: trace value at fractional position tau + k, linear interpolation. */
+static double aligned_sample(const float *trace, int n_samp, double tau, int k)
+{
+    double x = tau + (double)k;
+    double n = floor(x);
+    double f = x - n;
+    long m = (long)n;
+    return (1.0 - f) * sample_or_zero(trace, n_samp, m) + f * sample_or_zero(trace, n_samp, m + 1);
+}
+
+/* Energy of one focal point. beamformer: 0 = DAS (Eq. 3), 1 = DMAS (direct pairwise). */
+static double focal_point_energy(int beamformer, int n_ant, int n_samp, const float *ant_pos,
+                                 const float *traces, double dt, double t0, double v, int window,
+                                 const double r[3], double *tau, double *s)
+{
+    int h = (window - 1) / 2;
+    for (int i = 0; i < n_ant; ++i)
+        tau[i] = round_trip_delay(r, ant_pos + 3 * i, v, dt, t0);
+    double energy = 0.0;
+    for (int k = -h; k <= h; ++k) {
+        for (int i = 0; i < n_ant; ++i)
+            s[i] = aligned_sample(traces + (size_t)i * n_samp, n_samp, tau[i], k);
+        double sum;
+        if (beamformer == 0) {
+            sum = 0.0;
+            for (int i = 0; i < n_ant; ++i)
+                sum += s[i];
+        } else {
+            sum = 0.0;
+            for (int i = 0; i < n_ant - 1; ++i)
+                for (int j = i + 1; j < n_ant; ++j)
+                    sum += s[i] * s[j];
+        }
+        energy += sum * sum;
+    }
+    return energy;
+}
+
+/*
+ * Image an explicit list of voxels of a grid.
+ *   idx    [n][3] int32 voxel indices (ix, iy, iz); position = origin + idx * pitch
+ *   out    [n] energies
+ *   n_threads  OpenMP threads (<= 0: library default).  Returns the count used.
+ */
+int oracle_image_indices(int beamformer, int n_ant, int n_samp, const float *ant_pos,
+                         const float *traces, double dt, double t0, double v, int window,
+                         const double *origin, const double *pitch, long n, const int32_t *idx,
+                         double *out, int n_threads)
+{
+    int used = 1;
+#ifdef _OPENMP
+    if (n_threads <= 0)
+        n_threads = omp_get_max_threads();
+    used = n_threads;
+#pragma omp parallel num_threads(n_threads)
+#endif
+    {
+        double *tau = (double *)malloc(sizeof(double) * (size_t)n_ant);
+        double *s = (double *)malloc(sizeof(double) * (size_t)n_ant);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+        for (long p = 0; p < n; ++p) {
+            double r[3];
+            for (int d = 0; d < 3; ++d)
+                r[d] = origin[d] + (double)idx[3 * p + d] * pitch[d];
+            out[p] = focal_point_energy(beamformer, n_ant, n_samp, ant_pos, traces, dt, t0, v,
+                                        window, r, tau, s);
+        }
+        free(tau);
+        free(s);
+    }
+    return used;
+}
+
+/* Same, at explicit positions [n][3] (metres). */
+int oracle_image_points(int beamformer, int n_ant, int n_samp, const float *ant_pos,
+                        const float *traces, double dt, double t0, double v, int window, long n,
+                        const double *pts, double *out, int n_threads)
+{
+    int used = 1;
+#ifdef _OPENMP
+    if (n_threads <= 0)
+        n_threads = omp_get_max_threads();
+    used = n_threads;
+#pragma omp parallel num_threads(n_threads)
+#endif
+    {
+        double *tau = (double *)malloc(sizeof(double) * (size_t)n_ant);
+        double *s = (double *)malloc(sizeof(double) * (size_t)n_ant);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+        for (long p = 0; p < n; ++p)
+            out[p] = focal_point_energy(beamformer, n_ant, n_samp, ant_pos, traces, dt, t0, v,
+                                        window, pts + 3 * p, tau, s);
+        free(tau);
+        free(s);
+    }
+    return used;
+}
