@@ -1,0 +1,250 @@
+/*
+ * uwb.h -- C ABI of the MI355X (gfx950) library for confocal microwave imaging
+ * with a coarse-to-fine segment walk (Ettefagh, Moghaddam, Vahidian, "A Novel
+ * Low-Complexity Framework in Ultra-Wideband Imaging for Breast Cancer
+ * Detection", arXiv:1709.02549).
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers unless the comment says "host".  The caller
+ *    owns every buffer.  Nothing here allocates device memory, except the plan
+ *    objects of the batch interface (which own what they allocate).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *    enqueued asynchronously on it; results are ready when the stream is.
+ *  - The return value is a status: UWB_OK (0) or a negative UWB_E* code.  All
+ *    arguments are validated before anything is enqueued, so an error never
+ *    leaves partial work in flight.  No call throws or aborts.
+ *  - Traces are not scanned for NaN/Inf: non-finite samples propagate into the
+ *    affected voxels.  Antenna positions live in device memory and are not
+ *    scanned either; a non-finite position yields non-finite energies, never
+ *    an out-of-bounds access.
+ *  - Calls are stateless and reentrant; plan objects are not thread-safe.
+ */
+#ifndef UWB_H
+#define UWB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum uwb_status {
+    UWB_OK = 0,
+    UWB_EINVAL = -1,        /* null pointer, size or value out of its domain */
+    UWB_ERANGE = -2,        /* output or workspace too small, too many levels */
+    UWB_ENOMEM = -3,        /* allocation inside a plan failed */
+    UWB_EHIP = -4,          /* HIP launch or runtime error */
+    UWB_EUNSUPPORTED = -5   /* valid request outside what this build handles */
+};
+
+enum uwb_beamformer { UWB_DAS = 0, UWB_DMAS = 1 };
+
+/* Largest supported energy window (samples) and trace length. */
+#define UWB_MAX_WINDOW 31
+#define UWB_MAX_SAMPLES 65536
+
+/*
+ * One monostatic scan (Section II-A): M antennas at r_i, each recording Y_i.
+ *   ant_pos  device [n_ant][3] fp32, metres (z = 0 for a planar setup)
+ *   traces   device [n_ant][n_samp] fp32, antenna-major, row stride n_samp;
+ *            sample m was taken at time t0 + m*dt
+ *   dt       sampling period, s (> 0)
+ *   t0       time of sample 0 relative to the excitation peak, s (finite)
+ *   v        propagation speed in the medium, m/s (> 0)
+ * Requires n_ant >= 1 and 2 <= n_samp <= UWB_MAX_SAMPLES.
+ */
+typedef struct {
+    int32_t n_ant, n_samp;
+    const float *ant_pos;
+    const float *traces;
+    double dt, t0, v;
+} uwb_scan;
+
+/*
+ * A batch of same-shaped scans, e.g. many acquisitions imaged on one grid.
+ *   ant_pos  device [n_scans][n_ant][3] fp32
+ *   traces   device [n_scans][n_ant][n_samp] fp32
+ *   params   device [n_scans][3] fp64: (dt, t0, v) per scan
+ *   v_min, dt_min  host lower bounds of v and dt over the batch (> 0), used to
+ *            size on-chip staging; a scan below them gets NaN energies
+ */
+typedef struct {
+    int32_t n_scans, n_ant, n_samp;
+    const float *ant_pos;
+    const float *traces;
+    const double *params;
+    double v_min, dt_min;
+} uwb_scan_batch;
+
+/*
+ * Focal points "according to the desired resolution" (Section II-A): a regular
+ * grid of voxel centres  r(ix,iy,iz) = origin + (ix,iy,iz) * pitch.
+ * dims = (nx, ny, nz), each >= 1; nz == 1 is a planar (2D) image.  Images are
+ * stored [nz][ny][nx] fp32, x fastest.  pitch must be finite and > 0.
+ */
+typedef struct {
+    double origin[3];
+    double pitch[3];
+    int32_t dims[3];
+} uwb_grid;
+
+/*
+ * DAS energy image, Eq. (3) with the Eq. (1) delay:
+ *   tau_i(r) = (2 |r - r_i| / v - t0) / dt            (round trip, in samples)
+ *   s_i(r,k) = Y_i at fractional sample tau_i(r) + k (linear interpolation,
+ *              zero outside [0, n_samp)),  k = -h..h,  window = 2h+1
+ *   I(r)     = sum_k ( sum_i s_i(r,k) )^2
+ * window: odd, 1 <= window <= UWB_MAX_WINDOW (11 in the reference workloads).
+ * img: device [nz][ny][nx] fp32, written entirely.  FP32 arithmetic.
+ */
+int uwb_das(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img, void *stream);
+
+/*
+ * DMAS energy image (Section II-B): the aligned signals are multiplied in
+ * pairs and the products summed before the windowed energy,
+ *   I(r) = sum_k ( sum_{i<j} s_i(r,k) s_j(r,k) )^2 .
+ * Same arguments and layout as uwb_das.  FP32 arithmetic; the pairwise sum is
+ * regrouped as sum_j s_j * (sum_{i<j} s_i), which is exact in real arithmetic.
+ */
+int uwb_dmas(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img, void *stream);
+
+/* Batched forms: img is device [n_scans][nz][ny][nx]. */
+int uwb_das_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img,
+                  void *stream);
+int uwb_dmas_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img,
+                   void *stream);
+
+/*
+ * Detection (Section II-A): the tumour is at the voxel of maximal energy.
+ * The decision is taken in FP64 so it does not depend on FP32 rounding:
+ * every voxel whose FP32 energy is within 1e-3 (relative) of the FP32 maximum
+ * is re-evaluated in FP64 from the scan, and the winner is the lowest linear
+ * index (x fastest) among candidates whose FP64 energy is >= max - 1e-12*|max|.
+ *   img      the image produced by uwb_das / uwb_dmas for the same scan
+ *   out      device uwb_peak (one per scan for the batch form)
+ *   workspace/workspace_bytes  device scratch of at least
+ *            uwb_argmax_workspace_bytes(grid, n_scans) bytes
+ */
+typedef struct {
+    int64_t index;          /* linear voxel index, x fastest */
+    double value;           /* FP64 energy of that voxel */
+    float value32;          /* its FP32 image value */
+    int32_t candidates;     /* voxels re-evaluated in FP64 */
+} uwb_peak;
+
+size_t uwb_argmax_workspace_bytes(const uwb_grid *grid, int32_t n_scans);
+int uwb_argmax(const uwb_scan *scan, const uwb_grid *grid, int32_t window, int32_t beamformer,
+               const float *img, uwb_peak *out, void *workspace, size_t workspace_bytes, void *stream);
+int uwb_argmax_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window,
+                     int32_t beamformer, const float *img, uwb_peak *out, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
+/*
+ * Coarse-to-fine segment walk (Section III).
+ *
+ * walk = UWB_WALK_PAPER follows the three phases as written: one image of the
+ *   whole grid on a lattice decimated by D (points at D*k + floor(D/2) along each
+ *   axis; D manual, or automatic from the smallest tumour to detect, see
+ *   uwb_auto_decimation); then ROI selection: split the current box into 4
+ *   (8 in 3D) at x0 + floor(side/2), score each child on the decimated samples
+ *   inside it, keep the best, widen it by the sliding frame
+ *   floor(frame_level * child side) on each end (clipped to the grid), repeat;
+ *   stop when a child would hold fewer than 4 samples, after max_depth
+ *   splits, or by the W/B rule.
+ * walk = UWB_WALK_PER_LEVEL re-images every box on a g^d lattice (step
+ *   side/g); boxes stay aligned (grid side = g * 2^L), frame_level only widens
+ *   each child's scoring set, and the walk ends at box side g.
+ * In both modes the final ROI is the last box widened by
+ *   floor(frame_final * side) on each end, imaged at full resolution; the
+ *   detection is its maximal-energy voxel (same rule as uwb_argmax).
+ *
+ * Metrics (Section III, decision metric): mean, population variance, max,
+ *   max/mean, and Eq. (5): M = (1 - a) mu_c + a var_c with
+ *   a = (var_c - var_p) / var_c (a = 0 if var_c = 0), var_p being the variance
+ *   of the parent box's samples; Eq. (5) values are divided by the parent's
+ *   sample maximum first.  UWB_EQ5_CLAMPED clamps a to [0, 1].
+ * term = UWB_TERM_WB adds the Eq. (6)-(7) stop: with the previous and the
+ *   current box's samples as the two classes, W = sum of squared deviations
+ *   from the class means, B = sum_class n (class mean - pooled mean)^2; the first
+ *   split always proceeds, a later one stops the walk unless B grows and W
+ *   shrinks, and that split is undone.
+ * Ties among children (and voxels): lowest index among values
+ *   >= max - 1e-12*|max|.  All decisions are taken in FP64.
+ */
+typedef enum { UWB_MEAN = 0, UWB_VAR = 1, UWB_EQ5 = 2, UWB_MAX = 3, UWB_MAX_OVER_MEAN = 4,
+               UWB_EQ5_CLAMPED = 5 } uwb_metric;
+typedef enum { UWB_TERM_FIXED_DEPTH = 0, UWB_TERM_WB = 1 } uwb_term;
+typedef enum { UWB_WALK_PER_LEVEL = 0, UWB_WALK_PAPER = 1 } uwb_walk;
+
+typedef struct {
+    int32_t beamformer;     /* UWB_DAS or UWB_DMAS */
+    int32_t walk;           /* uwb_walk */
+    int32_t coarse;         /* g, even, 2..64 (PER_LEVEL); g^d <= 4096 */
+    int32_t decimation;     /* D >= 1 (PAPER); 0 = automatic from min_tumour */
+    double min_tumour;      /* metres, automatic D */
+    int32_t max_depth;      /* 0 = as deep as the mode allows; <= UWB_MAX_LEVELS */
+    int32_t metric;         /* uwb_metric */
+    int32_t term;           /* uwb_term */
+    double frame_level;     /* >= 0 */
+    double frame_final;     /* >= 0 */
+} uwb_segment_tree;
+
+#define UWB_MAX_LEVELS 16
+
+typedef struct {
+    int32_t n_levels;                       /* splits kept */
+    int32_t term_level;                     /* splits made (n_levels + 1 if W/B undid one) */
+    int32_t decimation;                     /* D used (PAPER), 0 otherwise */
+    int32_t n_samples_level0;               /* lattice points of the first image */
+    int32_t child[UWB_MAX_LEVELS];          /* Morton child (bx + 2 by + 4 bz) per split made */
+    int32_t box[UWB_MAX_LEVELS + 1][6];     /* finest-voxel [x0,x1,y0,y1,z0,z1) before/after each split */
+    double score[UWB_MAX_LEVELS][8];        /* child metrics per split made */
+    double wb[UWB_MAX_LEVELS + 1][2];       /* (W, B) of iterations 1, 2, ... */
+    int32_t n_wb;                           /* entries of wb written */
+    int32_t roi[6];                         /* final ROI box */
+    int64_t argmax;                         /* finest-grid linear index, x fastest */
+    double peak;                            /* FP64 energy there */
+    int64_t voxels_evaluated;               /* focal points beamformed in total */
+} uwb_segment_result;
+
+/* Largest ROI (voxels) the walk can end with for this grid and tree: the
+   minimum roi_capacity.  Negative status on invalid arguments. */
+int64_t uwb_segment_roi_capacity(const uwb_grid *finest, const uwb_segment_tree *tree);
+/* Device workspace bytes needed by uwb_segment_refine(_batch) for n_scans. */
+size_t uwb_segment_workspace_bytes(const uwb_grid *finest, const uwb_segment_tree *tree, int32_t n_scans);
+
+/*
+ * out:       device uwb_segment_result (one per scan for the batch form)
+ * roi_img:   device fp32 [roi_capacity] per scan (batch: scan s at
+ *            s * roi_capacity), the final ROI image [z][y][x] of the ROI box;
+ *            may be NULL
+ * roi_capacity: >= uwb_segment_roi_capacity(...), else UWB_ERANGE
+ */
+int uwb_segment_refine(const uwb_scan *scan, const uwb_grid *finest, int32_t window,
+                       const uwb_segment_tree *tree, uwb_segment_result *out, float *roi_img,
+                       int64_t roi_capacity, void *workspace, size_t workspace_bytes, void *stream);
+int uwb_segment_refine_batch(const uwb_scan_batch *scans, const uwb_grid *finest, int32_t window,
+                             const uwb_segment_tree *tree, uwb_segment_result *out, float *roi_img,
+                             int64_t roi_capacity, void *workspace, size_t workspace_bytes,
+                             void *stream);
+
+/*
+ * Automatic spatial decimation factor (Section III; worked example in
+ * Section IV): one focal point per square inscribed in the smallest tumour,
+ * D = floor(min_tumour / (sqrt(2) * pitch)), at least 1.  Host-only, pure.
+ * Returns D >= 1, or UWB_EINVAL for non-finite or non-positive arguments.
+ */
+int uwb_auto_decimation(double min_tumour, double pitch);
+
+/* Static description of a status code (never NULL). */
+const char *uwb_status_string(int status);
+
+/* Library version string, e.g. "uwb 0.1 gfx950". */
+const char *uwb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UWB_H */

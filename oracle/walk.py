@@ -33,7 +33,8 @@ Readings taken where the text is silent or ambiguous (all shared with the GPU):
 * the split point is x0 + floor(side/2); children are numbered bx + 2 by + 4 bz;
 * variance is the population variance (1/n);
 * in Eq. (5) sigma_{i-1}^2 is the variance of the parent box's samples; values are
-  divided by the parent's sample maximum first; a = 0 when sigma_i^2 = 0; a is not clamped;
+  divided by the parent's sample maximum first; a = 0 when sigma_i^2 = 0; "eq5" keeps a
+  as printed (unclamped), "eq5_clamped" clamps a to [0, 1] (the prose's reading);
 * Eq. (6)/(7) on scalar energies: the two classes are the sample sets of the
   previous and the current box; W = sum of squared deviations from each class mean,
   B = sum_class n_class (mean_class - pooled mean)^2; the first iteration always
@@ -48,7 +49,7 @@ import math
 
 import numpy as np
 
-METRICS = ("mean", "var", "eq5", "max", "max_over_mean")
+METRICS = ("mean", "var", "eq5", "max", "max_over_mean", "eq5_clamped")
 TERMS = ("fixed", "wb")
 WALKS = ("per_level", "paper")
 MAX_LEVELS = 16
@@ -123,7 +124,7 @@ def metric_value(name: str, x: np.ndarray, parent: np.ndarray) -> float:
     if name == "max_over_mean":
         mu = _mean(x)
         return float(np.max(x)) / mu if mu != 0.0 else 0.0
-    if name == "eq5":
+    if name in ("eq5", "eq5_clamped"):
         pm = float(np.max(parent))
         if pm > 0.0:
             x = x / pm
@@ -132,6 +133,10 @@ def metric_value(name: str, x: np.ndarray, parent: np.ndarray) -> float:
         sp = _var(parent)
         mu = _mean(x)
         alpha = (sc - sp) / sc if sc > 0.0 else 0.0
+        if name == "eq5_clamped":
+            # reading of the prose after Eq. (5): the blend moves from the mean
+            # (similar variances) to the variance (distinct variances)
+            alpha = min(max(alpha, 0.0), 1.0)
         return (1.0 - alpha) * mu + alpha * sc
     raise ValueError(name)
 

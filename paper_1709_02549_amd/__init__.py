@@ -1,0 +1,329 @@
+"""Python binding of libuwb (MI355X / gfx950 DAS-DMAS imaging and segment walk).
+
+Argument marshalling only: every step runs in the HIP library behind the C ABI
+of include/uwb.h.  Tensors must be CUDA (HIP) tensors; calls are enqueued on
+torch's current stream.  If the library is not built the import of an entry
+point raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import (METRICS, TERMS, UWB_DAS, UWB_DMAS, UWB_MAX_LEVELS, WALKS, UwbError,  # noqa: F401
+                   UwbGrid, UwbPeak, UwbScan, UwbScanBatch, UwbSegmentResult, UwbSegmentTree, check, lib)
+
+__all__ = ["DeviceScan", "DeviceBatch", "das", "dmas", "image", "das_batch", "dmas_batch", "image_batch",
+           "argmax", "argmax_batch", "segment_refine", "segment_refine_batch", "auto_decimation",
+           "SegmentTree", "UwbError"]
+
+
+def _stream(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _need_cuda(t: torch.Tensor, name: str, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+
+
+@dataclasses.dataclass
+class DeviceScan:
+    """One scan resident in device memory: ant_pos [M,3] f32, traces [M,T] f32."""
+    ant_pos: torch.Tensor
+    traces: torch.Tensor
+    dt: float
+    t0: float
+    v: float
+
+    @classmethod
+    def from_host(cls, s, device="cuda"):
+        return cls(torch.as_tensor(np.ascontiguousarray(s.ant_pos, np.float32)).to(device),
+                   torch.as_tensor(np.ascontiguousarray(s.traces, np.float32)).to(device),
+                   float(s.dt), float(s.t0), float(s.v))
+
+    def c(self) -> UwbScan:
+        _need_cuda(self.ant_pos, "ant_pos")
+        _need_cuda(self.traces, "traces")
+        return UwbScan(self.traces.shape[0], self.traces.shape[1], self.ant_pos.data_ptr(), self.traces.data_ptr(),
+                       self.dt, self.t0, self.v)
+
+
+@dataclasses.dataclass
+class DeviceBatch:
+    """Same-shaped scans: ant_pos [B,M,3] f32, traces [B,M,T] f32, params [B,3] f64 (dt, t0, v)."""
+    ant_pos: torch.Tensor
+    traces: torch.Tensor
+    params: torch.Tensor
+
+    @classmethod
+    def from_host(cls, scans, device="cuda"):
+        pos = np.stack([np.asarray(s.ant_pos, np.float32) for s in scans])
+        tr = np.stack([np.asarray(s.traces, np.float32) for s in scans])
+        par = np.array([[s.dt, s.t0, s.v] for s in scans], dtype=np.float64)
+        return cls(torch.as_tensor(pos).to(device), torch.as_tensor(tr).to(device), torch.as_tensor(par).to(device))
+
+    @property
+    def n_scans(self):
+        return int(self.traces.shape[0])
+
+    def c(self) -> UwbScanBatch:
+        _need_cuda(self.ant_pos, "ant_pos")
+        _need_cuda(self.traces, "traces")
+        _need_cuda(self.params, "params", torch.float64)
+        p = self.params.detach().cpu().numpy()
+        return UwbScanBatch(self.traces.shape[0], self.traces.shape[1], self.traces.shape[2],
+                            self.ant_pos.data_ptr(), self.traces.data_ptr(), self.params.data_ptr(),
+                            float(p[:, 2].min()), float(p[:, 0].min()))
+
+
+def grid_c(g) -> UwbGrid:
+    return UwbGrid((ctypes.c_double * 3)(*[float(x) for x in g.origin]),
+                   (ctypes.c_double * 3)(*[float(x) for x in g.pitch]),
+                   (ctypes.c_int32 * 3)(*[int(x) for x in g.dims]))
+
+
+def _img_shape(g):
+    nx, ny, nz = (int(x) for x in g.dims)
+    return (nz, ny, nx)
+
+
+def image(scan: DeviceScan, grid, beamformer: int, window: int = 11, out: torch.Tensor | None = None):
+    """Full-resolution DAS (beamformer 0) or DMAS (1) image [nz, ny, nx] fp32."""
+    if out is None:
+        out = torch.empty(_img_shape(grid), dtype=torch.float32, device=scan.traces.device)
+    _need_cuda(out, "out")
+    fn = lib().uwb_dmas if beamformer == UWB_DMAS else lib().uwb_das
+    sc, gc = scan.c(), grid_c(grid)
+    check(fn(ctypes.byref(sc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)),
+          "uwb_dmas" if beamformer else "uwb_das")
+    return out
+
+
+def das(scan, grid, window=11, out=None):
+    return image(scan, grid, UWB_DAS, window, out)
+
+
+def dmas(scan, grid, window=11, out=None):
+    return image(scan, grid, UWB_DMAS, window, out)
+
+
+def image_batch(batch: DeviceBatch, grid, beamformer: int, window: int = 11, out=None):
+    if out is None:
+        out = torch.empty((batch.n_scans,) + _img_shape(grid), dtype=torch.float32, device=batch.traces.device)
+    _need_cuda(out, "out")
+    fn = lib().uwb_dmas_batch if beamformer == UWB_DMAS else lib().uwb_das_batch
+    bc, gc = batch.c(), grid_c(grid)
+    check(fn(ctypes.byref(bc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)), "image_batch")
+    return out
+
+
+def das_batch(batch, grid, window=11, out=None):
+    return image_batch(batch, grid, UWB_DAS, window, out)
+
+
+def dmas_batch(batch, grid, window=11, out=None):
+    return image_batch(batch, grid, UWB_DMAS, window, out)
+
+
+@dataclasses.dataclass
+class Peak:
+    index: int
+    value: float
+    value32: float
+    candidates: int
+
+
+def _peaks(buf: torch.Tensor, n: int):
+    raw = buf.cpu().numpy().tobytes()
+    sz = ctypes.sizeof(UwbPeak)
+    out = []
+    for i in range(n):
+        p = UwbPeak.from_buffer_copy(raw[i * sz:(i + 1) * sz])
+        out.append(Peak(int(p.index), float(p.value), float(p.value32), int(p.candidates)))
+    return out
+
+
+class Workspace:
+    """Grow-only device scratch buffer reused across calls."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != torch.device(device):
+            self.buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_ws = Workspace()
+
+
+def argmax_async(scan: DeviceScan, grid, img: torch.Tensor, beamformer: int, window: int = 11,
+                 out: torch.Tensor | None = None, workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Enqueue the FP64-decided argmax; returns the device buffer holding one uwb_peak."""
+    gc, sc = grid_c(grid), scan.c()
+    need = lib().uwb_argmax_workspace_bytes(ctypes.byref(gc), 1)
+    ws = workspace if workspace is not None else _ws.get(need, img.device)
+    if out is None:
+        out = torch.empty(ctypes.sizeof(UwbPeak), dtype=torch.uint8, device=img.device)
+    _need_cuda(img, "img")
+    check(lib().uwb_argmax(ctypes.byref(sc), ctypes.byref(gc), window, beamformer, img.data_ptr(), out.data_ptr(),
+                           ws.data_ptr(), ws.numel(), _stream(img.device)), "uwb_argmax")
+    return out
+
+
+def argmax(scan, grid, img, beamformer, window=11) -> Peak:
+    return _peaks(argmax_async(scan, grid, img, beamformer, window), 1)[0]
+
+
+def argmax_batch_async(batch: DeviceBatch, grid, img: torch.Tensor, beamformer: int, window: int = 11,
+                       out=None, workspace=None, bc=None) -> torch.Tensor:
+    gc = grid_c(grid)
+    bc = bc if bc is not None else batch.c()
+    need = lib().uwb_argmax_workspace_bytes(ctypes.byref(gc), batch.n_scans)
+    ws = workspace if workspace is not None else _ws.get(need, img.device)
+    if out is None:
+        out = torch.empty(ctypes.sizeof(UwbPeak) * batch.n_scans, dtype=torch.uint8, device=img.device)
+    _need_cuda(img, "img")
+    check(lib().uwb_argmax_batch(ctypes.byref(bc), ctypes.byref(gc), window, beamformer, img.data_ptr(),
+                                 out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(img.device)), "uwb_argmax_batch")
+    return out
+
+
+def argmax_batch(batch, grid, img, beamformer, window=11):
+    return _peaks(argmax_batch_async(batch, grid, img, beamformer, window), batch.n_scans)
+
+
+def auto_decimation(min_tumour: float, pitch: float) -> int:
+    r = lib().uwb_auto_decimation(float(min_tumour), float(pitch))
+    check(min(r, 0), "uwb_auto_decimation")
+    return r
+
+
+# ----------------------------------------------------------------------------------
+# segment walk
+# ----------------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SegmentTree:
+    beamformer: int = 0
+    walk: str = "per_level"
+    coarse: int = 8
+    decimation: int = 0
+    min_tumour: float = 0.01
+    max_depth: int = 0
+    metric: str = "max"
+    term: str = "fixed"
+    frame_level: float = 0.0
+    frame_final: float = 0.25
+
+    def c(self) -> UwbSegmentTree:
+        return UwbSegmentTree(int(self.beamformer), WALKS[self.walk], int(self.coarse), int(self.decimation),
+                              float(self.min_tumour), int(self.max_depth), METRICS[self.metric], TERMS[self.term],
+                              float(self.frame_level), float(self.frame_final))
+
+
+@dataclasses.dataclass
+class SegmentResult:
+    n_levels: int
+    term_level: int
+    decimation: int
+    n_samples_level0: int
+    child: list
+    boxes: list
+    scores: list
+    wb: list
+    roi: tuple
+    argmax: int
+    peak: float
+    voxels_evaluated: int
+    roi_image: np.ndarray | None = None
+
+
+def _results(buf: torch.Tensor, n: int, n_child: int):
+    raw = buf.cpu().numpy().tobytes()
+    sz = ctypes.sizeof(UwbSegmentResult)
+    out = []
+    for i in range(n):
+        r = UwbSegmentResult.from_buffer_copy(raw[i * sz:(i + 1) * sz])
+        made = int(r.term_level)
+        out.append(SegmentResult(
+            int(r.n_levels), made, int(r.decimation), int(r.n_samples_level0),
+            [int(r.child[j]) for j in range(made)],
+            [tuple(int(x) for x in r.box[j]) for j in range(made + 1)],
+            [[float(r.score[j][c]) for c in range(n_child)] for j in range(made)],
+            [(float(r.wb[j][0]), float(r.wb[j][1])) for j in range(int(r.n_wb))],
+            tuple(int(x) for x in r.roi), int(r.argmax), float(r.peak), int(r.voxels_evaluated)))
+    return out
+
+
+def roi_capacity(grid, tree: SegmentTree) -> int:
+    gc, tc = grid_c(grid), tree.c()
+    cap = lib().uwb_segment_roi_capacity(ctypes.byref(gc), ctypes.byref(tc))
+    check(int(min(cap, 0)), "uwb_segment_roi_capacity")
+    return int(cap)
+
+
+def segment_refine_batch_async(batch: DeviceBatch, grid, tree: SegmentTree, window: int = 11, out=None,
+                               roi_img=None, workspace=None, bc=None):
+    gc, tc = grid_c(grid), tree.c()
+    bc = bc if bc is not None else batch.c()
+    dev = batch.traces.device
+    cap = roi_capacity(grid, tree)
+    need = lib().uwb_segment_workspace_bytes(ctypes.byref(gc), ctypes.byref(tc), batch.n_scans)
+    ws = workspace if workspace is not None else _ws.get(need, dev)
+    if out is None:
+        out = torch.empty(ctypes.sizeof(UwbSegmentResult) * batch.n_scans, dtype=torch.uint8, device=dev)
+    rp = 0
+    if roi_img is not None:
+        _need_cuda(roi_img, "roi_img")
+        if roi_img.numel() < cap * batch.n_scans:
+            raise ValueError("roi_img smaller than n_scans * roi capacity")
+        rp = roi_img.data_ptr()
+    check(lib().uwb_segment_refine_batch(ctypes.byref(bc), ctypes.byref(gc), window, ctypes.byref(tc),
+                                         out.data_ptr(), rp, cap, ws.data_ptr(), ws.numel(), _stream(dev)),
+          "uwb_segment_refine_batch")
+    return out, cap
+
+
+def segment_refine_batch(batch, grid, tree: SegmentTree, window=11, want_roi=False):
+    dev = batch.traces.device
+    roi = None
+    if want_roi:
+        roi = torch.empty(roi_capacity(grid, tree) * batch.n_scans, dtype=torch.float32, device=dev)
+    out, cap = segment_refine_batch_async(batch, grid, tree, window, roi_img=roi)
+    n_child = 4 if int(grid.dims[2]) == 1 else 8
+    res = _results(out, batch.n_scans, n_child)
+    if want_roi:
+        r = roi.cpu().numpy()
+        for i, x in enumerate(res):
+            b = x.roi
+            shape = (b[5] - b[4], b[3] - b[2], b[1] - b[0])
+            x.roi_image = r[i * cap:i * cap + int(np.prod(shape))].reshape(shape)
+    return res
+
+
+def segment_refine(scan: DeviceScan, grid, tree: SegmentTree, window=11, want_roi=False):
+    gc, tc, sc = grid_c(grid), tree.c(), scan.c()
+    dev = scan.traces.device
+    cap = roi_capacity(grid, tree)
+    need = lib().uwb_segment_workspace_bytes(ctypes.byref(gc), ctypes.byref(tc), 1)
+    ws = _ws.get(need, dev)
+    out = torch.empty(ctypes.sizeof(UwbSegmentResult), dtype=torch.uint8, device=dev)
+    roi = torch.empty(cap, dtype=torch.float32, device=dev) if want_roi else None
+    check(lib().uwb_segment_refine(ctypes.byref(sc), ctypes.byref(gc), window, ctypes.byref(tc), out.data_ptr(),
+                                   roi.data_ptr() if roi is not None else 0, cap, ws.data_ptr(), ws.numel(),
+                                   _stream(dev)), "uwb_segment_refine")
+    res = _results(out, 1, 4 if int(grid.dims[2]) == 1 else 8)[0]
+    if want_roi:
+        b = res.roi
+        shape = (b[5] - b[4], b[3] - b[2], b[1] - b[0])
+        res.roi_image = roi[:int(np.prod(shape))].cpu().numpy().reshape(shape)
+    return res

@@ -1,0 +1,239 @@
+// Host side of the C ABI declared in include/uwb.h: argument validation and
+// dispatch to the kernels.  Validation runs before any HIP call, so an invalid
+// request returns its status without touching the device.
+#include <cmath>
+#include <cstring>
+
+#include "uwb_internal.h"
+#include "walk_internal.h"
+
+namespace uwb {
+
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int check_window(int32_t w) {
+    if (w < 1 || (w % 2) == 0) return UWB_EINVAL;
+    if (w > UWB_MAX_WINDOW) return UWB_EUNSUPPORTED;
+    return UWB_OK;
+}
+
+int check_grid(const uwb_grid *g, GridView *out) {
+    if (!g) return UWB_EINVAL;
+    for (int d = 0; d < 3; ++d) {
+        if (!std::isfinite(g->origin[d]) || !finite_pos(g->pitch[d]) || g->dims[d] < 1) return UWB_EINVAL;
+        out->origin[d] = g->origin[d];
+        out->pitch[d] = g->pitch[d];
+        out->dims[d] = g->dims[d];
+    }
+    const double nvox = (double)g->dims[0] * g->dims[1] * g->dims[2];
+    if (nvox > 1.0e12) return UWB_EUNSUPPORTED;
+    return UWB_OK;
+}
+
+static int check_sizes(int32_t n_ant, int32_t n_samp) {
+    if (n_ant < 1 || n_samp < 2) return UWB_EINVAL;
+    if (n_samp > UWB_MAX_SAMPLES || n_ant > (1 << 20)) return UWB_EUNSUPPORTED;
+    return UWB_OK;
+}
+
+int scan_set(const uwb_scan *s, ScanSet *out) {
+    if (!s || !s->ant_pos || !s->traces) return UWB_EINVAL;
+    int st = check_sizes(s->n_ant, s->n_samp);
+    if (st) return st;
+    if (!finite_pos(s->dt) || !finite_pos(s->v) || !std::isfinite(s->t0)) return UWB_EINVAL;
+    out->ant_pos = s->ant_pos;
+    out->traces = s->traces;
+    out->params = nullptr;
+    out->pos_stride = 0;
+    out->tr_stride = 0;
+    out->n_ant = s->n_ant;
+    out->n_samp = s->n_samp;
+    out->dt = s->dt;
+    out->t0 = s->t0;
+    out->v = s->v;
+    return UWB_OK;
+}
+
+int batch_set(const uwb_scan_batch *b, ScanSet *out) {
+    if (!b || !b->ant_pos || !b->traces || !b->params) return UWB_EINVAL;
+    if (b->n_scans < 1) return UWB_EINVAL;
+    if (b->n_scans > 65535) return UWB_EUNSUPPORTED;
+    int st = check_sizes(b->n_ant, b->n_samp);
+    if (st) return st;
+    if (!finite_pos(b->v_min) || !finite_pos(b->dt_min)) return UWB_EINVAL;
+    out->ant_pos = b->ant_pos;
+    out->traces = b->traces;
+    out->params = b->params;
+    out->pos_stride = (int64_t)b->n_ant * 3;
+    out->tr_stride = (int64_t)b->n_ant * b->n_samp;
+    out->n_ant = b->n_ant;
+    out->n_samp = b->n_samp;
+    out->dt = b->dt_min;      // lower bounds: size the on-chip staging
+    out->t0 = 0.0;
+    out->v = b->v_min;
+    return UWB_OK;
+}
+
+static int image_common(int bf, const ScanSet &ss, int n, const uwb_grid *grid, int32_t window, float *img,
+                        void *stream) {
+    GridView g;
+    int st = check_grid(grid, &g);
+    if (st) return st;
+    if ((st = check_window(window))) return st;
+    if (!img) return UWB_EINVAL;
+    return launch_image32(bf, ss, n, g, window, img, (hipStream_t)stream);
+}
+
+static int argmax_common(const ScanSet &ss, int n, const uwb_grid *grid, int32_t window, int32_t bf,
+                         const float *img, uwb_peak *out, void *ws, size_t ws_bytes, void *stream) {
+    GridView g;
+    int st = check_grid(grid, &g);
+    if (st) return st;
+    if ((st = check_window(window))) return st;
+    if (bf != UWB_DAS && bf != UWB_DMAS) return UWB_EINVAL;
+    if (!img || !out || !ws) return UWB_EINVAL;
+    if (ws_bytes < argmax_ws_bytes(g, n)) return UWB_ERANGE;
+    return launch_argmax(bf, ss, n, g, window, img, out, ws, (hipStream_t)stream);
+}
+
+static int walk_common(const ScanSet &ss, int n, const uwb_grid *finest, int32_t window,
+                       const uwb_segment_tree *tree, uwb_segment_result *out, float *roi_img, int64_t roi_capacity,
+                       void *ws, size_t ws_bytes, void *stream) {
+    GridView g;
+    int st = check_grid(finest, &g);
+    if (st) return st;
+    if ((st = check_window(window))) return st;
+    WalkArgs a;
+    int64_t bound = 0;
+    size_t need = 0;
+    if ((st = plan_walk(g, tree, n, &a, &bound, &need))) return st;
+    if (!out || !ws) return UWB_EINVAL;
+    if (roi_img && roi_capacity < bound) return UWB_ERANGE;
+    if (!roi_img && roi_capacity != 0 && roi_capacity < bound) return UWB_ERANGE;
+    if (ws_bytes < need) return UWB_ERANGE;
+    a.ss = ss;
+    a.window = window;
+    a.out = out;
+    a.roi_img = roi_img;
+    a.roi_img_stride = roi_img ? roi_capacity : 0;
+    const uintptr_t p = ((uintptr_t)ws + 255) & ~(uintptr_t)255;
+    a.roi64 = reinterpret_cast<double *>(p);
+    a.dec64 = a.roi64 + (size_t)n * bound;
+    return launch_walk(a, n, (hipStream_t)stream);
+}
+
+}  // namespace uwb
+
+using namespace uwb;
+
+extern "C" {
+
+int uwb_das(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img, void *stream) {
+    ScanSet ss;
+    int st = scan_set(scan, &ss);
+    return st ? st : image_common(UWB_DAS, ss, 1, grid, window, img, stream);
+}
+
+int uwb_dmas(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img, void *stream) {
+    ScanSet ss;
+    int st = scan_set(scan, &ss);
+    return st ? st : image_common(UWB_DMAS, ss, 1, grid, window, img, stream);
+}
+
+int uwb_das_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img, void *stream) {
+    ScanSet ss;
+    int st = batch_set(scans, &ss);
+    return st ? st : image_common(UWB_DAS, ss, scans->n_scans, grid, window, img, stream);
+}
+
+int uwb_dmas_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img, void *stream) {
+    ScanSet ss;
+    int st = batch_set(scans, &ss);
+    return st ? st : image_common(UWB_DMAS, ss, scans->n_scans, grid, window, img, stream);
+}
+
+size_t uwb_argmax_workspace_bytes(const uwb_grid *grid, int32_t n_scans) {
+    GridView g;
+    if (check_grid(grid, &g) || n_scans < 1) return 0;
+    return argmax_ws_bytes(g, n_scans);
+}
+
+int uwb_argmax(const uwb_scan *scan, const uwb_grid *grid, int32_t window, int32_t beamformer, const float *img,
+               uwb_peak *out, void *workspace, size_t workspace_bytes, void *stream) {
+    ScanSet ss;
+    int st = scan_set(scan, &ss);
+    return st ? st : argmax_common(ss, 1, grid, window, beamformer, img, out, workspace, workspace_bytes, stream);
+}
+
+int uwb_argmax_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, int32_t beamformer,
+                     const float *img, uwb_peak *out, void *workspace, size_t workspace_bytes, void *stream) {
+    ScanSet ss;
+    int st = batch_set(scans, &ss);
+    return st ? st
+              : argmax_common(ss, scans->n_scans, grid, window, beamformer, img, out, workspace, workspace_bytes,
+                              stream);
+}
+
+int64_t uwb_segment_roi_capacity(const uwb_grid *finest, const uwb_segment_tree *tree) {
+    GridView g;
+    int st = check_grid(finest, &g);
+    if (st) return st;
+    WalkArgs a;
+    int64_t bound = 0;
+    size_t need = 0;
+    if ((st = plan_walk(g, tree, 1, &a, &bound, &need))) return st;
+    return bound;
+}
+
+size_t uwb_segment_workspace_bytes(const uwb_grid *finest, const uwb_segment_tree *tree, int32_t n_scans) {
+    GridView g;
+    if (check_grid(finest, &g)) return 0;
+    WalkArgs a;
+    int64_t bound = 0;
+    size_t need = 0;
+    if (plan_walk(g, tree, n_scans, &a, &bound, &need)) return 0;
+    return need;
+}
+
+int uwb_segment_refine(const uwb_scan *scan, const uwb_grid *finest, int32_t window, const uwb_segment_tree *tree,
+                       uwb_segment_result *out, float *roi_img, int64_t roi_capacity, void *workspace,
+                       size_t workspace_bytes, void *stream) {
+    ScanSet ss;
+    int st = scan_set(scan, &ss);
+    return st ? st
+              : walk_common(ss, 1, finest, window, tree, out, roi_img, roi_capacity, workspace, workspace_bytes,
+                            stream);
+}
+
+int uwb_segment_refine_batch(const uwb_scan_batch *scans, const uwb_grid *finest, int32_t window,
+                             const uwb_segment_tree *tree, uwb_segment_result *out, float *roi_img,
+                             int64_t roi_capacity, void *workspace, size_t workspace_bytes, void *stream) {
+    ScanSet ss;
+    int st = batch_set(scans, &ss);
+    return st ? st
+              : walk_common(ss, scans->n_scans, finest, window, tree, out, roi_img, roi_capacity, workspace,
+                            workspace_bytes, stream);
+}
+
+int uwb_auto_decimation(double min_tumour, double pitch) {
+    if (!finite_pos(min_tumour) || !finite_pos(pitch)) return UWB_EINVAL;
+    const double d = std::floor(min_tumour / (std::sqrt(2.0) * pitch));
+    if (!(d < 2147483647.0)) return UWB_EUNSUPPORTED;
+    return d < 1.0 ? 1 : (int)d;
+}
+
+const char *uwb_status_string(int status) {
+    switch (status) {
+        case UWB_OK: return "ok";
+        case UWB_EINVAL: return "invalid argument";
+        case UWB_ERANGE: return "output, workspace or depth out of range";
+        case UWB_ENOMEM: return "out of memory";
+        case UWB_EHIP: return "HIP runtime or launch error";
+        case UWB_EUNSUPPORTED: return "unsupported request";
+        default: return "unknown status";
+    }
+}
+
+const char *uwb_version(void) { return "uwb 0.1 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,549 @@
+// Coarse-to-fine segment walk (Section III): spatial decimation, ROI selection
+// with the mean / variance / Eq. (5) metrics and the Eq. (6)-(7) stop, sliding
+// frame, final full-resolution imaging of the ROI.
+//
+// Launch sequence per batch (stream-ordered, no host round trip):
+//   [paper walk]  k_lattice64   decimated image of the whole grid      -> ws
+//   k_walk        one workgroup per scan runs every level: (per-level walk:
+//                 re-image the box on a g^d lattice in LDS), parent / child
+//                 statistics by block reductions, W/B test, selection, frame
+//                 -> uwb_segment_result (boxes, children, scores, ROI)
+//   k_lattice64   ROI at full resolution, box read from the result    -> ws, roi_img
+//   k_roi_argmax  maximal-energy voxel of the ROI                      -> result
+// Every energy here is evaluated in FP64 (the walk is latency-bound: a few
+// thousand focal points per scan), so each decision is taken in the same
+// precision as a double-precision reference and does not hinge on FP32 rounding.
+#include <climits>
+#include <cmath>
+
+#include "uwb_internal.h"
+#include "walk_internal.h"
+
+namespace uwb {
+namespace {
+
+constexpr int kWaves = kBlock / 64;
+
+// ----------------------------------------------------------------------------
+// block reductions of small vectors (all threads get the result)
+// ----------------------------------------------------------------------------
+template <int N>
+__device__ void block_sum(double (&v)[N], double *red /* [kWaves][N] */) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) red[w * N + i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double s = red[i];
+        for (int k = 1; k < kWaves; ++k) s += red[k * N + i];
+        v[i] = s;
+    }
+}
+
+template <int N>
+__device__ void block_max(double (&v)[N], double *red) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = wave_max(v[i]);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) red[w * N + i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double s = red[i];
+        for (int k = 1; k < kWaves; ++k) s = fmax(s, red[k * N + i]);
+        v[i] = s;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// sample sets: a lattice of points with values, and membership in boxes
+// ----------------------------------------------------------------------------
+struct Lattice {
+    int x0[3];      // finest index of lattice point k = 0 along each axis
+    int step;       // D
+    int cnt[3];     // points per axis
+    __device__ int count() const { return cnt[0] * cnt[1] * cnt[2]; }
+    __device__ void coord(int p, int &x, int &y, int &z) const {
+        const int kx = p % cnt[0], ky = (p / cnt[0]) % cnt[1], kz = p / (cnt[0] * cnt[1]);
+        x = x0[0] + step * kx;
+        y = x0[1] + step * ky;
+        z = x0[2] + step * kz;
+    }
+};
+
+__device__ __forceinline__ bool in_box(const int *b, int x, int y, int z) {
+    return x >= b[0] && x < b[1] && y >= b[2] && y < b[3] && z >= b[4] && z < b[5];
+}
+
+// child c of box b, split at lo + floor(side/2) along the active axes (Morton bits)
+__device__ __forceinline__ void split_box(const int *b, int c, int nact, int *out) {
+    for (int i = 0; i < 6; ++i) out[i] = b[i];
+    for (int d = 0; d < nact; ++d) {
+        const int lo = b[2 * d], hi = b[2 * d + 1];
+        const int mid = lo + (hi - lo) / 2;
+        if ((c >> d) & 1) out[2 * d] = mid;
+        else out[2 * d + 1] = mid;
+    }
+}
+
+// widen each active side by floor(frac * side) on both ends, clipped to the grid
+__device__ __forceinline__ void expand_box(const int *b, double frac, int nact, const int *dims, int *out) {
+    for (int i = 0; i < 6; ++i) out[i] = b[i];
+    for (int d = 0; d < nact; ++d) {
+        const int lo = b[2 * d], hi = b[2 * d + 1];
+        const int e = (int)floor(frac * (double)(hi - lo));
+        out[2 * d] = max(0, lo - e);
+        out[2 * d + 1] = min(dims[d], hi + e);
+    }
+}
+
+// Decision metric of Section III on one child set (stats of raw and normalised values).
+__device__ double metric_value(int metric, double n, double mean, double m2, double mx, double nmean, double nvar,
+                               double pnvar) {
+    switch (metric) {
+        case UWB_MEAN: return mean;
+        case UWB_VAR: return m2 / n;
+        case UWB_MAX: return mx;
+        case UWB_MAX_OVER_MEAN: return mean != 0.0 ? mx / mean : 0.0;
+        case UWB_EQ5:
+        case UWB_EQ5_CLAMPED: {
+            double a = nvar > 0.0 ? (nvar - pnvar) / nvar : 0.0;
+            if (metric == UWB_EQ5_CLAMPED) a = fmin(fmax(a, 0.0), 1.0);
+            return (1.0 - a) * nmean + a * nvar;
+        }
+    }
+    return 0.0;
+}
+
+// ----------------------------------------------------------------------------
+// k_lattice64: FP64 energies on a lattice (decimated image, or the ROI read
+// from the walk result).  8 lanes cooperate on a point (antennas split 8 ways).
+// ----------------------------------------------------------------------------
+constexpr int kGroup = 8;
+constexpr int kPointsPerBlock = 4 * (kBlock / kGroup);   // 128
+
+__global__ __launch_bounds__(kBlock) void k_lattice64(const WalkArgs a, int from_result) {
+    const int scan = blockIdx.y;
+    Lattice L;
+    int64_t cap;
+    double *dst;
+    float *dst32 = nullptr;
+    if (from_result) {
+        const uwb_segment_result &r = a.out[scan];
+        for (int d = 0; d < 3; ++d) { L.x0[d] = r.roi[2 * d]; L.cnt[d] = r.roi[2 * d + 1] - r.roi[2 * d]; }
+        L.step = 1;
+        cap = a.roi_cap;
+        dst = a.roi64 + (int64_t)scan * a.roi_cap;
+        if (a.roi_img) dst32 = a.roi_img + (int64_t)scan * a.roi_img_stride;
+    } else {
+        for (int d = 0; d < 3; ++d) { L.x0[d] = a.dec_x0[d]; L.cnt[d] = a.dec_cnt[d]; }
+        L.step = a.decimation;
+        cap = a.dec_count;
+        dst = a.dec64 + (int64_t)scan * a.dec_count;
+    }
+    const int64_t n = min((int64_t)L.count(), cap);
+    const int64_t p0 = (int64_t)blockIdx.x * kPointsPerBlock;
+    if (p0 >= n) return;
+    const ScanConst sc = scan_const(a.ss, scan);
+    const int gl = threadIdx.x % kGroup;
+    for (int it = 0; it < kPointsPerBlock / (kBlock / kGroup); ++it) {
+        const int64_t p = p0 + it * (kBlock / kGroup) + threadIdx.x / kGroup;
+        const bool ok = p < n;
+        int x, y, z;
+        L.coord(ok ? (int)p : 0, x, y, z);
+        const double rx = a.g.origin[0] + x * a.g.pitch[0];
+        const double ry = a.g.origin[1] + y * a.g.pitch[1];
+        const double rz = a.g.origin[2] + z * a.g.pitch[2];
+        const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, gl, kGroup);
+        if (ok && gl == 0) {
+            dst[p] = e;
+            if (dst32) dst32[p] = (float)e;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// k_walk: the ROI-selection loop, one workgroup per scan.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_walk(const WalkArgs a) {
+    __shared__ double lv[kMaxCoarsePoints];      // per-level lattice values (per-level walk)
+    __shared__ double red[kWaves * 32];
+    __shared__ int sbox[6];
+    const int scan = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int nact = a.g.dims[2] > 1 ? 3 : 2;
+    const int nchild = 1 << nact;
+    const int dims[3] = {a.g.dims[0], a.g.dims[1], a.g.dims[2]};
+    uwb_segment_result &R = a.out[scan];
+    const ScanConst sc = scan_const(a.ss, scan);
+    const bool paper = a.walk == UWB_WALK_PAPER;
+
+    int box[6] = {0, dims[0], 0, dims[1], 0, dims[2]};
+    int boxes[UWB_MAX_LEVELS + 1][6];
+    for (int i = 0; i < 6; ++i) boxes[0][i] = box[i];
+    double prev_n = 0, prev_mean = 0, prev_m2 = 0, prevW = 0, prevB = 0;
+    int n_kept = 0, made = 0, n_wb = 0;
+    int64_t nvox = 0;
+
+    Lattice L;
+    const double *src;
+    if (paper) {
+        for (int d = 0; d < 3; ++d) { L.x0[d] = a.dec_x0[d]; L.cnt[d] = a.dec_cnt[d]; }
+        L.step = a.decimation;
+        src = a.dec64 + (int64_t)scan * a.dec_count;
+        nvox = L.count();
+    } else {
+        src = lv;
+    }
+
+    for (int lev = 0; lev <= a.depth; ++lev) {
+        if (lev == a.depth && a.term != UWB_TERM_WB) { n_kept = a.depth; break; }
+        int side = 0, step = 1;
+        if (!paper) {
+            // image the current box on its g^d lattice
+            side = dims[0] >> lev;
+            step = side / a.coarse;
+            for (int d = 0; d < 3; ++d) {
+                L.x0[d] = d < nact ? box[2 * d] + step / 2 : 0;
+                L.cnt[d] = d < nact ? a.coarse : 1;
+            }
+            L.step = step;
+            const int P = L.count();
+            int G = kBlock / P;                 // lanes per point
+            if (G > 64) G = 64;
+            if (G < 1) G = 1;
+            G = 1 << (31 - __clz(G));
+            const int per = kBlock / G;
+            for (int q0 = 0; q0 < P; q0 += per) {
+                const int p = q0 + tid / G;
+                const bool ok = p < P;
+                int x, y, z;
+                L.coord(ok ? p : 0, x, y, z);
+                const double rx = a.g.origin[0] + x * a.g.pitch[0];
+                const double ry = a.g.origin[1] + y * a.g.pitch[1];
+                const double rz = a.g.origin[2] + z * a.g.pitch[2];
+                const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, tid % G, G);
+                if (ok && tid % G == 0) lv[p] = e;
+            }
+            __syncthreads();
+            nvox += P;
+        }
+        const int P = L.count();
+
+        // children boxes and their scoring boxes
+        int cbox[8][6], sbx[8][6];
+        const int half = side / 2;
+        const int efr = paper ? 0 : (int)floor(a.frame_level * (double)half);
+        for (int c = 0; c < nchild; ++c) {
+            split_box(box, c, nact, cbox[c]);
+            for (int i = 0; i < 6; ++i) sbx[c][i] = cbox[c][i];
+            if (!paper) {
+                for (int d = 0; d < nact; ++d) {
+                    sbx[c][2 * d] = max(box[2 * d], cbox[c][2 * d] - efr);
+                    sbx[c][2 * d + 1] = min(box[2 * d + 1], cbox[c][2 * d + 1] + efr);
+                }
+            }
+        }
+
+        // pass 1: counts, sums, maxima of the parent (current box) and children
+        double s1[18], mx[9];
+        for (int i = 0; i < 18; ++i) s1[i] = 0.0;
+        for (int i = 0; i < 9; ++i) mx[i] = -INFINITY;
+        for (int p = tid; p < P; p += kBlock) {
+            int x, y, z;
+            L.coord(p, x, y, z);
+            if (!in_box(box, x, y, z)) continue;
+            const double v = src[p];
+            s1[0] += 1.0; s1[1] += v; mx[0] = fmax(mx[0], v);
+            for (int c = 0; c < nchild; ++c)
+                if (in_box(sbx[c], x, y, z)) { s1[2 + 2 * c] += 1.0; s1[3 + 2 * c] += v; mx[1 + c] = fmax(mx[1 + c], v); }
+        }
+        block_sum(s1, red);
+        block_max(mx, red);
+        const double pn = s1[0], pmean = s1[1] / pn, pmax = mx[0];
+        const double scale = pmax > 0.0 ? pmax : 1.0;    // Eq. (5) normalisation
+        double cmean[8];
+        for (int c = 0; c < nchild; ++c) cmean[c] = s1[3 + 2 * c] / s1[2 + 2 * c];
+        // pass 2: normalised sums (Eq. 5) and raw squared deviations
+        double s2[18];
+        for (int i = 0; i < 18; ++i) s2[i] = 0.0;
+        for (int p = tid; p < P; p += kBlock) {
+            int x, y, z;
+            L.coord(p, x, y, z);
+            if (!in_box(box, x, y, z)) continue;
+            const double v = src[p];
+            const double vn = pmax > 0.0 ? v / scale : v;
+            s2[0] += (v - pmean) * (v - pmean); s2[1] += vn;
+            for (int c = 0; c < nchild; ++c)
+                if (in_box(sbx[c], x, y, z)) {
+                    s2[2 + 2 * c] += (v - cmean[c]) * (v - cmean[c]);
+                    s2[3 + 2 * c] += vn;
+                }
+        }
+        block_sum(s2, red);
+        const double pm2 = s2[0];
+        const double pnmean = s2[1] / pn;
+        double cnmean[8];
+        for (int c = 0; c < nchild; ++c) cnmean[c] = s2[3 + 2 * c] / s1[2 + 2 * c];
+        // pass 3: normalised squared deviations (Eq. 5 variances)
+        double s3[9];
+        for (int i = 0; i < 9; ++i) s3[i] = 0.0;
+        if (a.metric == UWB_EQ5 || a.metric == UWB_EQ5_CLAMPED) {
+            for (int p = tid; p < P; p += kBlock) {
+                int x, y, z;
+                L.coord(p, x, y, z);
+                if (!in_box(box, x, y, z)) continue;
+                const double v = src[p];
+                const double vn = pmax > 0.0 ? v / scale : v;
+                s3[0] += (vn - pnmean) * (vn - pnmean);
+                for (int c = 0; c < nchild; ++c)
+                    if (in_box(sbx[c], x, y, z)) s3[1 + c] += (vn - cnmean[c]) * (vn - cnmean[c]);
+            }
+            block_sum(s3, red);
+        }
+
+        // Eq. (6)-(7) stop on the previous and the current box's samples
+        bool stop = false;
+        if (a.term == UWB_TERM_WB && lev >= 1) {
+            const double pooled = (prev_n * prev_mean + pn * pmean) / (prev_n + pn);
+            const double W = prev_m2 + pm2;
+            const double B = prev_n * (prev_mean - pooled) * (prev_mean - pooled) + pn * (pmean - pooled) * (pmean - pooled);
+            if (tid == 0) { R.wb[n_wb][0] = W; R.wb[n_wb][1] = B; }
+            ++n_wb;
+            if (lev >= 2 && (B <= prevB || W >= prevW)) { n_kept = lev - 1; stop = true; }
+            prevW = W;
+            prevB = B;
+        }
+        if (stop) break;
+        prev_n = pn;
+        prev_mean = pmean;
+        prev_m2 = pm2;
+        if (lev == a.depth) { n_kept = a.depth; break; }
+        if (paper) {
+            double cmin = INFINITY;
+            for (int c = 0; c < nchild; ++c) cmin = fmin(cmin, s1[2 + 2 * c]);
+            if (cmin < kMinChildSamples) { n_kept = lev; break; }
+        }
+        // score the children and select (lowest index within the tie band)
+        double sc8[8];
+        double best = -INFINITY;
+        for (int c = 0; c < nchild; ++c) {
+            const double n = s1[2 + 2 * c];
+            const double nvar = s3[1 + c] / n;
+            sc8[c] = metric_value(a.metric, n, cmean[c], s2[2 + 2 * c], mx[1 + c], cnmean[c], nvar, s3[0] / pn);
+            best = fmax(best, sc8[c]);
+        }
+        const double thr = best - kTieRel * fabs(best);
+        int sel = 0;
+        for (int c = nchild - 1; c >= 0; --c)
+            if (sc8[c] >= thr) sel = c;
+        if (tid == 0) {
+            R.child[made] = sel;
+            for (int c = 0; c < 8; ++c) R.score[made][c] = c < nchild ? sc8[c] : 0.0;
+        }
+        ++made;
+        if (paper) expand_box(cbox[sel], a.frame_level, nact, dims, box);
+        else for (int i = 0; i < 6; ++i) box[i] = cbox[sel][i];
+        for (int i = 0; i < 6; ++i) boxes[lev + 1][i] = box[i];
+        __syncthreads();   // lv is rewritten by the next level
+    }
+    int roi[6];
+    expand_box(boxes[n_kept], a.frame_final, nact, dims, roi);
+    if (tid == 0) {
+        R.n_levels = n_kept;
+        R.term_level = made;
+        R.decimation = paper ? a.decimation : 0;
+        R.n_samples_level0 = paper ? a.dec_count : (int)(nact == 3 ? a.coarse * a.coarse * a.coarse : a.coarse * a.coarse);
+        R.n_wb = n_wb;
+        for (int l = 0; l <= made; ++l)
+            for (int i = 0; i < 6; ++i) R.box[l][i] = boxes[l][i];
+        for (int i = 0; i < 6; ++i) R.roi[i] = roi[i];
+        const int64_t rv = (int64_t)(roi[1] - roi[0]) * (roi[3] - roi[2]) * (roi[5] - roi[4]);
+        R.voxels_evaluated = nvox + rv;
+        R.argmax = -1;
+        R.peak = 0.0;
+    }
+}
+
+// Maximal-energy voxel of the ROI (rule: lowest finest-grid index within the 1e-12 band).
+__global__ __launch_bounds__(kBlock) void k_roi_argmax(const WalkArgs a) {
+    __shared__ double red[kWaves];
+    __shared__ long long redi[kWaves];
+    const int scan = blockIdx.x;
+    uwb_segment_result &R = a.out[scan];
+    const int rx0 = R.roi[0], ry0 = R.roi[2], rz0 = R.roi[4];
+    const int rnx = R.roi[1] - R.roi[0], rny = R.roi[3] - R.roi[2], rnz = R.roi[5] - R.roi[4];
+    const int64_t n = min((int64_t)rnx * rny * rnz, a.roi_cap);
+    const double *v = a.roi64 + (int64_t)scan * a.roi_cap;
+    double m = -INFINITY;
+    for (int64_t p = threadIdx.x; p < n; p += kBlock) m = fmax(m, v[p]);
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    double mm = red[0];
+    for (int i = 1; i < kWaves; ++i) mm = fmax(mm, red[i]);
+    const double thr = mm - kTieRel * fabs(mm);
+    long long best = LLONG_MAX;
+    for (int64_t p = threadIdx.x; p < n; p += kBlock) {
+        if (v[p] >= thr) {
+            const int64_t kx = p % rnx, ky = (p / rnx) % rny, kz = p / ((int64_t)rnx * rny);
+            const long long lin = (rx0 + kx) + (int64_t)a.g.dims[0] * ((ry0 + ky) + (int64_t)a.g.dims[1] * (rz0 + kz));
+            best = lin < best ? lin : best;
+        }
+    }
+    best = wave_min_ll(best);
+    if ((threadIdx.x & 63) == 0) redi[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long b = redi[0];
+        for (int i = 1; i < kWaves; ++i) b = redi[i] < b ? redi[i] : b;
+        R.argmax = b == LLONG_MAX ? -1 : b;
+        // value at the winner
+        double pv = __builtin_nan("");
+        if (b != LLONG_MAX) {
+            const int64_t nx = a.g.dims[0], ny = a.g.dims[1];
+            const int64_t ix = b % nx - rx0, iy = (b / nx) % ny - ry0, iz = b / (nx * ny) - rz0;
+            pv = v[(iz * rny + iy) * rnx + ix];
+        }
+        R.peak = pv;
+    }
+}
+
+}  // namespace
+
+static int64_t lattice_points(int n, int step) {   // points D*k + floor(D/2) < n
+    const int first = step / 2;
+    return first < n ? (int64_t)(n - 1 - first) / step + 1 : 0;
+}
+
+static int64_t lattice_in(int lo, int hi, int step) {  // lattice coordinates inside [lo, hi)
+    int64_t c = 0;
+    for (int x = lo; x < hi; ++x) c += (x % step) == step / 2;
+    return c;
+}
+
+int plan_walk(const GridView &g, const uwb_segment_tree *t, int n_scans, WalkArgs *a, int64_t *roi_bound,
+              size_t *ws_bytes) {
+    if (!t) return UWB_EINVAL;
+    if (t->beamformer != UWB_DAS && t->beamformer != UWB_DMAS) return UWB_EINVAL;
+    if (t->walk != UWB_WALK_PER_LEVEL && t->walk != UWB_WALK_PAPER) return UWB_EINVAL;
+    if (t->metric < UWB_MEAN || t->metric > UWB_EQ5_CLAMPED) return UWB_EINVAL;
+    if (t->term != UWB_TERM_FIXED_DEPTH && t->term != UWB_TERM_WB) return UWB_EINVAL;
+    if (!std::isfinite(t->frame_level) || t->frame_level < 0 || !std::isfinite(t->frame_final) || t->frame_final < 0)
+        return UWB_EINVAL;
+    if (t->max_depth < 0) return UWB_EINVAL;
+    if (t->max_depth > UWB_MAX_LEVELS) return UWB_ERANGE;
+    if (n_scans < 1) return UWB_EINVAL;
+    const int nact = g.dims[2] > 1 ? 3 : 2;
+    a->g = g;
+    a->bf = t->beamformer;
+    a->walk = t->walk;
+    a->metric = t->metric;
+    a->term = t->term;
+    a->frame_level = t->frame_level;
+    a->frame_final = t->frame_final;
+    a->coarse = t->coarse;
+    a->decimation = 0;
+    a->dec_count = 0;
+    for (int d = 0; d < 3; ++d) { a->dec_x0[d] = 0; a->dec_cnt[d] = 1; }
+    int64_t bound = 0;
+    if (t->walk == UWB_WALK_PER_LEVEL) {
+        const int n = g.dims[0], gc = t->coarse;
+        if (g.dims[1] != n || (nact == 3 && g.dims[2] != n)) return UWB_EINVAL;
+        if (gc < 2 || gc % 2 || gc > 64) return UWB_EINVAL;
+        int64_t pts = 1;
+        for (int d = 0; d < nact; ++d) pts *= gc;
+        if (pts > kMaxCoarsePoints) return UWB_EUNSUPPORTED;
+        if (n % gc) return UWB_EINVAL;
+        const int q = n / gc;
+        if (q & (q - 1)) return UWB_EINVAL;
+        int top = 0;
+        while ((1 << top) < q) ++top;
+        int depth = t->max_depth == 0 ? top : (t->max_depth < top ? t->max_depth : top);
+        if (depth > UWB_MAX_LEVELS) return UWB_ERANGE;
+        a->depth = depth;
+        const int kept_min = t->term == UWB_TERM_WB ? (depth < 1 ? depth : 1) : depth;
+        const int s = n >> kept_min;
+        int64_t side = s + 2 * (int64_t)std::floor(t->frame_final * (double)s);
+        if (side > n) side = n;
+        bound = 1;
+        for (int d = 0; d < nact; ++d) bound *= side;
+    } else {
+        int dec = t->decimation;
+        if (dec < 0) return UWB_EINVAL;
+        if (dec == 0) {
+            if (!std::isfinite(t->min_tumour) || t->min_tumour <= 0) return UWB_EINVAL;
+            const double dd = std::floor(t->min_tumour / (std::sqrt(2.0) * g.pitch[0]));
+            if (!(dd < 2147483647.0)) return UWB_EUNSUPPORTED;
+            dec = dd < 1.0 ? 1 : (int)dd;
+        }
+        for (int d = 0; d < nact; ++d)
+            if (dec > g.dims[d]) return UWB_EINVAL;
+        a->decimation = dec;
+        int64_t cnt = 1;
+        for (int d = 0; d < nact; ++d) {
+            a->dec_x0[d] = dec / 2;
+            a->dec_cnt[d] = (int)lattice_points(g.dims[d], dec);
+            cnt *= a->dec_cnt[d];
+        }
+        a->dec_count = cnt;
+        const int depth = t->max_depth == 0 ? UWB_MAX_LEVELS : t->max_depth;
+        a->depth = depth;
+        // can the walk stop before its first split?  (data-independent: child sample counts)
+        int64_t cmin = INT64_MAX;
+        for (int c = 0; c < (1 << nact); ++c) {
+            int64_t k = 1;
+            for (int d = 0; d < nact; ++d) {
+                const int mid = g.dims[d] / 2;
+                k *= ((c >> d) & 1) ? lattice_in(mid, g.dims[d], dec) : lattice_in(0, mid, dec);
+            }
+            cmin = k < cmin ? k : cmin;
+        }
+        const int lmin = (depth >= 1 && cmin >= (int64_t)kMinChildSamples) ? 1 : 0;
+        // largest box side per axis at each level, then the largest ROI over reachable levels
+        int64_t side[3] = {g.dims[0], g.dims[1], g.dims[2]};
+        for (int l = 0; l <= depth; ++l) {
+            if (l >= lmin) {
+                int64_t v = 1;
+                for (int d = 0; d < nact; ++d) {
+                    int64_t r = side[d] + 2 * (int64_t)std::floor(t->frame_final * (double)side[d]);
+                    v *= r < g.dims[d] ? r : g.dims[d];
+                }
+                bound = v > bound ? v : bound;
+            }
+            for (int d = 0; d < nact; ++d) {
+                const int64_t c = (side[d] + 1) / 2;
+                int64_t s2 = c + 2 * (int64_t)std::floor(t->frame_level * (double)c);
+                side[d] = s2 < g.dims[d] ? s2 : g.dims[d];
+            }
+        }
+    }
+    *roi_bound = bound;
+    a->roi_cap = bound;
+    *ws_bytes = 256 + (size_t)n_scans * 8 * (size_t)(bound + a->dec_count) + 256;
+    return UWB_OK;
+}
+
+int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st) {
+    if (a.walk == UWB_WALK_PAPER) {
+        const unsigned nb = (unsigned)((a.dec_count + kPointsPerBlock - 1) / kPointsPerBlock);
+        hipLaunchKernelGGL(k_lattice64, dim3(nb, n_scans), dim3(kBlock), 0, st, a, 0);
+    }
+    hipLaunchKernelGGL(k_walk, dim3(n_scans), dim3(kBlock), 0, st, a);
+    const unsigned nr = (unsigned)((a.roi_cap + kPointsPerBlock - 1) / kPointsPerBlock);
+    hipLaunchKernelGGL(k_lattice64, dim3(nr, n_scans), dim3(kBlock), 0, st, a, 1);
+    hipLaunchKernelGGL(k_roi_argmax, dim3(n_scans), dim3(kBlock), 0, st, a);
+    return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
+}
+
+}  // namespace uwb

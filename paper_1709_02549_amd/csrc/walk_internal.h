@@ -1,0 +1,38 @@
+// Internal arguments of the segment-walk kernels (not part of the public ABI).
+#pragma once
+
+#include "uwb_internal.h"
+
+namespace uwb {
+
+constexpr int kMaxCoarsePoints = 4096;   // g^d lattice values held in LDS per level
+constexpr double kMinChildSamples = 4;   // paper walk: stop when a child holds fewer samples
+
+struct WalkArgs {
+    ScanSet ss;
+    GridView g;
+    int window, bf;
+    int walk, coarse, metric, term, depth;
+    double frame_level, frame_final;
+    // paper walk: decimated lattice (D, first point, points per axis)
+    int decimation;
+    int dec_x0[3], dec_cnt[3];
+    int64_t dec_count;
+    double *dec64;             // [n_scans][dec_count]
+    // ROI
+    int64_t roi_cap;           // ROI bound: stride of roi64
+    double *roi64;             // [n_scans][roi_cap]
+    float *roi_img;            // optional, scan s at s * roi_img_stride
+    int64_t roi_img_stride;
+    uwb_segment_result *out;   // [n_scans]
+};
+
+int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st);
+
+// Host planning of a walk: validates the tree against the grid and fills the
+// mode fields of WalkArgs (depth, decimated lattice) plus the ROI bound and the
+// workspace size for n_scans.
+int plan_walk(const GridView &g, const uwb_segment_tree *t, int n_scans, WalkArgs *a, int64_t *roi_bound,
+              size_t *ws_bytes);
+
+}  // namespace uwb

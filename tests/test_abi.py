@@ -1,0 +1,222 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared entry
+point, validates its arguments before touching the device, and its pure host
+functions (automatic decimation, sizes) give the documented values."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "uwb.h")
+FAKE = 0x1000    # a non-null pointer value: never dereferenced because validation fails first
+
+
+def _abi():
+    from paper_1709_02549_amd import _abi as a
+    return a
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(uwb_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _abi().lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    for n in names:
+        assert n in _abi().PROTOTYPES, f"binding has no prototype for {n}"
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors agree with the C compiler's sizeof / offsetof for every struct of uwb.h."""
+    import subprocess
+    a = _abi()
+    structs = {"uwb_scan": a.UwbScan, "uwb_scan_batch": a.UwbScanBatch, "uwb_grid": a.UwbGrid,
+               "uwb_peak": a.UwbPeak, "uwb_segment_tree": a.UwbSegmentTree, "uwb_segment_result": a.UwbSegmentResult}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def _scan(**kw):
+    a = _abi()
+    d = dict(n_ant=4, n_samp=64, ant_pos=FAKE, traces=FAKE, dt=2e-11, t0=0.0, v=1e8)
+    d.update(kw)
+    return a.UwbScan(**d)
+
+
+def _grid(dims=(8, 8, 1), pitch=(1e-3, 1e-3, 1e-3), origin=(0.0, 0.0, 0.0)):
+    a = _abi()
+    return a.UwbGrid((ctypes.c_double * 3)(*origin), (ctypes.c_double * 3)(*pitch), (ctypes.c_int32 * 3)(*dims))
+
+
+@pytest.mark.parametrize("fn", ["uwb_das", "uwb_dmas"])
+def test_image_argument_errors(fn):
+    a = _abi()
+    f = getattr(a.lib(), fn)
+    g = _grid()
+    E = a.UWB_EINVAL
+    assert f(None, ctypes.byref(g), 11, FAKE, None) == E
+    assert f(ctypes.byref(_scan()), None, 11, FAKE, None) == E
+    assert f(ctypes.byref(_scan()), ctypes.byref(g), 11, None, None) == E
+    assert f(ctypes.byref(_scan(ant_pos=None)), ctypes.byref(g), 11, FAKE, None) == E
+    assert f(ctypes.byref(_scan(traces=None)), ctypes.byref(g), 11, FAKE, None) == E
+    assert f(ctypes.byref(_scan(n_ant=0)), ctypes.byref(g), 11, FAKE, None) == E
+    assert f(ctypes.byref(_scan(n_samp=1)), ctypes.byref(g), 11, FAKE, None) == E
+    assert f(ctypes.byref(_scan(n_samp=70000)), ctypes.byref(g), 11, FAKE, None) == a.UWB_EUNSUPPORTED
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        assert f(ctypes.byref(_scan(dt=bad)), ctypes.byref(g), 11, FAKE, None) == E
+        assert f(ctypes.byref(_scan(v=bad)), ctypes.byref(g), 11, FAKE, None) == E
+    assert f(ctypes.byref(_scan(t0=float("nan"))), ctypes.byref(g), 11, FAKE, None) == E
+    for w in (0, 2, 10, -1):
+        assert f(ctypes.byref(_scan()), ctypes.byref(g), w, FAKE, None) == E
+    assert f(ctypes.byref(_scan()), ctypes.byref(g), 33, FAKE, None) == a.UWB_EUNSUPPORTED
+    for dims in [(0, 8, 1), (8, -1, 1), (8, 8, 0)]:
+        assert f(ctypes.byref(_scan()), ctypes.byref(_grid(dims=dims)), 11, FAKE, None) == E
+    for pitch in [(0.0, 1e-3, 1e-3), (1e-3, float("nan"), 1e-3), (1e-3, 1e-3, -1.0)]:
+        assert f(ctypes.byref(_scan()), ctypes.byref(_grid(pitch=pitch)), 11, FAKE, None) == E
+    assert f(ctypes.byref(_scan()), ctypes.byref(_grid(origin=(float("inf"), 0, 0))), 11, FAKE, None) == E
+
+
+def test_batch_argument_errors():
+    a = _abi()
+    f = a.lib().uwb_das_batch
+    g = _grid()
+
+    def b(**kw):
+        d = dict(n_scans=2, n_ant=4, n_samp=64, ant_pos=FAKE, traces=FAKE, params=FAKE, v_min=1e8, dt_min=2e-11)
+        d.update(kw)
+        return a.UwbScanBatch(**d)
+
+    assert f(ctypes.byref(b(n_scans=0)), ctypes.byref(g), 11, FAKE, None) == a.UWB_EINVAL
+    assert f(ctypes.byref(b(params=None)), ctypes.byref(g), 11, FAKE, None) == a.UWB_EINVAL
+    assert f(ctypes.byref(b(v_min=0.0)), ctypes.byref(g), 11, FAKE, None) == a.UWB_EINVAL
+    assert f(ctypes.byref(b(n_scans=70000)), ctypes.byref(g), 11, FAKE, None) == a.UWB_EUNSUPPORTED
+
+
+def test_argmax_argument_errors():
+    a = _abi()
+    L = a.lib()
+    g = _grid()
+    need = L.uwb_argmax_workspace_bytes(ctypes.byref(g), 1)
+    assert need > 0
+    s = _scan()
+    assert L.uwb_argmax(ctypes.byref(s), ctypes.byref(g), 11, 2, FAKE, FAKE, FAKE, need, None) == a.UWB_EINVAL
+    assert L.uwb_argmax(ctypes.byref(s), ctypes.byref(g), 11, 0, None, FAKE, FAKE, need, None) == a.UWB_EINVAL
+    assert L.uwb_argmax(ctypes.byref(s), ctypes.byref(g), 11, 0, FAKE, FAKE, FAKE, need - 1, None) == a.UWB_ERANGE
+    assert L.uwb_argmax_workspace_bytes(None, 1) == 0
+
+
+def _tree(**kw):
+    a = _abi()
+    d = dict(beamformer=0, walk=0, coarse=8, decimation=0, min_tumour=0.01, max_depth=0, metric=3, term=0,
+             frame_level=0.0, frame_final=0.25)
+    d.update(kw)
+    return a.UwbSegmentTree(**d)
+
+
+def test_segment_sizes_and_errors():
+    a = _abi()
+    L = a.lib()
+    g512 = _grid(dims=(512, 512, 1), pitch=(0.1 / 512,) * 3)
+    t = _tree()
+    # per-level, fixed depth: last box side 8, widened by floor(0.25 * 8) = 2 on each end
+    assert L.uwb_segment_roi_capacity(ctypes.byref(g512), ctypes.byref(t)) == 12 * 12
+    # W/B can stop after the first split: box side 256 -> 256 + 2 * 64 = 384
+    assert L.uwb_segment_roi_capacity(ctypes.byref(g512), ctypes.byref(_tree(term=1))) == 384 * 384
+    g3 = _grid(dims=(256, 256, 256), pitch=(0.1 / 256,) * 3)
+    assert L.uwb_segment_roi_capacity(ctypes.byref(g3), ctypes.byref(t)) == 12 ** 3
+    E = a.UWB_EINVAL
+    assert L.uwb_segment_roi_capacity(ctypes.byref(_grid(dims=(100, 100, 1))), ctypes.byref(t)) == E   # not 8*2^L
+    assert L.uwb_segment_roi_capacity(ctypes.byref(_grid(dims=(512, 256, 1))), ctypes.byref(t)) == E   # not square
+    assert L.uwb_segment_roi_capacity(ctypes.byref(g512), ctypes.byref(_tree(coarse=7))) == E
+    assert L.uwb_segment_roi_capacity(ctypes.byref(g512), ctypes.byref(_tree(metric=6))) == E
+    assert L.uwb_segment_roi_capacity(ctypes.byref(g512), ctypes.byref(_tree(term=2))) == E
+    assert L.uwb_segment_roi_capacity(ctypes.byref(g512), ctypes.byref(_tree(frame_final=-0.1))) == E
+    assert L.uwb_segment_roi_capacity(ctypes.byref(g512), ctypes.byref(_tree(max_depth=17))) == a.UWB_ERANGE
+    assert L.uwb_segment_roi_capacity(ctypes.byref(g512), ctypes.byref(_tree(coarse=128))) == E
+    assert L.uwb_segment_roi_capacity(ctypes.byref(g3), ctypes.byref(_tree(coarse=32))) == a.UWB_EUNSUPPORTED
+    # paper walk: automatic D from min_tumour; manual D larger than the grid is invalid
+    gp = _grid(dims=(100, 100, 1), pitch=(1e-3,) * 3)
+    assert L.uwb_segment_roi_capacity(ctypes.byref(gp), ctypes.byref(_tree(walk=1))) > 0
+    assert L.uwb_segment_roi_capacity(ctypes.byref(gp), ctypes.byref(_tree(walk=1, decimation=101))) == E
+    assert L.uwb_segment_roi_capacity(ctypes.byref(gp), ctypes.byref(_tree(walk=1, min_tumour=0.0))) == E
+    ws = L.uwb_segment_workspace_bytes(ctypes.byref(g512), ctypes.byref(t), 4)
+    assert ws >= 4 * 8 * 144
+    s = _scan()
+    cap = 144
+    assert L.uwb_segment_refine(ctypes.byref(s), ctypes.byref(g512), 11, ctypes.byref(t), None, FAKE, cap, FAKE, ws,
+                                None) == E
+    assert L.uwb_segment_refine(ctypes.byref(s), ctypes.byref(g512), 11, ctypes.byref(t), FAKE, FAKE, cap - 1,
+                                FAKE, ws, None) == a.UWB_ERANGE
+    assert L.uwb_segment_refine(ctypes.byref(s), ctypes.byref(g512), 11, ctypes.byref(t), FAKE, FAKE, cap, FAKE, 8,
+                                None) == a.UWB_ERANGE
+    assert L.uwb_segment_refine(ctypes.byref(s), ctypes.byref(g512), 11, None, FAKE, FAKE, cap, FAKE, ws,
+                                None) == E
+
+
+def test_paper_walk_roi_bound_covers_oracle_walks():
+    """The ROI bound of the paper walk is never below what the oracle's walks end with."""
+    import numpy as np
+    import oracle
+    import synth
+    a = _abi()
+    for seed in range(3):
+        s = synth.c1_scan(seed, noiseless=True)
+        for fl in (0.0, 0.25, 0.6):
+            for term in ("fixed", "wb"):
+                t = _tree(walk=1, frame_level=fl, term=1 if term == "wb" else 0)
+                gc = _grid(dims=s.grid.dims, pitch=s.grid.pitch, origin=s.grid.origin)
+                cap = a.lib().uwb_segment_roi_capacity(ctypes.byref(gc), ctypes.byref(t))
+                r = oracle.walk(s, oracle.TreeParams(walk="paper", frame_level=fl, term=term, metric="max"))
+                roi = r.roi
+                assert (roi[1] - roi[0]) * (roi[3] - roi[2]) * (roi[5] - roi[4]) <= cap
+                assert np.all(np.array(roi) >= 0)
+
+
+def test_auto_decimation_matches_paper_example():
+    a = _abi()
+    with open(os.path.join(ROOT, "tests", "golden", "auto_decimation.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                dmin, pitch, want = line.split()
+                assert a.lib().uwb_auto_decimation(float(dmin), float(pitch)) == int(want)
+    assert a.lib().uwb_auto_decimation(0.0, 1e-3) == a.UWB_EINVAL
+    assert a.lib().uwb_auto_decimation(0.01, float("nan")) == a.UWB_EINVAL
+
+
+def test_status_strings():
+    a = _abi()
+    for st in (0, -1, -2, -3, -4, -5, -99):
+        assert isinstance(a.lib().uwb_status_string(st), bytes)
+    assert a.lib().uwb_version().startswith(b"uwb")
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The package never imports the oracle or the generator."""
+    pkg = os.path.join(ROOT, "paper_1709_02549_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, fn
+                assert "liboracle" not in txt, fn

@@ -1,0 +1,115 @@
+"""GPU parity of the segment walk (Section III) against the oracle: bit-exact child
+sequence, boxes, stop level, ROI and argmax; FP64 scores and W/B values."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+METRICS = ["mean", "var", "eq5", "max", "max_over_mean", "eq5_clamped"]
+
+
+def uwb():
+    import paper_1709_02549_amd as m
+    return m
+
+
+def _params(**kw):
+    return oracle.TreeParams(**kw), uwb().SegmentTree(**kw)
+
+
+def _compare(g, o, exact_scores=1e-9):
+    assert g.child == o.child
+    assert g.n_levels == o.n_levels and g.term_level == o.term_level
+    assert [tuple(b) for b in g.boxes] == [tuple(b) for b in o.boxes]
+    assert tuple(g.roi) == tuple(o.roi)
+    assert g.argmax == o.argmax
+    assert g.peak == pytest.approx(o.peak, rel=1e-9)
+    assert g.voxels_evaluated == o.voxels_evaluated
+    for a, b in zip(g.scores, o.scores):
+        np.testing.assert_allclose(a, b, rtol=exact_scores, atol=1e-300)
+    assert len(g.wb) == len(o.wb)
+    for a, b in zip(g.wb, o.wb):
+        np.testing.assert_allclose(a, b, rtol=1e-9)
+    if o.roi_image is not None and g.roi_image is not None:
+        np.testing.assert_allclose(g.roi_image, o.roi_image, rtol=1e-6, atol=1e-6 * o.roi_image.max())
+
+
+@pytest.mark.parametrize("metric", METRICS)
+@pytest.mark.parametrize("term", ["fixed", "wb"])
+@pytest.mark.parametrize("bf", [0, 1])
+def test_per_level_c1(metric, term, bf):
+    s = synth.c1_scan(7)
+    op, gp = _params(beamformer=bf, coarse=8, metric=metric, term=term, frame_level=0.25, frame_final=0.25)
+    o = oracle.walk(s, op)
+    g = uwb().segment_refine(uwb().DeviceScan.from_host(s), s.grid, gp, want_roi=True)
+    _compare(g, o)
+
+
+@pytest.mark.parametrize("metric", METRICS)
+@pytest.mark.parametrize("term", ["fixed", "wb"])
+@pytest.mark.parametrize("bf", [0, 1])
+def test_paper_walk_c1(metric, term, bf):
+    s = synth.c1_scan(8)
+    op, gp = _params(beamformer=bf, walk="paper", metric=metric, term=term, frame_level=0.25, frame_final=0.25,
+                     min_tumour=0.01)
+    o = oracle.walk(s, op)
+    g = uwb().segment_refine(uwb().DeviceScan.from_host(s), s.grid, gp, want_roi=True)
+    assert g.decimation == o.decimation
+    _compare(g, o)
+
+
+@pytest.mark.parametrize("bf", [0, 1])
+@pytest.mark.parametrize("metric", ["max", "mean"])
+def test_c2_full_size_batch(bf, metric):
+    """C2: 512 x 512, g = 8, 32 antennas, T = 2048; 8 scans in one batched launch."""
+    scans = [synth.c2_scan(k) for k in range(8)]
+    u = uwb()
+    b = u.DeviceBatch.from_host(scans)
+    op, gp = _params(beamformer=bf, coarse=8, metric=metric, frame_final=0.25)
+    res = u.segment_refine_batch(b, scans[0].grid, gp, want_roi=True)
+    for s, g in zip(scans, res):
+        _compare(g, oracle.walk(s, op))
+
+
+@pytest.mark.parametrize("metric", ["max", "eq5", "var"])
+def test_c2_paper_walk_manual_and_auto(metric):
+    s = synth.c2_scan(11)
+    for dec in (0, 20):
+        op, gp = _params(beamformer=1, walk="paper", decimation=dec, metric=metric, frame_level=0.25, term="wb")
+        o = oracle.walk(s, op)
+        g = uwb().segment_refine(uwb().DeviceScan.from_host(s), s.grid, gp)
+        _compare(g, o)
+
+
+@pytest.mark.parametrize("bf", [0, 1])
+def test_c3_octree(bf):
+    """3D octree walk on the C3 geometry (64 antennas, T = 4096) at 64^3 and at the full 256^3."""
+    for n, seed in [(64, 0), (256, 1)]:
+        s = synth.c3_scan(seed, n_grid=n)
+        op, gp = _params(beamformer=bf, coarse=8, metric="max", frame_final=0.25)
+        o = oracle.walk(s, op)
+        g = uwb().segment_refine(uwb().DeviceScan.from_host(s), s.grid, gp, want_roi=True)
+        _compare(g, o)
+
+
+def test_frame_level_and_depth_limits():
+    s = synth.c1_scan(9)
+    for kw in [dict(max_depth=2), dict(max_depth=1, term="wb"), dict(coarse=4, frame_level=0.5),
+               dict(coarse=16, frame_final=0.0), dict(coarse=2, metric="mean")]:
+        op, gp = _params(beamformer=0, **kw)
+        _compare(uwb().segment_refine(uwb().DeviceScan.from_host(s), s.grid, gp), oracle.walk(s, op))
+
+
+def test_walk_deterministic():
+    s = synth.c2_scan(2)
+    u = uwb()
+    ds = u.DeviceScan.from_host(s)
+    _, gp = _params(beamformer=1, coarse=8, metric="eq5", term="wb")
+    a = u.segment_refine(ds, s.grid, gp, want_roi=True)
+    b = u.segment_refine(ds, s.grid, gp, want_roi=True)
+    assert a.child == b.child and a.scores == b.scores and a.argmax == b.argmax
+    assert np.array_equal(a.roi_image, b.roi_image)
