@@ -119,6 +119,7 @@ static int walk_common(const ScanSet &ss, int n, const uwb_grid *finest, int32_t
     const uintptr_t p = ((uintptr_t)ws + 255) & ~(uintptr_t)255;
     a.roi64 = reinterpret_cast<double *>(p);
     a.dec64 = a.roi64 + (size_t)n * bound;
+    size_walk_lds(&a, ss.n_ant);
     return launch_walk(a, n, (hipStream_t)stream);
 }
 

@@ -77,6 +77,92 @@ __device__ __forceinline__ long long wave_min_ll(long long x) {
 }
 
 // ------------------------------------------------------------------------------
+// Staging of trace samples for the FP64 evaluations (walk, ROI, argmax guard).
+// For a box of focal points, every antenna's samples that any point of the box
+// can touch are copied once into LDS (zero outside the recorded trace); the
+// per-point loops then gather from LDS instead of issuing dependent HBM loads.
+// ------------------------------------------------------------------------------
+constexpr int kStageMaxAnt = 1024;
+
+struct Stage {
+    float *buf;      // staged samples, antenna i at buf[off[i] .. off[i] + len[i])
+    int *lo;         // first staged sample index of antenna i
+    int *off;
+    int *len;
+    int cap;         // floats available in buf
+};
+
+// Exclusive prefix sum of one int per thread over the workgroup; returns the total.
+__device__ __forceinline__ int block_exclusive_scan(int x, int *out, int *tmp /* [kBlock/64] */) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = x;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    __syncthreads();
+    if (lane == 63) tmp[w] = inc;
+    __syncthreads();
+    int base = 0, total = 0;
+    for (int k = 0; k < kBlock / 64; ++k) {
+        if (k < w) base += tmp[k];
+        total += tmp[k];
+    }
+    *out = base + inc - x;
+    return total;
+}
+
+// Stage the samples a box of focal points [blo, bhi] (inclusive finest indices) can
+// touch.  Returns false (uniformly) when they do not fit; the caller then reads HBM.
+__device__ bool stage_box(const Stage &st, int *tmp, const ScanConst &sc, int M, int T, int window,
+                          const GridView &g, const int *blo, const int *bhi) {
+    if (M > kStageMaxAnt) return false;
+    const int h = (window - 1) / 2;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < M; i += kBlock) {
+        double dn2 = 0.0, df2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double a = (double)sc.pos[3 * i + d];
+            const double l = g.origin[d] + blo[d] * g.pitch[d] - a;
+            const double u = g.origin[d] + bhi[d] * g.pitch[d] - a;
+            const double n = fmin(fmax(0.0, l), u);
+            const double f = fmax(fabs(l), fabs(u));
+            dn2 += n * n;
+            df2 += f * f;
+        }
+        const double tmin = sc.s * sqrt(dn2) - sc.t0s, tmax = sc.s * sqrt(df2) - sc.t0s;
+        double lo = fmin(fmax(floor(tmin) - h - 1, -(double)(window + 1)), (double)T);
+        double hi = fmin(fmax(floor(tmax) + h + 2, lo + window), (double)(T + window));
+        st.lo[i] = (int)lo;
+        st.len[i] = (int)(hi - lo) + 1;
+    }
+    __syncthreads();
+    // prefix sum of the lengths: thread t owns antennas [t*c, (t+1)*c)
+    const int c = (M + kBlock - 1) / kBlock;
+    int mine = 0;
+    for (int i = tid * c; i < min(M, (tid + 1) * c); ++i) mine += st.len[i];
+    int base;
+    const int total = block_exclusive_scan(mine, &base, tmp);
+    if (total > st.cap) return false;
+    for (int i = tid * c; i < min(M, (tid + 1) * c); ++i) {
+        st.off[i] = base;
+        base += st.len[i];
+    }
+    __syncthreads();
+    const int lane = tid & 63;
+    for (int i = tid >> 6; i < M; i += kBlock / 64) {
+        const float *tr = sc.tr + (int64_t)i * T;
+        const int l0 = st.lo[i], n = st.len[i], o = st.off[i];
+        for (int m = lane; m < n; m += 64) {
+            const int gi = l0 + m;
+            st.buf[o + m] = (gi >= 0 && gi < T) ? tr[gi] : 0.f;
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
+// ------------------------------------------------------------------------------
 // FP64 energy of one focal point, evaluated cooperatively by a group of G lanes
 // (G a power of two <= 64, lanes of one group contiguous in the wave).  Lane
 // `gl` of the group takes antennas gl, gl+G, ...  The window is processed in
@@ -84,6 +170,7 @@ __device__ __forceinline__ long long wave_min_ll(long long x) {
 // a fixed register budget.  Partial sums of the group are combined with
 //   (S, P) (+) (S', P') = (S + S', P + P' + S S'),
 // which is the exact decomposition of sum_{i<j} s_i s_j over two antenna sets.
+// Samples come from a Stage (LDS) when `st` is non-null, else from HBM.
 // Every lane of the group returns the energy.
 // ------------------------------------------------------------------------------
 constexpr int kChunk = 8;
@@ -94,7 +181,7 @@ __device__ __forceinline__ double trace64(const float *tr, int T, long long m) {
 
 template <int BF>
 __device__ double energy64_group(const ScanConst &sc, int M, int T, int window, double rx, double ry,
-                                 double rz, int gl, int G) {
+                                 double rz, int gl, int G, const Stage *st) {
     const int h = (window - 1) / 2;
     double energy = 0.0;
     for (int k0 = -h; k0 <= h; k0 += kChunk) {
@@ -109,20 +196,39 @@ __device__ double energy64_group(const ScanConst &sc, int M, int T, int window, 
             const double tau = sc.s * sqrt(dx * dx + dy * dy + dz * dz) - sc.t0s;
             const double fl = floor(tau);
             const double f = tau - fl;
-            // clamp keeps the index arithmetic finite for absurd inputs; such
-            // positions are far outside the trace, where samples are zero anyway
-            const double flc = fmin(fmax(fl, -1.0e9), 1.0e9);
-            const long long n = (long long)flc;
-            const float *tr = sc.tr + (int64_t)i * T;
+            if (st) {
+                // window [n-h, n+h+1] lies inside the staged span by construction;
+                // the clamp only guards non-finite inputs
+                const int l0 = st->lo[i], ln = st->len[i];
+                const double nc = fmin(fmax(fl, (double)(l0 + h)), (double)(l0 + ln - h - 2));
+                const float *p = st->buf + st->off[i] + ((int)nc - l0);
 #pragma unroll
-            for (int j = 0; j < kChunk; ++j) {
-                const int k = k0 + j;
-                if (k <= h) {
-                    const double y0 = trace64(tr, T, n + k);
-                    const double y1 = trace64(tr, T, n + k + 1);
-                    const double s = (1.0 - f) * y0 + f * y1;
-                    if (BF == UWB_DMAS) P[j] += s * S[j];
-                    S[j] += s;
+                for (int j = 0; j < kChunk; ++j) {
+                    const int k = k0 + j;
+                    if (k <= h) {
+                        const double y0 = (double)p[k];
+                        const double y1 = (double)p[k + 1];
+                        const double s = (1.0 - f) * y0 + f * y1;
+                        if (BF == UWB_DMAS) P[j] += s * S[j];
+                        S[j] += s;
+                    }
+                }
+            } else {
+                // clamp keeps the index arithmetic finite for absurd inputs; such
+                // positions are far outside the trace, where samples are zero anyway
+                const double flc = fmin(fmax(fl, -1.0e9), 1.0e9);
+                const long long n = (long long)flc;
+                const float *tr = sc.tr + (int64_t)i * T;
+#pragma unroll
+                for (int j = 0; j < kChunk; ++j) {
+                    const int k = k0 + j;
+                    if (k <= h) {
+                        const double y0 = trace64(tr, T, n + k);
+                        const double y1 = trace64(tr, T, n + k + 1);
+                        const double s = (1.0 - f) * y0 + f * y1;
+                        if (BF == UWB_DMAS) P[j] += s * S[j];
+                        S[j] += s;
+                    }
                 }
             }
         }
@@ -149,9 +255,10 @@ __device__ double energy64_group(const ScanConst &sc, int M, int T, int window, 
 }
 
 __device__ __forceinline__ double energy64_dispatch(int bf, const ScanConst &sc, int M, int T, int window,
-                                                    double rx, double ry, double rz, int gl, int G) {
-    return bf == UWB_DMAS ? energy64_group<UWB_DMAS>(sc, M, T, window, rx, ry, rz, gl, G)
-                          : energy64_group<UWB_DAS>(sc, M, T, window, rx, ry, rz, gl, G);
+                                                    double rx, double ry, double rz, int gl, int G,
+                                                    const Stage *st = nullptr) {
+    return bf == UWB_DMAS ? energy64_group<UWB_DMAS>(sc, M, T, window, rx, ry, rz, gl, G, st)
+                          : energy64_group<UWB_DAS>(sc, M, T, window, rx, ry, rz, gl, G, st);
 }
 
 }  // namespace uwb

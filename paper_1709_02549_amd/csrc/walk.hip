@@ -156,6 +156,30 @@ __global__ __launch_bounds__(kBlock) void k_lattice64(const WalkArgs a, int from
     if (p0 >= n) return;
     const ScanConst sc = scan_const(a.ss, scan);
     const int gl = threadIdx.x % kGroup;
+    // stage the samples of this workgroup's points (bounding box of points p0 .. p1)
+    extern __shared__ __align__(16) unsigned char dsm[];
+    __shared__ int tmp[kWaves];
+    Stage st;
+    st.lo = reinterpret_cast<int *>(dsm);
+    st.off = st.lo + a.stage_ant;
+    st.len = st.off + a.stage_ant;
+    st.buf = reinterpret_cast<float *>(st.len + a.stage_ant);
+    st.cap = a.lattice_stage_cap;
+    int blo[3], bhi[3];
+    {
+        const int p1 = (int)min(p0 + kPointsPerBlock - 1, n - 1);
+        int f[3], l[3];
+        L.coord((int)p0, f[0], f[1], f[2]);
+        L.coord(p1, l[0], l[1], l[2]);
+        const bool same_z = f[2] == l[2], same_row = same_z && f[1] == l[1];
+        blo[0] = same_row ? f[0] : L.x0[0];
+        bhi[0] = same_row ? l[0] : L.x0[0] + L.step * (L.cnt[0] - 1);
+        blo[1] = same_z ? f[1] : L.x0[1];
+        bhi[1] = same_z ? l[1] : L.x0[1] + L.step * (L.cnt[1] - 1);
+        blo[2] = f[2];
+        bhi[2] = l[2];
+    }
+    const bool staged = stage_box(st, tmp, sc, a.ss.n_ant, a.ss.n_samp, a.window, a.g, blo, bhi);
     for (int it = 0; it < kPointsPerBlock / (kBlock / kGroup); ++it) {
         const int64_t p = p0 + it * (kBlock / kGroup) + threadIdx.x / kGroup;
         const bool ok = p < n;
@@ -164,7 +188,8 @@ __global__ __launch_bounds__(kBlock) void k_lattice64(const WalkArgs a, int from
         const double rx = a.g.origin[0] + x * a.g.pitch[0];
         const double ry = a.g.origin[1] + y * a.g.pitch[1];
         const double rz = a.g.origin[2] + z * a.g.pitch[2];
-        const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, gl, kGroup);
+        const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, gl, kGroup,
+                                           staged ? &st : nullptr);
         if (ok && gl == 0) {
             dst[p] = e;
             if (dst32) dst32[p] = (float)e;
@@ -176,9 +201,16 @@ __global__ __launch_bounds__(kBlock) void k_lattice64(const WalkArgs a, int from
 // k_walk: the ROI-selection loop, one workgroup per scan.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_walk(const WalkArgs a) {
-    __shared__ double lv[kMaxCoarsePoints];      // per-level lattice values (per-level walk)
+    extern __shared__ __align__(16) unsigned char dsm[];
+    double *lv = reinterpret_cast<double *>(dsm);     // per-level lattice values (per-level walk)
     __shared__ double red[kWaves * 32];
-    __shared__ int sbox[6];
+    __shared__ int tmp[kWaves];
+    Stage st;
+    st.lo = reinterpret_cast<int *>(dsm + sizeof(double) * a.pmax);
+    st.off = st.lo + a.stage_ant;
+    st.len = st.off + a.stage_ant;
+    st.buf = reinterpret_cast<float *>(st.len + a.stage_ant);
+    st.cap = a.stage_cap;
     const int scan = blockIdx.x;
     const int tid = threadIdx.x;
     const int nact = a.g.dims[2] > 1 ? 3 : 2;
@@ -219,6 +251,9 @@ __global__ __launch_bounds__(kBlock) void k_walk(const WalkArgs a) {
             }
             L.step = step;
             const int P = L.count();
+            int blo[3], bhi[3];
+            for (int d = 0; d < 3; ++d) { blo[d] = L.x0[d]; bhi[d] = L.x0[d] + step * (L.cnt[d] - 1); }
+            const bool staged = stage_box(st, tmp, sc, a.ss.n_ant, a.ss.n_samp, a.window, a.g, blo, bhi);
             int G = kBlock / P;                 // lanes per point
             if (G > 64) G = 64;
             if (G < 1) G = 1;
@@ -232,7 +267,8 @@ __global__ __launch_bounds__(kBlock) void k_walk(const WalkArgs a) {
                 const double rx = a.g.origin[0] + x * a.g.pitch[0];
                 const double ry = a.g.origin[1] + y * a.g.pitch[1];
                 const double rz = a.g.origin[2] + z * a.g.pitch[2];
-                const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, tid % G, G);
+                const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, tid % G, G,
+                                                   staged ? &st : nullptr);
                 if (ok && tid % G == 0) lv[p] = e;
             }
             __syncthreads();
@@ -534,14 +570,28 @@ int plan_walk(const GridView &g, const uwb_segment_tree *t, int n_scans, WalkArg
     return UWB_OK;
 }
 
+// LDS sizes of the walk kernels for M antennas (stage tables for up to kStageMaxAnt).
+void size_walk_lds(WalkArgs *a, int n_ant) {
+    constexpr int kWalkLds = 60 * 1024, kLatticeLds = 40 * 1024;
+    a->pmax = a->walk == UWB_WALK_PER_LEVEL ? a->coarse * a->coarse * (a->g.dims[2] > 1 ? a->coarse : 1) : 0;
+    a->stage_ant = n_ant < kStageMaxAnt ? n_ant : kStageMaxAnt;
+    const int fixed = 8 * a->pmax + 12 * a->stage_ant;
+    a->stage_cap = (kWalkLds - fixed) / 4;
+    if (a->stage_cap < 0) a->stage_cap = 0;
+    a->lds_walk = (size_t)fixed + 4 * (size_t)a->stage_cap;
+    a->lattice_stage_cap = (kLatticeLds - 12 * a->stage_ant) / 4;
+    if (a->lattice_stage_cap < 0) a->lattice_stage_cap = 0;
+    a->lds_lattice = (size_t)12 * a->stage_ant + 4 * (size_t)a->lattice_stage_cap;
+}
+
 int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st) {
     if (a.walk == UWB_WALK_PAPER) {
         const unsigned nb = (unsigned)((a.dec_count + kPointsPerBlock - 1) / kPointsPerBlock);
-        hipLaunchKernelGGL(k_lattice64, dim3(nb, n_scans), dim3(kBlock), 0, st, a, 0);
+        hipLaunchKernelGGL(k_lattice64, dim3(nb, n_scans), dim3(kBlock), a.lds_lattice, st, a, 0);
     }
-    hipLaunchKernelGGL(k_walk, dim3(n_scans), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_walk, dim3(n_scans), dim3(kBlock), a.lds_walk, st, a);
     const unsigned nr = (unsigned)((a.roi_cap + kPointsPerBlock - 1) / kPointsPerBlock);
-    hipLaunchKernelGGL(k_lattice64, dim3(nr, n_scans), dim3(kBlock), 0, st, a, 1);
+    hipLaunchKernelGGL(k_lattice64, dim3(nr, n_scans), dim3(kBlock), a.lds_lattice, st, a, 1);
     hipLaunchKernelGGL(k_roi_argmax, dim3(n_scans), dim3(kBlock), 0, st, a);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }

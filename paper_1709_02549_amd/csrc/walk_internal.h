@@ -25,9 +25,14 @@ struct WalkArgs {
     float *roi_img;            // optional, scan s at s * roi_img_stride
     int64_t roi_img_stride;
     uwb_segment_result *out;   // [n_scans]
+    // dynamic LDS layout: [coarse values: pmax doubles][stage tables: 3 * stage_ant ints][stage: stage_cap floats]
+    int pmax, stage_ant, stage_cap;
+    size_t lds_walk, lds_lattice;
+    int lattice_stage_cap;
 };
 
 int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st);
+void size_walk_lds(WalkArgs *a, int n_ant);
 
 // Host planning of a walk: validates the tree against the grid and fills the
 // mode fields of WalkArgs (depth, decimated lattice) plus the ROI bound and the
