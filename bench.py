@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--coarse", type=int, default=16, help="walk lattice points per side (g)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="before timing, run one plain device copy of this many MiB (HBM counter reference)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only (--gpus 1); multi-GPU sharding is not part of this build",
@@ -111,6 +113,12 @@ def main():
             uwb.segment_refine_batch_async(batch, grid, trees[bf], W, out=out, workspace=ws, bc=bc)
         mark("walk", 1)
 
+    if args.copy_ref_mib > 0:
+        src = torch.ones(args.copy_ref_mib * 262144, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()

@@ -230,6 +230,51 @@ int uwb_segment_refine_batch(const uwb_scan_batch *scans, const uwb_grid *finest
                              void *stream);
 
 /*
+ * Batched serving of uneven scans: many scans, each with its own antenna
+ * count, trace length and grid, imaged (DAS or DMAS, as uwb_das / uwb_dmas)
+ * by one persistent launch that is captured once into a HIP graph.
+ *
+ * uwb_batch_plan_create copies per-scan descriptors and the (scan, tile) work
+ * list to device memory it owns and captures the graph.  The item array is
+ * host memory and is not kept; the scans' traces, positions and output
+ * images are device buffers that must stay valid while the plan is run.
+ * All scans of a plan are planar (nz == 1) or all volumetric.
+ * uwb_batch_run enqueues one replay on `stream`.
+ * uwb_batch_autotune times every candidate configuration on this batch
+ * (`reps` replays each, on `stream`, synchronising), keeps the fastest, and if
+ * the environment variable UWB_TUNE_CACHE names a file, records it there; a
+ * later plan of the same batch shape created with cfg == NULL reuses it.
+ * uwb_batch_timestamps synchronises `stream` and returns, per scan, the time
+ * from the start of the last replay to the moment its last tile finished
+ * (ns, device clock; -1 if not finished).
+ * uwb_batch_set_config / uwb_batch_autotune rebuild the plan's device state:
+ * no replay of the plan may be in flight.
+ */
+typedef struct {
+    uwb_scan scan;
+    uwb_grid grid;
+    float *img;             /* device [nz][ny][nx] fp32 */
+} uwb_batch_item;
+
+typedef struct {
+    int32_t vpl;            /* voxels per lane: 1, 2 or 4 (planar tile 16 x 16*vpl; volumetric uses 2) */
+    int32_t wgs_per_cu;     /* resident workgroups per compute unit, 1..32 */
+    int32_t lds_kb;         /* LDS staging budget per workgroup in KiB, 4..60 (sets the antenna chunk) */
+    int32_t order;          /* 0: scans by decreasing cost (tiles x antennas); 1: as given */
+} uwb_batch_config;
+
+typedef struct uwb_batch_plan uwb_batch_plan;
+
+int uwb_batch_plan_create(uwb_batch_plan **plan, const uwb_batch_item *items, int32_t n_scans,
+                          int32_t beamformer, int32_t window, const uwb_batch_config *cfg);
+int uwb_batch_run(uwb_batch_plan *plan, void *stream);
+int uwb_batch_autotune(uwb_batch_plan *plan, int32_t reps, void *stream, uwb_batch_config *best);
+int uwb_batch_get_config(const uwb_batch_plan *plan, uwb_batch_config *cfg);
+int uwb_batch_set_config(uwb_batch_plan *plan, const uwb_batch_config *cfg);
+int uwb_batch_timestamps(uwb_batch_plan *plan, int64_t *done_ns, void *stream);
+int uwb_batch_plan_destroy(uwb_batch_plan *plan);
+
+/*
  * Automatic spatial decimation factor (Section III; worked example in
  * Section IV): one focal point per square inscribed in the smallest tumour,
  * D = floor(min_tumour / (sqrt(2) * pitch)), at least 1.  Host-only, pure.

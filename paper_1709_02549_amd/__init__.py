@@ -14,10 +14,11 @@ import numpy as np
 import torch
 
 from . import _abi
-from ._abi import (METRICS, TERMS, UWB_DAS, UWB_DMAS, UWB_MAX_LEVELS, WALKS, UwbError,  # noqa: F401
-                   UwbGrid, UwbPeak, UwbScan, UwbScanBatch, UwbSegmentResult, UwbSegmentTree, check, lib)
+from ._abi import (METRICS, TERMS, UWB_DAS, UWB_DMAS, UWB_MAX_LEVELS, WALKS, UwbBatchConfig,  # noqa: F401
+                   UwbBatchItem, UwbError, UwbGrid, UwbPeak, UwbScan, UwbScanBatch, UwbSegmentResult,
+                   UwbSegmentTree, check, lib)
 
-__all__ = ["DeviceScan", "DeviceBatch", "das", "dmas", "image", "das_batch", "dmas_batch", "image_batch",
+__all__ = ["BatchPlan", "DeviceScan", "DeviceBatch", "das", "dmas", "image", "das_batch", "dmas_batch", "image_batch",
            "argmax", "argmax_batch", "segment_refine", "segment_refine_batch", "auto_decimation",
            "SegmentTree", "UwbError"]
 
@@ -327,3 +328,61 @@ def segment_refine(scan: DeviceScan, grid, tree: SegmentTree, window=11, want_ro
         shape = (b[5] - b[4], b[3] - b[2], b[1] - b[0])
         res.roi_image = roi[:int(np.prod(shape))].cpu().numpy().reshape(shape)
     return res
+
+
+# ----------------------------------------------------------------------------------
+# batched serving of uneven scans (persistent, graph-captured launch)
+# ----------------------------------------------------------------------------------
+
+class BatchPlan:
+    """One plan over many scans of uneven shape: items are (DeviceScan, grid, out image tensor)."""
+
+    def __init__(self, items, beamformer: int, window: int = 11, config: dict | None = None):
+        self._keep = list(items)
+        n = len(self._keep)
+        arr = (UwbBatchItem * n)()
+        for k, (sc, g, out) in enumerate(self._keep):
+            _need_cuda(out, "out")
+            arr[k] = UwbBatchItem(sc.c(), grid_c(g), out.data_ptr())
+        self.device = self._keep[0][2].device
+        self._h = ctypes.c_void_p()
+        cfg = None
+        if config is not None:
+            cfg = UwbBatchConfig(config["vpl"], config["wgs_per_cu"], config["lds_kb"], config["order"])
+        check(lib().uwb_batch_plan_create(ctypes.byref(self._h), arr, n, beamformer, window,
+                                          ctypes.byref(cfg) if cfg is not None else None), "uwb_batch_plan_create")
+        self.n = n
+
+    def run(self):
+        check(lib().uwb_batch_run(self._h, _stream(self.device)), "uwb_batch_run")
+
+    @property
+    def config(self) -> dict:
+        c = UwbBatchConfig()
+        check(lib().uwb_batch_get_config(self._h, ctypes.byref(c)), "uwb_batch_get_config")
+        return {"vpl": c.vpl, "wgs_per_cu": c.wgs_per_cu, "lds_kb": c.lds_kb, "order": c.order}
+
+    def set_config(self, config: dict):
+        c = UwbBatchConfig(config["vpl"], config["wgs_per_cu"], config["lds_kb"], config["order"])
+        check(lib().uwb_batch_set_config(self._h, ctypes.byref(c)), "uwb_batch_set_config")
+
+    def autotune(self, reps: int = 3) -> dict:
+        c = UwbBatchConfig()
+        check(lib().uwb_batch_autotune(self._h, reps, _stream(self.device), ctypes.byref(c)), "uwb_batch_autotune")
+        return {"vpl": c.vpl, "wgs_per_cu": c.wgs_per_cu, "lds_kb": c.lds_kb, "order": c.order}
+
+    def timestamps_ns(self) -> np.ndarray:
+        out = (ctypes.c_int64 * self.n)()
+        check(lib().uwb_batch_timestamps(self._h, out, _stream(self.device)), "uwb_batch_timestamps")
+        return np.frombuffer(out, dtype=np.int64).copy()
+
+    def close(self):
+        if self._h:
+            lib().uwb_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

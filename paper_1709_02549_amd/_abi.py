@@ -57,6 +57,14 @@ class UwbSegmentResult(ctypes.Structure):
                 ("voxels_evaluated", c_i64)]
 
 
+class UwbBatchItem(ctypes.Structure):
+    _fields_ = [("scan", UwbScan), ("grid", UwbGrid), ("img", c_vp)]
+
+
+class UwbBatchConfig(ctypes.Structure):
+    _fields_ = [("vpl", c_i32), ("wgs_per_cu", c_i32), ("lds_kb", c_i32), ("order", c_i32)]
+
+
 # name -> (restype, argtypes)
 PROTOTYPES = {
     "uwb_das": (c_i32, [ctypes.POINTER(UwbScan), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp]),
@@ -76,6 +84,14 @@ PROTOTYPES = {
     "uwb_segment_refine_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32,
                                          ctypes.POINTER(UwbSegmentTree), c_vp, c_vp, c_i64, c_vp, ctypes.c_size_t,
                                          c_vp]),
+    "uwb_batch_plan_create": (c_i32, [ctypes.POINTER(c_vp), ctypes.POINTER(UwbBatchItem), c_i32, c_i32, c_i32,
+                                      ctypes.POINTER(UwbBatchConfig)]),
+    "uwb_batch_run": (c_i32, [c_vp, c_vp]),
+    "uwb_batch_autotune": (c_i32, [c_vp, c_i32, c_vp, ctypes.POINTER(UwbBatchConfig)]),
+    "uwb_batch_get_config": (c_i32, [c_vp, ctypes.POINTER(UwbBatchConfig)]),
+    "uwb_batch_set_config": (c_i32, [c_vp, ctypes.POINTER(UwbBatchConfig)]),
+    "uwb_batch_timestamps": (c_i32, [c_vp, ctypes.POINTER(c_i64), c_vp]),
+    "uwb_batch_plan_destroy": (c_i32, [c_vp]),
     "uwb_auto_decimation": (c_i32, [c_f64, c_f64]),
     "uwb_status_string": (ctypes.c_char_p, [c_i32]),
     "uwb_version": (ctypes.c_char_p, []),

@@ -1,0 +1,508 @@
+// Batched serving of uneven scans: one persistent, graph-captured launch.
+//
+// A plan holds, in device memory, one descriptor per scan (its own antenna
+// count, trace length, grid and output) and a work list of (scan, tile) items,
+// scan-major, scans ordered by decreasing cost (longest-processing-time first)
+// or as given.  The persistent kernel keeps a fixed number of workgroups per CU
+// resident; each pulls the next item with one atomic, images that tile with the
+// same tile body as the single-scan kernel, and the workgroup that finishes a
+// scan's last tile stamps the scan's completion time (s_memrealtime, 100 MHz).
+// A reset kernel and the persistent kernel are captured once into a hipGraph;
+// uwb_batch_run replays it.  The tile shape (voxels per lane), the resident
+// workgroups per CU, the LDS staging budget (hence the antenna chunk) and the
+// item order are chosen by uwb_batch_autotune, which times every candidate on
+// the plan's own batch and may persist the winner in a cache file.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "image32.h"
+
+namespace uwb {
+
+struct BatchDesc {
+    const float *pos;
+    const float *tr;
+    float *img;
+    int M, T;
+    double s, t0s;
+    GridView g;
+    int tiles_x, tiles_y;
+    int rs, chunk;
+    int first_item;
+    int n_tiles;
+};
+
+struct BatchArgs {
+    const BatchDesc *descs;
+    const int *item_scan;
+    int n_items, n_scans;
+    int *counter;
+    int *remaining;
+    unsigned long long *t_done;
+    unsigned long long *t_start;
+};
+
+namespace {
+
+__global__ void k_batch_reset(BatchArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) { *a.counter = 0; *a.t_start = 0ull; }
+    for (int s = i; s < a.n_scans; s += gridDim.x * blockDim.x) {
+        a.remaining[s] = a.descs[s].n_tiles;
+        a.t_done[s] = 0ull;
+    }
+}
+
+template <int BF, int W, bool D3, int VPL>
+__global__ __launch_bounds__(kBlock) void k_batch32(const BatchArgs a) {
+    extern __shared__ __align__(16) float smem[];
+    __shared__ int s_item;
+    // Lane 0 is the only lane that touches the work counter.  Each iteration has a
+    // single lane-0 region (completion of the previous item, fetch of the next)
+    // between two barriers, and the exit test reads the item as a scalar: if the
+    // loop were entered through a lane-0-only block, or its exit were a per-lane
+    // value, the compiler may restructure it so that lanes 1..63 keep iterating on
+    // a stale item while lane 0, which would fetch the next one, waits at the exit.
+    if (threadIdx.x == 0) {
+        const unsigned long long t = __builtin_amdgcn_s_memrealtime();
+        const int it = atomicAdd(a.counter, 1);
+        if (it == 0) *a.t_start = t;
+        s_item = it;
+    }
+    __syncthreads();
+    int item = __builtin_amdgcn_readfirstlane(s_item);
+    while (item < a.n_items) {
+        const int scan = a.item_scan[item];
+        const BatchDesc &d = a.descs[scan];
+        int tx, ty, tz;
+        TileShape<D3, VPL>::get(tx, ty, tz);
+        const int tile = item - d.first_item;
+        TileJob j;
+        j.pos = d.pos;
+        j.tr = d.tr;
+        j.img = d.img;
+        j.M = d.M;
+        j.T = d.T;
+        j.s = d.s;
+        j.t0s = d.t0s;
+        j.g = d.g;
+        j.tx0 = (tile % d.tiles_x) * tx;
+        j.ty0 = ((tile / d.tiles_x) % d.tiles_y) * ty;
+        j.tz0 = (tile / (d.tiles_x * d.tiles_y)) * tz;
+        j.rs = d.rs;
+        j.chunk = d.chunk;
+        image_tile<BF, W, D3, VPL>(j, smem);
+        __syncthreads();   // every lane's image stores are issued before the scan counter moves
+        if (threadIdx.x == 0) {
+            __threadfence();
+            if (atomicSub(&a.remaining[scan], 1) == 1) {
+                __threadfence();
+                a.t_done[scan] = __builtin_amdgcn_s_memrealtime();
+            }
+            s_item = atomicAdd(a.counter, 1);
+        }
+        __syncthreads();
+        item = __builtin_amdgcn_readfirstlane(s_item);
+    }
+}
+
+template <int BF, int W>
+hipError_t launch_batch_w(bool d3, int vpl, unsigned grid, size_t lds, hipStream_t st, const BatchArgs &a) {
+    if (d3) {
+        hipLaunchKernelGGL((k_batch32<BF, W, true, 2>), dim3(grid), dim3(kBlock), lds, st, a);
+    } else if (vpl == 1) {
+        hipLaunchKernelGGL((k_batch32<BF, W, false, 1>), dim3(grid), dim3(kBlock), lds, st, a);
+    } else if (vpl == 4) {
+        hipLaunchKernelGGL((k_batch32<BF, W, false, 4>), dim3(grid), dim3(kBlock), lds, st, a);
+    } else {
+        hipLaunchKernelGGL((k_batch32<BF, W, false, 2>), dim3(grid), dim3(kBlock), lds, st, a);
+    }
+    return hipGetLastError();
+}
+
+template <int BF>
+hipError_t launch_batch_bf(int window, bool d3, int vpl, unsigned grid, size_t lds, hipStream_t st,
+                           const BatchArgs &a) {
+    switch (window) {
+#define UWB_W(w) case w: return launch_batch_w<BF, w>(d3, vpl, grid, lds, st, a);
+        UWB_WINDOWS(UWB_W)
+#undef UWB_W
+    }
+    return hipErrorInvalidValue;
+}
+
+struct HostItem {
+    uwb_scan scan;
+    GridView g;
+    float *img;
+};
+
+}  // namespace
+}  // namespace uwb
+
+using namespace uwb;
+
+struct uwb_batch_plan {
+    int bf, window, n;
+    bool d3;
+    std::vector<HostItem> items;
+    uwb_batch_config cfg;
+    // device
+    BatchDesc *descs = nullptr;
+    int *item_scan = nullptr;
+    int *counters = nullptr;            // [0] work counter, [1..n] remaining tiles
+    unsigned long long *stamps = nullptr;   // [0] start, [1..n] done
+    int n_items = 0;
+    size_t lds = 0;
+    unsigned grid = 0;
+    int cus = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string key;
+};
+
+namespace uwb {
+namespace {
+
+void free_device(uwb_batch_plan *p) {
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    if (p->descs) hipFree(p->descs);
+    if (p->item_scan) hipFree(p->item_scan);
+    p->descs = nullptr;
+    p->item_scan = nullptr;
+}
+
+BatchArgs args_of(const uwb_batch_plan *p) {
+    BatchArgs a;
+    a.descs = p->descs;
+    a.item_scan = p->item_scan;
+    a.n_items = p->n_items;
+    a.n_scans = p->n;
+    a.counter = p->counters;
+    a.remaining = p->counters + 1;
+    a.t_done = p->stamps + 1;
+    a.t_start = p->stamps;
+    return a;
+}
+
+hipError_t enqueue(const uwb_batch_plan *p, hipStream_t st) {
+    const BatchArgs a = args_of(p);
+    const unsigned rb = (unsigned)std::min(1024, (p->n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_batch_reset, dim3(rb > 0 ? rb : 1), dim3(kBlock), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return p->bf == UWB_DMAS ? launch_batch_bf<UWB_DMAS>(p->window, p->d3, p->cfg.vpl, p->grid, p->lds, st, a)
+                             : launch_batch_bf<UWB_DAS>(p->window, p->d3, p->cfg.vpl, p->grid, p->lds, st, a);
+}
+
+// Build descriptors and the work list for the plan's current configuration, then capture the graph.
+int materialise(uwb_batch_plan *p) {
+    free_device(p);
+    const int vpl = p->d3 ? 2 : p->cfg.vpl;
+    const int budget = p->cfg.lds_kb * 1024;
+    int tx, ty, tz;
+    tile_shape(p->d3, vpl, &tx, &ty, &tz);
+    std::vector<BatchDesc> d(p->n);
+    std::vector<double> cost(p->n);
+    size_t lds = 0;
+    for (int s = 0; s < p->n; ++s) {
+        const HostItem &it = p->items[s];
+        BatchDesc &b = d[s];
+        b.pos = it.scan.ant_pos;
+        b.tr = it.scan.traces;
+        b.img = it.img;
+        b.M = it.scan.n_ant;
+        b.T = it.scan.n_samp;
+        b.s = 2.0 / (it.scan.v * it.scan.dt);
+        b.t0s = it.scan.t0 / it.scan.dt;
+        b.g = it.g;
+        b.tiles_x = (it.g.dims[0] + tx - 1) / tx;
+        b.tiles_y = (it.g.dims[1] + ty - 1) / ty;
+        const int tiles_z = (it.g.dims[2] + tz - 1) / tz;
+        b.n_tiles = b.tiles_x * b.tiles_y * tiles_z;
+        b.rs = staged_samples(b.s, (tx - 1) * it.g.pitch[0], (ty - 1) * it.g.pitch[1], (tz - 1) * it.g.pitch[2],
+                              p->window, b.T);
+        const int per_ant = b.rs * 4 + 16;
+        if (per_ant > budget) return UWB_EUNSUPPORTED;
+        b.chunk = std::min(std::min(budget / per_ant, kBlock), b.M);
+        lds = std::max(lds, (size_t)b.chunk * per_ant);
+        cost[s] = (double)b.n_tiles * b.M;
+    }
+    std::vector<int> order(p->n);
+    for (int s = 0; s < p->n; ++s) order[s] = s;
+    if (p->cfg.order == 0)
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<int> item_scan;
+    for (int s : order) {
+        d[s].first_item = (int)item_scan.size();
+        for (int t = 0; t < d[s].n_tiles; ++t) item_scan.push_back(s);
+        if (item_scan.size() > 0x7fffff00u) return UWB_EUNSUPPORTED;
+    }
+    p->n_items = (int)item_scan.size();
+    p->lds = lds;
+    if (hipMalloc(&p->descs, sizeof(BatchDesc) * p->n) != hipSuccess) return UWB_ENOMEM;
+    if (hipMalloc(&p->item_scan, sizeof(int) * std::max(1, p->n_items)) != hipSuccess) return UWB_ENOMEM;
+    if (hipMemcpy(p->descs, d.data(), sizeof(BatchDesc) * p->n, hipMemcpyHostToDevice) != hipSuccess) return UWB_EHIP;
+    if (p->n_items &&
+        hipMemcpy(p->item_scan, item_scan.data(), sizeof(int) * p->n_items, hipMemcpyHostToDevice) != hipSuccess)
+        return UWB_EHIP;
+    p->grid = (unsigned)std::max(1, std::min(p->cus * p->cfg.wgs_per_cu, std::max(1, p->n_items)));
+    // capture reset + persistent kernel once; replays need no host work
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return UWB_EHIP;
+    const hipError_t e = enqueue(p, p->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) {
+        if (g) hipGraphDestroy(g);
+        return UWB_EHIP;
+    }
+    p->graph = g;
+    if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) return UWB_EHIP;
+    return UWB_OK;
+}
+
+// Cache key: beamformer, window, dimensionality and the batch's shape histogram.
+std::string plan_key(const uwb_batch_plan *p) {
+    std::vector<std::string> parts;
+    for (const HostItem &it : p->items) {
+        char b[96];
+        snprintf(b, sizeof b, "%dx%dx%dx%dx%d", it.scan.n_ant, it.scan.n_samp, it.g.dims[0], it.g.dims[1],
+                 it.g.dims[2]);
+        parts.emplace_back(b);
+    }
+    std::sort(parts.begin(), parts.end());
+    std::string k = "bf" + std::to_string(p->bf) + "_w" + std::to_string(p->window) + "_n" + std::to_string(p->n);
+    size_t i = 0;
+    while (i < parts.size()) {
+        size_t j = i;
+        while (j < parts.size() && parts[j] == parts[i]) ++j;
+        k += "_" + parts[i] + ":" + std::to_string(j - i);
+        i = j;
+    }
+    // keys are long for mixed batches: keep a stable 64-bit FNV-1a digest
+    unsigned long long h = 1469598103934665603ull;
+    for (char c : k) { h ^= (unsigned char)c; h *= 1099511628211ull; }
+    char out[64];
+    snprintf(out, sizeof out, "bf%d_w%d_%016llx", p->bf, p->window, h);
+    return out;
+}
+
+// Tiny JSON cache: {"key": [vpl, wgs_per_cu, lds_kb, order], ...}
+bool cache_lookup(const std::string &key, uwb_batch_config *cfg) {
+    const char *path = getenv("UWB_TUNE_CACHE");
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    std::string txt;
+    char buf[4096];
+    size_t r;
+    while ((r = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, r);
+    fclose(f);
+    const size_t at = txt.find("\"" + key + "\"");
+    if (at == std::string::npos) return false;
+    const size_t lb = txt.find('[', at);
+    if (lb == std::string::npos) return false;
+    int v[4];
+    if (sscanf(txt.c_str() + lb, "[%d, %d, %d, %d]", &v[0], &v[1], &v[2], &v[3]) != 4) return false;
+    cfg->vpl = v[0];
+    cfg->wgs_per_cu = v[1];
+    cfg->lds_kb = v[2];
+    cfg->order = v[3];
+    return true;
+}
+
+void cache_store(const std::string &key, const uwb_batch_config &c) {
+    const char *path = getenv("UWB_TUNE_CACHE");
+    if (!path) return;
+    std::string txt;
+    if (FILE *f = fopen(path, "r")) {
+        char buf[4096];
+        size_t r;
+        while ((r = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, r);
+        fclose(f);
+    }
+    // collect existing entries except ours
+    std::vector<std::string> lines;
+    size_t pos = 0;
+    while ((pos = txt.find('"', pos)) != std::string::npos) {
+        const size_t e = txt.find('"', pos + 1);
+        const size_t rb = txt.find(']', e);
+        if (e == std::string::npos || rb == std::string::npos) break;
+        const std::string k = txt.substr(pos + 1, e - pos - 1);
+        if (k != key) lines.push_back(txt.substr(pos, rb - pos + 1));
+        pos = rb + 1;
+    }
+    char mine[256];
+    snprintf(mine, sizeof mine, "\"%s\": [%d, %d, %d, %d]", key.c_str(), c.vpl, c.wgs_per_cu, c.lds_kb, c.order);
+    lines.emplace_back(mine);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fputs("{\n", f);
+    for (size_t i = 0; i < lines.size(); ++i) fprintf(f, "  %s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+    fputs("}\n", f);
+    fclose(f);
+    rename(tmp.c_str(), path);
+}
+
+bool valid_config(const uwb_batch_config &c) {
+    return (c.vpl == 1 || c.vpl == 2 || c.vpl == 4) && c.wgs_per_cu >= 1 && c.wgs_per_cu <= 32 && c.lds_kb >= 4 &&
+           c.lds_kb <= 60 && (c.order == 0 || c.order == 1);
+}
+
+}  // namespace
+
+int check_window(int32_t w);
+int check_grid(const uwb_grid *g, GridView *out);
+int scan_set(const uwb_scan *s, ScanSet *out);
+
+}  // namespace uwb
+
+extern "C" {
+
+int uwb_batch_plan_create(uwb_batch_plan **plan, const uwb_batch_item *items, int32_t n_scans, int32_t beamformer,
+                          int32_t window, const uwb_batch_config *cfg) {
+    if (!plan || !items || n_scans < 1) return UWB_EINVAL;
+    *plan = nullptr;
+    if (beamformer != UWB_DAS && beamformer != UWB_DMAS) return UWB_EINVAL;
+    int st = check_window(window);
+    if (st) return st;
+    if (cfg && !valid_config(*cfg)) return UWB_EINVAL;
+    uwb_batch_plan *p = new (std::nothrow) uwb_batch_plan();
+    if (!p) return UWB_ENOMEM;
+    p->bf = beamformer;
+    p->window = window;
+    p->n = n_scans;
+    p->items.resize(n_scans);
+    for (int s = 0; s < n_scans; ++s) {
+        ScanSet ss;
+        if ((st = scan_set(&items[s].scan, &ss)) || (st = check_grid(&items[s].grid, &p->items[s].g))) {
+            delete p;
+            return st;
+        }
+        if (!items[s].img) { delete p; return UWB_EINVAL; }
+        const bool d3 = items[s].grid.dims[2] > 1;
+        if (s == 0) p->d3 = d3;
+        else if (d3 != p->d3) { delete p; return UWB_EUNSUPPORTED; }   // one kernel shape per plan
+        p->items[s].scan = items[s].scan;
+        p->items[s].img = items[s].img;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || p->cus < 1) {
+        delete p;
+        return UWB_EHIP;
+    }
+    if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) { delete p; return UWB_EHIP; }
+    if (hipMalloc(&p->counters, sizeof(int) * (n_scans + 1)) != hipSuccess ||
+        hipMalloc(&p->stamps, sizeof(unsigned long long) * (n_scans + 1)) != hipSuccess) {
+        uwb_batch_plan_destroy(p);
+        return UWB_ENOMEM;
+    }
+    p->key = plan_key(p);
+    uwb_batch_config c = {2, 8, 40, 0};
+    if (cfg) c = *cfg;
+    else {
+        uwb_batch_config cached;
+        if (cache_lookup(p->key, &cached) && valid_config(cached)) c = cached;
+    }
+    p->cfg = c;
+    if ((st = materialise(p))) {
+        uwb_batch_plan_destroy(p);
+        return st;
+    }
+    *plan = p;
+    return UWB_OK;
+}
+
+int uwb_batch_run(uwb_batch_plan *plan, void *stream) {
+    if (!plan || !plan->exec) return UWB_EINVAL;
+    return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? UWB_OK : UWB_EHIP;
+}
+
+int uwb_batch_get_config(const uwb_batch_plan *plan, uwb_batch_config *cfg) {
+    if (!plan || !cfg) return UWB_EINVAL;
+    *cfg = plan->cfg;
+    return UWB_OK;
+}
+
+int uwb_batch_set_config(uwb_batch_plan *plan, const uwb_batch_config *cfg) {
+    if (!plan || !cfg || !valid_config(*cfg)) return UWB_EINVAL;
+    const uwb_batch_config old = plan->cfg;
+    plan->cfg = *cfg;
+    int st = materialise(plan);
+    if (st) {
+        plan->cfg = old;
+        materialise(plan);
+    }
+    return st;
+}
+
+int uwb_batch_autotune(uwb_batch_plan *plan, int32_t reps, void *stream, uwb_batch_config *best) {
+    if (!plan || reps < 1) return UWB_EINVAL;
+    const hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return UWB_EHIP;
+    const int vpls[3] = {1, 2, 4}, wgs[3] = {2, 4, 8}, ldss[2] = {16, 40}, orders[2] = {0, 1};
+    uwb_batch_config bestc = plan->cfg;
+    float bestt = 1e30f;
+    int status = UWB_OK;
+    for (int v : vpls) {
+        if (plan->d3 && v != 2) continue;
+        for (int w : wgs)
+            for (int l : ldss)
+                for (int o : orders) {
+                    plan->cfg = {v, w, l, o};
+                    if (materialise(plan) != UWB_OK) continue;
+                    if (hipGraphLaunch(plan->exec, st) != hipSuccess) { status = UWB_EHIP; break; }
+                    hipEventRecord(e0, st);
+                    for (int r = 0; r < reps; ++r) hipGraphLaunch(plan->exec, st);
+                    hipEventRecord(e1, st);
+                    if (hipEventSynchronize(e1) != hipSuccess) { status = UWB_EHIP; break; }
+                    float ms = 0.f;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    if (ms < bestt) { bestt = ms; bestc = plan->cfg; }
+                }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    plan->cfg = bestc;
+    const int st2 = materialise(plan);
+    if (status == UWB_OK) status = st2;
+    if (status == UWB_OK) cache_store(plan->key, bestc);
+    if (best) *best = bestc;
+    return status;
+}
+
+int uwb_batch_timestamps(uwb_batch_plan *plan, int64_t *done_ns, void *stream) {
+    if (!plan || !done_ns) return UWB_EINVAL;
+    std::vector<unsigned long long> s(plan->n + 1);
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return UWB_EHIP;
+    if (hipMemcpy(s.data(), plan->stamps, sizeof(unsigned long long) * (plan->n + 1), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return UWB_EHIP;
+    for (int i = 0; i < plan->n; ++i)
+        done_ns[i] = s[i + 1] ? (int64_t)(s[i + 1] - s[0]) * 10 : -1;   // 100 MHz counter -> ns
+    return UWB_OK;
+}
+
+int uwb_batch_plan_destroy(uwb_batch_plan *plan) {
+    if (!plan) return UWB_EINVAL;
+    free_device(plan);
+    if (plan->counters) hipFree(plan->counters);
+    if (plan->stamps) hipFree(plan->stamps);
+    if (plan->cap_stream) hipStreamDestroy(plan->cap_stream);
+    delete plan;
+    return UWB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,200 @@
+// FP32 tile body of the full-resolution DAS / DMAS kernels (shared by the
+// grid-mapped kernel in image32.hip and the persistent batch kernel in
+// batch.hip).  Internal header.
+#pragma once
+
+#include "uwb_internal.h"
+
+namespace uwb {
+
+constexpr int kLdsBudget = 40 * 1024;   // bytes of staged samples per workgroup (default)
+
+// Every odd window 1..31 is compiled.
+#define UWB_WINDOWS(X) X(1) X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) X(27) X(29) X(31)
+
+int staged_samples(double s, double ex, double ey, double ez, int window, int T);
+void tile_shape(bool d3, int vpl, int *tx, int *ty, int *tz);
+
+// One tile of one scan.
+struct TileJob {
+    const float *pos;     // [M][3]
+    const float *tr;      // [M][T]
+    float *img;           // [nz][ny][nx]
+    int M, T;
+    double s, t0s;        // samples per metre of path (2 / (v dt)) and t0 / dt
+    GridView g;
+    int tx0, ty0, tz0;    // first voxel of the tile
+    int rs;               // staged samples per antenna (LDS stride)
+    int chunk;            // antennas staged per pass
+};
+
+// Tile geometry.  2D: 16 (x) by 16*VPL (y); lane (tx, ty) owns y = ty + 16 v.
+//                 3D: 8 x 8 x 4*VPL;     lane (tx, ty, tz) owns z = tz + 4 v.
+// A wave covers a 16 x 4 (2D) or 8 x 8 (3D) patch per v, so its delays -- and
+// its LDS addresses -- stay within a few samples of each other.
+template <bool D3, int VPL> struct TileShape {
+    static constexpr int X = D3 ? 8 : 16, Y = D3 ? 8 : 16 * VPL, Z = D3 ? 4 * VPL : 1;
+    __device__ static void get(int &x, int &y, int &z) { x = X; y = Y; z = Z; }
+};
+
+template <int BF, int W, bool D3, int VPL>
+__device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
+    using TS = TileShape<D3, VPL>;
+    constexpr int H = (W - 1) / 2;
+    constexpr int TX = TS::X, TY = TS::Y, TZ = TS::Z;
+    const int chunk = j.chunk, rs = j.rs;
+    float4 *tab = reinterpret_cast<float4 *>(smem);          // [chunk]
+    float *stage = smem + 4 * chunk;                          // [chunk][rs]
+    const int tid = threadIdx.x;
+    const int nx = j.g.dims[0], ny = j.g.dims[1], nz = j.g.dims[2];
+    const int T = j.T, M = j.M;
+    const int tx0 = j.tx0, ty0 = j.ty0, tz0 = j.tz0;
+
+    const float qx = (float)(j.s * j.g.pitch[0]);
+    const float qy = (float)(j.s * j.g.pitch[1]);
+    const float qz = (float)(j.s * j.g.pitch[2]);
+    const float t0s = (float)j.t0s;
+    // this scan's own staging need must fit the launch's (a batch is sized for its bound)
+    const double ex = (TX - 1) * j.g.pitch[0], ey = (TY - 1) * j.g.pitch[1], ez = (TZ - 1) * j.g.pitch[2];
+    const double need = ceil(j.s * sqrt(ex * ex + ey * ey + ez * ez)) + W + 6;
+    const bool fits = need <= (double)rs || rs >= T + 2 * W + 2;
+
+    // lane -> voxels
+    int vx, vy[VPL], vz[VPL];
+    if (!D3) {
+        vx = tx0 + (tid & 15);
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) { vy[v] = ty0 + (tid >> 4) + 16 * v; vz[v] = 0; }
+    } else {
+        vx = tx0 + (tid & 7);
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) { vy[v] = ty0 + ((tid >> 3) & 7); vz[v] = tz0 + (tid >> 6) + 4 * v; }
+    }
+    const float fx = (float)vx;
+    float fy[VPL], fz[VPL];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) { fy[v] = (float)vy[v]; fz[v] = (float)vz[v]; }
+
+    // bounding box of the tile's voxels (inclusive finest indices)
+    const int bx1 = min(tx0 + TX, nx) - 1, by1 = min(ty0 + TY, ny) - 1, bz1 = min(tz0 + TZ, nz) - 1;
+
+    float acc[VPL][W];
+    float pre[BF == UWB_DMAS ? VPL : 1][BF == UWB_DMAS ? W : 1];
+#pragma unroll
+    for (int v = 0; v < VPL; ++v)
+#pragma unroll
+        for (int k = 0; k < W; ++k) acc[v][k] = 0.f;
+    if (BF == UWB_DMAS) {
+#pragma unroll
+        for (int v = 0; v < (BF == UWB_DMAS ? VPL : 1); ++v)
+#pragma unroll
+            for (int k = 0; k < (BF == UWB_DMAS ? W : 1); ++k) pre[v][k] = 0.f;
+    }
+
+    for (int a0 = 0; a0 < M; a0 += chunk) {
+        const int nch = min(chunk, M - a0);
+        __syncthreads();   // previous chunk (or previous tile) fully consumed
+        if (tid < nch) {
+            const int i = a0 + tid;
+            const double ax = (double)j.pos[3 * i + 0];
+            const double ay = (double)j.pos[3 * i + 1];
+            const double az = (double)j.pos[3 * i + 2];
+            // antenna-relative offsets in sample units: c + idx * q
+            const double cx = j.s * (j.g.origin[0] - ax);
+            const double cy = j.s * (j.g.origin[1] - ay);
+            const double cz = j.s * (j.g.origin[2] - az);
+            const double dqx = j.s * j.g.pitch[0], dqy = j.s * j.g.pitch[1], dqz = j.s * j.g.pitch[2];
+            const double lx = cx + tx0 * dqx, hx = cx + bx1 * dqx;
+            const double ly = cy + ty0 * dqy, hy = cy + by1 * dqy;
+            const double lz = cz + tz0 * dqz, hz = cz + bz1 * dqz;
+            // nearest point of the tile's box to the antenna (the antenna is at 0 here)
+            const double mx = fmin(fmax(0.0, lx), hx), my = fmin(fmax(0.0, ly), hy), mz = fmin(fmax(0.0, lz), hz);
+            const double tmin = sqrt(mx * mx + my * my + mz * mz) - j.t0s;
+            // first staged sample: one below the lowest window start; clamped so that
+            // a window outside the trace still reads a run of zeros
+            double lo = floor(tmin) - (H + 1);
+            lo = fmin(fmax(lo, -(double)(W + 1)), (double)(T + W + 1 - rs));
+            const int ilo = (int)lo;
+            float4 e;
+            e.x = (float)cx;
+            e.y = (float)cy;
+            e.z = D3 ? (float)cz : (float)(cz * cz);
+            e.w = __int_as_float(tid * rs - ilo - H);   // window start = floor(tau) + this
+            tab[tid] = e;
+        }
+        __syncthreads();
+        // stage [lo, lo + rs) of every antenna of the chunk
+        const int wave = tid >> 6, lane = tid & 63;
+        for (int jj = wave; jj < nch; jj += kBlock / 64) {
+            const int ilo = jj * rs - H - __float_as_int(tab[jj].w);
+            const float *tr = j.tr + (int64_t)(a0 + jj) * T;
+            float *dst = stage + jj * rs;
+            for (int m = lane; m < rs; m += 64) {
+                const int gidx = ilo + m;
+                dst[m] = (gidx >= 0 && gidx < T) ? tr[gidx] : 0.f;
+            }
+        }
+        __syncthreads();
+
+        for (int jj = 0; jj < nch; ++jj) {
+            const float4 e = tab[jj];
+            const int base = __float_as_int(e.w);
+            const int lob = jj * rs, hib = jj * rs + rs - (W + 1);
+            const float dx = fmaf(fx, qx, e.x);
+            float part;
+            if (!D3) {
+                part = fmaf(dx, dx, e.z);
+            } else {
+                const float dy = fmaf(fy[0], qy, e.y);
+                part = fmaf(dy, dy, dx * dx);
+            }
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) {
+                float d2;
+                if (!D3) {
+                    const float dy = fmaf(fy[v], qy, e.y);
+                    d2 = fmaf(dy, dy, part);
+                } else {
+                    const float dz = fmaf(fz[v], qz, e.z);
+                    d2 = fmaf(dz, dz, part);
+                }
+                const float tau = __builtin_amdgcn_sqrtf(d2) - t0s;
+                const float fl = floorf(tau);
+                const float f = tau - fl;
+                const float g = 1.f - f;
+                int idx = (int)fl + base;
+                idx = min(max(idx, lob), hib);
+                const float *p = stage + idx;
+                float y[W + 1];
+#pragma unroll
+                for (int k = 0; k <= W; ++k) y[k] = p[k];
+                if (BF == UWB_DAS) {
+#pragma unroll
+                    for (int k = 0; k < W; ++k) acc[v][k] = fmaf(f, y[k + 1], fmaf(g, y[k], acc[v][k]));
+                } else {
+#pragma unroll
+                    for (int k = 0; k < W; ++k) {
+                        const float s = fmaf(f, y[k + 1], g * y[k]);
+                        pre[v][k] = fmaf(s, acc[v][k], pre[v][k]);
+                        acc[v][k] += s;
+                    }
+                }
+            }
+        }
+    }
+
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+        float en = 0.f;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const float q = (BF == UWB_DMAS) ? pre[v][k] : acc[v][k];
+            en = fmaf(q, q, en);
+        }
+        if (!fits) en = __builtin_nanf("");
+        if (vx < nx && vy[v] < ny && vz[v] < nz)
+            j.img[((int64_t)vz[v] * ny + vy[v]) * nx + vx] = en;
+    }
+}
+
+}  // namespace uwb

@@ -38,7 +38,8 @@ def test_struct_layouts_match_header(tmp_path):
     import subprocess
     a = _abi()
     structs = {"uwb_scan": a.UwbScan, "uwb_scan_batch": a.UwbScanBatch, "uwb_grid": a.UwbGrid,
-               "uwb_peak": a.UwbPeak, "uwb_segment_tree": a.UwbSegmentTree, "uwb_segment_result": a.UwbSegmentResult}
+               "uwb_peak": a.UwbPeak, "uwb_segment_tree": a.UwbSegmentTree, "uwb_segment_result": a.UwbSegmentResult,
+               "uwb_batch_item": a.UwbBatchItem, "uwb_batch_config": a.UwbBatchConfig}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void) {']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -220,3 +221,28 @@ def test_product_path_has_no_oracle_dependency():
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, fn
                 assert "liboracle" not in txt, fn
+
+
+def test_batch_plan_argument_errors():
+    a = _abi()
+    L = a.lib()
+    h = ctypes.c_void_p()
+    item = a.UwbBatchItem(_scan(), _grid(), FAKE)
+    items = (a.UwbBatchItem * 2)(item, item)
+    E = a.UWB_EINVAL
+    assert L.uwb_batch_plan_create(None, items, 2, 0, 11, None) == E
+    assert L.uwb_batch_plan_create(ctypes.byref(h), None, 2, 0, 11, None) == E
+    assert L.uwb_batch_plan_create(ctypes.byref(h), items, 0, 0, 11, None) == E
+    assert L.uwb_batch_plan_create(ctypes.byref(h), items, 2, 3, 11, None) == E
+    assert L.uwb_batch_plan_create(ctypes.byref(h), items, 2, 0, 4, None) == E
+    for bad in [(3, 4, 16, 0), (2, 0, 16, 0), (2, 4, 2, 0), (2, 4, 16, 2), (2, 64, 16, 0)]:
+        cfg = a.UwbBatchConfig(*bad)
+        assert L.uwb_batch_plan_create(ctypes.byref(h), items, 2, 0, 11, ctypes.byref(cfg)) == E
+    bad_item = (a.UwbBatchItem * 2)(item, a.UwbBatchItem(_scan(n_ant=0), _grid(), FAKE))
+    assert L.uwb_batch_plan_create(ctypes.byref(h), bad_item, 2, 0, 11, None) == E
+    no_img = (a.UwbBatchItem * 1)(a.UwbBatchItem(_scan(), _grid(), None))
+    assert L.uwb_batch_plan_create(ctypes.byref(h), no_img, 1, 0, 11, None) == E
+    mixed = (a.UwbBatchItem * 2)(item, a.UwbBatchItem(_scan(), _grid(dims=(8, 8, 4)), FAKE))
+    assert L.uwb_batch_plan_create(ctypes.byref(h), mixed, 2, 0, 11, None) == a.UWB_EUNSUPPORTED
+    assert L.uwb_batch_run(None, None) == E
+    assert L.uwb_batch_plan_destroy(None) == E

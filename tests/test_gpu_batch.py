@@ -1,0 +1,114 @@
+"""Batched serving of uneven scans (persistent, graph-captured launch): each scan's
+image equals the single-scan kernel's bitwise and the oracle to the image
+tolerance; graph replays are stable; the autotuner keeps outputs unchanged."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+
+def uwb():
+    import paper_1709_02549_amd as m
+    return m
+
+
+def _uneven(n, seed0=100):
+    scans = [synth.c4_scan(seed0 + k) for k in range(n)]
+    u = uwb()
+    dev = [u.DeviceScan.from_host(s) for s in scans]
+    outs = [torch.full((1, s.grid.dims[1], s.grid.dims[0]), -1.0, device="cuda") for s in scans]
+    return scans, dev, outs
+
+
+@pytest.mark.parametrize("bf", [0, 1])
+def test_batch_plan_matches_single_scan_and_oracle(bf):
+    u = uwb()
+    scans, dev, outs = _uneven(24)
+    plan = u.BatchPlan([(d, s.grid, o) for d, s, o in zip(dev, scans, outs)], bf)
+    plan.run()
+    torch.cuda.synchronize()
+    for s, d, o in zip(scans, dev, outs):
+        one = u.image(d, s.grid, bf)
+        assert torch.equal(one, o), (s.n_ant, s.n_samp, s.grid.dims)
+    # oracle on three of them (sampled voxels for the large grids)
+    for k in (0, 5, 11):
+        s, o = scans[k], outs[k].cpu().numpy().ravel()
+        nx = s.grid.dims[0]
+        sel = np.random.default_rng(k).choice(nx * s.grid.dims[1], 500, replace=False)
+        want = oracle.image_indices(s, bf, np.stack([sel % nx, sel // nx, 0 * sel], 1))
+        ref = oracle.image_indices(s, bf, [[int(np.argmax(o)) % nx, int(np.argmax(o)) // nx, 0]])[0]
+        assert np.max(np.abs(o[sel] - want)) / ref <= 1e-4
+    ts = plan.timestamps_ns()
+    assert np.all(ts > 0)
+    plan.close()
+
+
+def test_graph_replays_with_eager_work_between():
+    u = uwb()
+    scans, dev, outs = _uneven(16, 300)
+    plan = u.BatchPlan([(d, s.grid, o) for d, s, o in zip(dev, scans, outs)], 1)
+    ref = [u.image(d, s.grid, 1).clone() for d, s in zip(dev, scans)]
+    for rep in range(4):
+        for o in outs:
+            o.fill_(float(rep) - 7.0)        # eager work on the same stream between replays
+        plan.run()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o, r), rep
+    plan.close()
+
+
+@pytest.mark.parametrize("cfg", [dict(vpl=1, wgs_per_cu=2, lds_kb=16, order=1),
+                                 dict(vpl=4, wgs_per_cu=8, lds_kb=40, order=0),
+                                 dict(vpl=2, wgs_per_cu=4, lds_kb=8, order=0)])
+def test_every_config_gives_identical_images(cfg):
+    u = uwb()
+    scans, dev, outs = _uneven(12, 500)
+    plan = u.BatchPlan([(d, s.grid, o) for d, s, o in zip(dev, scans, outs)], 0, config=cfg)
+    assert plan.config == cfg
+    plan.run()
+    torch.cuda.synchronize()
+    for d, s, o in zip(dev, scans, outs):
+        assert torch.equal(u.image(d, s.grid, 0), o)
+    plan.close()
+
+
+def test_autotune_and_cache(tmp_path, monkeypatch):
+    u = uwb()
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("UWB_TUNE_CACHE", str(cache))
+    scans, dev, outs = _uneven(20, 700)
+    items = [(d, s.grid, o) for d, s, o in zip(dev, scans, outs)]
+    plan = u.BatchPlan(items, 0)
+    best = plan.autotune(reps=2)
+    assert best["vpl"] in (1, 2, 4)
+    assert cache.exists() and cache.read_text().strip().startswith("{")
+    plan.run()
+    torch.cuda.synchronize()
+    for d, s, o in zip(dev, scans, outs):
+        assert torch.equal(u.image(d, s.grid, 0), o)
+    plan.close()
+    again = u.BatchPlan(items, 0)              # same batch shape: the cached winner is reused
+    assert again.config == best
+    again.close()
+
+
+def test_volumetric_plan_and_mixed_rejected():
+    u = uwb()
+    s3 = [synth.c3_scan(k, n_grid=32, n_ant=16, n_samp=1024) for k in range(3)]
+    d3 = [u.DeviceScan.from_host(s) for s in s3]
+    o3 = [torch.empty((32, 32, 32), device="cuda") for _ in s3]
+    plan = u.BatchPlan([(d, s.grid, o) for d, s, o in zip(d3, s3, o3)], 1)
+    plan.run()
+    torch.cuda.synchronize()
+    for d, s, o in zip(d3, s3, o3):
+        assert torch.equal(u.image(d, s.grid, 1), o)
+    plan.close()
+    s2 = synth.c1_scan(0, n_grid=32)
+    with pytest.raises(u.UwbError):
+        u.BatchPlan([(d3[0], s3[0].grid, o3[0]), (u.DeviceScan.from_host(s2), s2.grid,
+                                                   torch.empty((1, 32, 32), device="cuda"))], 0)
