@@ -33,8 +33,23 @@ def flops_per_va(bf: int, window: int) -> int:
     return FLOPS_DELAY + window * (4 if bf == 0 else 6)
 
 
-PEAK_FP32 = 157.3e12        # MI355X vector FP32, packed FMA
-PEAK_FP32_UNPACKED = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (no packed FP32 in this build)
+# MI355X vector FP32: 256 CU x 4 SIMD x 32 FP32 lanes per clock x 2 flop (FMA) x 2.4 GHz
+PEAK_FP32 = 157.3e12
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2      # wave64 FP32 instructions per second (2 cycles each)
+
+# HBM bytes per launch of the DMAS kernel at the default batch, from two rocprofv3 --pmc runs
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a 256 MiB copy); valid only for the kernel
+# sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
+TRAFFIC = {"source_hash": "12642dd4847ae4f1", "batch": 256, "bytes": 310766066}
+
+
+def _kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("image32.h", "image32.hip"):
+        with open(os.path.join(ROOT, "paper_1709_02549_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def main():
@@ -151,6 +166,8 @@ def main():
 
     fl = flops_per_va(1, W) * va
     achieved = fl / (med["dmas"] * 1e-3)
+    traffic = TRAFFIC["bytes"] if (TRAFFIC["source_hash"] == _kernel_source_hash() and B == TRAFFIC["batch"]) \
+        else None
     out = {
         "metric": "DAS/DMAS Gvoxel·antenna/s; scans/s hierarchical vs full at equal loc. error",
         "value": round(value, 2),
@@ -169,11 +186,9 @@ def main():
                    "batch_scans": B, "distinct_scans": len(distinct), "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": "k_image32 DMAS (W=11, 2D)",
                      "achieved": round(achieved / 1e12, 3), "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_FP32, 4), "traffic": traffic,
                      "flops_per_voxel_antenna": flops_per_va(1, W),
-                     "avg_launch_ms": round(med["dmas"], 5),
-                     "peak_unpacked_fp32": PEAK_FP32_UNPACKED / 1e12,
-                     "frac_unpacked": round(achieved / PEAK_FP32_UNPACKED, 4)},
+                     "avg_launch_ms": round(med["dmas"], 5)},
         "components_ms": {k: round(v, 5) for k, v in med.items()},
         "das_gvas": round(das_gvas, 2),
         "dmas_gvas": round(dmas_gvas, 2),
