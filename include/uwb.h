@@ -275,6 +275,40 @@ int uwb_batch_timestamps(uwb_batch_plan *plan, int64_t *done_ns, void *stream);
 int uwb_batch_plan_destroy(uwb_batch_plan *plan);
 
 /*
+ * Learned segment proposer (extension): a small CNN that scores the four
+ * children of a quadtree box from the box's 32 x 32 coarse DAS energy image,
+ * normalised by its maximum.
+ *   conv3x3(1->32, stride 1) ReLU -> 3 x [conv3x3(32->32, stride 2) ReLU]
+ *   child c = bx + 2 by: mean of the 2 x 2 cells of quadrant (bx, by) -> 32
+ *   features -> shared linear 32 -> 1 -> 4 logits -> softmax.
+ * Zero padding 1.  BF16 weights and activations, FP32 accumulation; FP32
+ * master weights, gradients and Adam moments (beta 0.9 / 0.999, eps 1e-8).
+ * Parameters (uwb_cnn_param_count() = 28097 floats) are flat, in the order
+ * conv weights 1..4 ([32][Cin][3][3] each), conv biases 1..4 ([32] each),
+ * readout weight [32], readout bias.
+ *   x        device [n][32][32] BF16 (uint16 bit patterns), n <= max_batch
+ *   labels   device [n] int32 in 0..3 (the child holding the target)
+ *   probs    device [n][4] fp32
+ *   grad_out device [28097] fp32 (may be NULL); loss_out device fp32 (may be NULL)
+ * The handle owns its device buffers.  Calls on one handle must not overlap.
+ * uwb_cnn_get_state / set_state move the checkpoint (masters, moments, step)
+ * through host buffers of 28097 floats each, synchronising `stream`.
+ */
+typedef struct uwb_cnn uwb_cnn;
+int uwb_cnn_param_count(void);
+int uwb_cnn_create(uwb_cnn **cnn, int32_t max_batch, const float *init_params /* host */);
+int uwb_cnn_destroy(uwb_cnn *cnn);
+int uwb_cnn_forward(uwb_cnn *cnn, const uint16_t *x, int32_t n, float *probs, void *stream);
+int uwb_cnn_gradients(uwb_cnn *cnn, const uint16_t *x, const int32_t *labels, int32_t n, float *grad_out,
+                      float *loss_out, void *stream);
+int uwb_cnn_train_step(uwb_cnn *cnn, const uint16_t *x, const int32_t *labels, int32_t n, float lr,
+                       float *loss_out, void *stream);
+int uwb_cnn_get_state(uwb_cnn *cnn, float *theta, float *m, float *v, int64_t *step, void *stream);
+int uwb_cnn_set_state(uwb_cnn *cnn, const float *theta, const float *m, const float *v, int64_t step,
+                      void *stream);
+const uint16_t *uwb_cnn_weights_bf16(const uwb_cnn *cnn);
+
+/*
  * Automatic spatial decimation factor (Section III; worked example in
  * Section IV): one focal point per square inscribed in the smallest tumour,
  * D = floor(min_tumour / (sqrt(2) * pitch)), at least 1.  Host-only, pure.

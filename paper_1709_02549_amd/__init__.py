@@ -18,7 +18,7 @@ from ._abi import (METRICS, TERMS, UWB_DAS, UWB_DMAS, UWB_MAX_LEVELS, WALKS, Uwb
                    UwbBatchItem, UwbError, UwbGrid, UwbPeak, UwbScan, UwbScanBatch, UwbSegmentResult,
                    UwbSegmentTree, check, lib)
 
-__all__ = ["BatchPlan", "DeviceScan", "DeviceBatch", "das", "dmas", "image", "das_batch", "dmas_batch", "image_batch",
+__all__ = ["BatchPlan", "CNN", "DeviceScan", "DeviceBatch", "das", "dmas", "image", "das_batch", "dmas_batch", "image_batch",
            "argmax", "argmax_batch", "segment_refine", "segment_refine_batch", "auto_decimation",
            "SegmentTree", "UwbError"]
 
@@ -379,6 +379,92 @@ class BatchPlan:
     def close(self):
         if self._h:
             lib().uwb_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------------
+# learned segment proposer (BF16 CNN)
+# ----------------------------------------------------------------------------------
+
+def to_bf16(t: torch.Tensor) -> torch.Tensor:
+    """Round a float tensor to bfloat16 (nearest, ties to even) on its device."""
+    return t.to(torch.bfloat16).contiguous()
+
+
+class CNN:
+    """Device-resident CNN (parameters, Adam state, activation buffers for up to max_batch samples)."""
+
+    def __init__(self, max_batch: int, init_params):
+        p = np.ascontiguousarray(np.asarray(init_params, dtype=np.float32))
+        self.n_params = int(lib().uwb_cnn_param_count())
+        if p.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        self._h = ctypes.c_void_p()
+        check(lib().uwb_cnn_create(ctypes.byref(self._h), int(max_batch), p.ctypes.data_as(ctypes.c_void_p)),
+              "uwb_cnn_create")
+        self.max_batch = int(max_batch)
+
+    @staticmethod
+    def _x(x: torch.Tensor):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.bfloat16 and x.is_contiguous()):
+            raise TypeError("x must be a contiguous CUDA bfloat16 tensor [n, 32, 32]")
+        return x
+
+    def forward(self, x: torch.Tensor, probs: torch.Tensor | None = None) -> torch.Tensor:
+        x = self._x(x)
+        n = int(x.shape[0])
+        if probs is None:
+            probs = torch.empty((n, 4), dtype=torch.float32, device=x.device)
+        check(lib().uwb_cnn_forward(self._h, x.data_ptr(), n, probs.data_ptr(), _stream(x.device)), "uwb_cnn_forward")
+        return probs
+
+    def gradients(self, x: torch.Tensor, labels: torch.Tensor):
+        x = self._x(x)
+        n = int(x.shape[0])
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _need_cuda(labels, "labels", torch.int32)
+        check(lib().uwb_cnn_gradients(self._h, x.data_ptr(), labels.data_ptr(), n, g.data_ptr(), loss.data_ptr(),
+                                      _stream(x.device)), "uwb_cnn_gradients")
+        return g, loss
+
+    def train_step(self, x: torch.Tensor, labels: torch.Tensor, lr: float, loss: torch.Tensor | None = None):
+        x = self._x(x)
+        _need_cuda(labels, "labels", torch.int32)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        check(lib().uwb_cnn_train_step(self._h, x.data_ptr(), labels.data_ptr(), int(x.shape[0]), float(lr),
+                                       loss.data_ptr(), _stream(x.device)), "uwb_cnn_train_step")
+        return loss
+
+    def get_state(self):
+        th = np.zeros(self.n_params, np.float32)
+        m = np.zeros(self.n_params, np.float32)
+        v = np.zeros(self.n_params, np.float32)
+        step = ctypes.c_int64()
+        check(lib().uwb_cnn_get_state(self._h, th.ctypes.data_as(ctypes.c_void_p), m.ctypes.data_as(ctypes.c_void_p),
+                                      v.ctypes.data_as(ctypes.c_void_p), ctypes.byref(step), _stream()),
+              "uwb_cnn_get_state")
+        return {"theta": th, "m": m, "v": v, "step": int(step.value)}
+
+    def set_state(self, st: dict):
+        th, m, v = (np.ascontiguousarray(st[k], dtype=np.float32) for k in ("theta", "m", "v"))
+        check(lib().uwb_cnn_set_state(self._h, th.ctypes.data_as(ctypes.c_void_p), m.ctypes.data_as(ctypes.c_void_p),
+                                      v.ctypes.data_as(ctypes.c_void_p), int(st["step"]), _stream()),
+              "uwb_cnn_set_state")
+
+    def weights_ptr(self) -> int:
+        return int(lib().uwb_cnn_weights_bf16(self._h) or 0)
+
+    def close(self):
+        if self._h:
+            lib().uwb_cnn_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -92,6 +92,15 @@ PROTOTYPES = {
     "uwb_batch_set_config": (c_i32, [c_vp, ctypes.POINTER(UwbBatchConfig)]),
     "uwb_batch_timestamps": (c_i32, [c_vp, ctypes.POINTER(c_i64), c_vp]),
     "uwb_batch_plan_destroy": (c_i32, [c_vp]),
+    "uwb_cnn_param_count": (c_i32, []),
+    "uwb_cnn_create": (c_i32, [ctypes.POINTER(c_vp), c_i32, c_vp]),
+    "uwb_cnn_destroy": (c_i32, [c_vp]),
+    "uwb_cnn_forward": (c_i32, [c_vp, c_vp, c_i32, c_vp, c_vp]),
+    "uwb_cnn_gradients": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp]),
+    "uwb_cnn_train_step": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_f32, c_vp, c_vp]),
+    "uwb_cnn_get_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(c_i64), c_vp]),
+    "uwb_cnn_set_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]),
+    "uwb_cnn_weights_bf16": (c_vp, [c_vp]),
     "uwb_auto_decimation": (c_i32, [c_f64, c_f64]),
     "uwb_status_string": (ctypes.c_char_p, [c_i32]),
     "uwb_version": (ctypes.c_char_p, []),

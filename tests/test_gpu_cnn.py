@@ -1,0 +1,121 @@
+"""GPU CNN (BF16 weights/activations, FP32 accumulation) against the FP64 oracle fed the same
+BF16-rounded weights, inputs and stored activations."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import cnn as ocnn  # noqa: E402
+
+
+def uwb():
+    import paper_1709_02549_amd as m
+    return m
+
+
+def _params(seed):
+    p = ocnn.Params.init(seed)
+    rng = np.random.default_rng(seed + 100)
+    p.b = [rng.normal(0, 0.05, ocnn.CH) for _ in range(4)]
+    p.bl = 0.1
+    # the GPU computes with BF16 copies of the FP32 masters: give the oracle the same numbers
+    flat32 = p.flat().astype(np.float32)
+    return flat32, ocnn.Params.from_flat(ocnn.bf16_round(flat32))
+
+
+def _inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0, 1, (n, 32, 32)) ** 4          # peaky, like normalised energy images
+    xb = ocnn.bf16_round(x)
+    return torch.tensor(xb, dtype=torch.float32, device="cuda").to(torch.bfloat16), xb, rng.integers(0, 4, n)
+
+
+@pytest.mark.parametrize("n", [1, 37, 256])
+def test_forward_matches_oracle(n):
+    flat, p = _params(1)
+    net = uwb().CNN(256, flat)
+    xg, xb, _ = _inputs(n, 2)
+    pg = net.forward(xg).cpu().numpy()
+    logits, _ = ocnn.forward(p, xb, act_round=ocnn.bf16_round)
+    po = ocnn.softmax(logits)
+    np.testing.assert_allclose(pg.sum(axis=1), 1.0, rtol=1e-6)
+    assert np.max(np.abs(pg - po)) <= 1e-2
+    assert np.mean(np.abs(pg - po)) <= 2e-3
+    net.close()
+
+
+def test_gradients_match_oracle():
+    flat, p = _params(3)
+    net = uwb().CNN(64, flat)
+    xg, xb, lab = _inputs(64, 4)
+    g, loss = net.gradients(xg, torch.tensor(lab, dtype=torch.int32, device="cuda"))
+    g = g.cpu().numpy().astype(np.float64)
+    lo, go, _ = ocnn.loss_and_grad(p, xb, lab, act_round=ocnn.bf16_round)
+    assert float(loss.cpu()) == pytest.approx(lo, rel=2e-3)
+    # per tensor: relative error of the gradient vector
+    bounds = [0, 288, 288 + 9216, 288 + 2 * 9216, 288 + 3 * 9216, 288 + 3 * 9216 + 128, 28097]
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        rel = np.linalg.norm(g[a:b] - go[a:b]) / max(np.linalg.norm(go[a:b]), 1e-30)
+        assert rel <= 2e-2, (a, b, rel)
+    net.close()
+
+
+def _task(n, seed):
+    """Label = quadrant of the brightest pixel of a noisy image with one bright blob."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0, 0.3, (n, 32, 32))
+    yy, xx = np.mgrid[0:32, 0:32]
+    lab = rng.integers(0, 4, n)
+    for i in range(n):
+        cx = 4 + 16 * (lab[i] & 1) + rng.integers(0, 8)
+        cy = 4 + 16 * (lab[i] >> 1) + rng.integers(0, 8)
+        x[i] += np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2) / 8.0)
+    x /= x.max(axis=(1, 2), keepdims=True)
+    return (torch.tensor(x, dtype=torch.float32, device="cuda").to(torch.bfloat16),
+            torch.tensor(lab, dtype=torch.int32, device="cuda"))
+
+
+def test_training_learns_and_is_deterministic_and_resumable():
+    flat, _ = _params(7)
+    xs, ls = _task(512, 8)
+    a = uwb().CNN(128, flat)
+    losses = []
+    for step in range(60):
+        k = (step * 128) % 512
+        losses.append(float(a.train_step(xs[k:k + 128], ls[k:k + 128], 3e-3).cpu()))
+        if step == 29:
+            ckpt = a.get_state()
+    assert np.mean(losses[-10:]) < 0.5 * np.mean(losses[:5])
+    probs = a.forward(xs[:128]).cpu().numpy()
+    acc = np.mean(np.argmax(probs, 1) == ls[:128].cpu().numpy())
+    assert acc >= 0.8
+    # same run again: bitwise identical losses
+    b = uwb().CNN(128, flat)
+    again = [float(b.train_step(xs[(s * 128) % 512:(s * 128) % 512 + 128], ls[(s * 128) % 512:(s * 128) % 512 + 128],
+                                3e-3).cpu()) for s in range(60)]
+    assert again == losses
+    # resume from step 30 in a fresh handle: bitwise identical continuation
+    c = uwb().CNN(128, flat)
+    c.set_state(ckpt)
+    cont = [float(c.train_step(xs[(s * 128) % 512:(s * 128) % 512 + 128], ls[(s * 128) % 512:(s * 128) % 512 + 128],
+                               3e-3).cpu()) for s in range(30, 60)]
+    assert cont == losses[30:]
+    assert np.array_equal(c.get_state()["theta"], a.get_state()["theta"])
+    for h in (a, b, c):
+        h.close()
+
+
+def test_first_adam_step_moves_each_weight_against_its_gradient():
+    """Step 1 of Adam moves every weight by lr * g / (|g| + eps): the sign must oppose the oracle's gradient."""
+    flat, p = _params(9)
+    net = uwb().CNN(32, flat)
+    xg, xb, lab = _inputs(32, 10)
+    net.train_step(xg, torch.tensor(lab, dtype=torch.int32, device="cuda"), 1e-3)
+    th = net.get_state()["theta"].astype(np.float64)
+    _, go, _ = ocnn.loss_and_grad(p, xb, lab, act_round=ocnn.bf16_round)
+    d = th - flat.astype(np.float64)
+    big = np.abs(go) > 1e-3 * np.abs(go).max()
+    assert np.mean(np.sign(d[big]) == -np.sign(go[big])) > 0.99
+    assert np.allclose(np.abs(d[big]), 1e-3, rtol=1e-2)
+    net.close()
