@@ -206,6 +206,8 @@ typedef struct {
     int64_t argmax;                         /* finest-grid linear index, x fastest */
     double peak;                            /* FP64 energy there */
     int64_t voxels_evaluated;               /* focal points beamformed in total */
+    int32_t learned_mask;                   /* learned walk: bit l set if the CNN decided split l */
+    int32_t reserved;
 } uwb_segment_result;
 
 /* Largest ROI (voxels) the walk can end with for this grid and tree: the
@@ -287,7 +289,9 @@ int uwb_batch_plan_destroy(uwb_batch_plan *plan);
  * conv weights 1..4 ([32][Cin][3][3] each), conv biases 1..4 ([32] each),
  * readout weight [32], readout bias.
  *   x        device [n][32][32] BF16 (uint16 bit patterns), n <= max_batch
- *   labels   device [n] int32 in 0..3 (the child holding the target)
+ *   labels   device [n] int32 in 0..3 (the child holding the target); a sample
+ *            with any other label is masked out (no loss, no gradient; the
+ *            mean still divides by n)
  *   probs    device [n][4] fp32
  *   grad_out device [28097] fp32 (may be NULL); loss_out device fp32 (may be NULL)
  * The handle owns its device buffers.  Calls on one handle must not overlap.
@@ -307,6 +311,57 @@ int uwb_cnn_get_state(uwb_cnn *cnn, float *theta, float *m, float *v, int64_t *s
 int uwb_cnn_set_state(uwb_cnn *cnn, const float *theta, const float *m, const float *v, int64_t step,
                       void *stream);
 const uint16_t *uwb_cnn_weights_bf16(const uwb_cnn *cnn);
+
+/*
+ * Learned walk: the per-level quadtree walk (planar grid, g = 32, fixed depth)
+ * in which, at every split, the CNN scores the children from the box's coarse
+ * DAS lattice; its child is kept when its probability is >= threshold,
+ * otherwise the tree's metric decides (on the same FP64 lattice).  The final
+ * ROI is imaged with the tree's beamformer as in uwb_segment_refine.
+ * learned_mask bit l of each result tells which splits the CNN decided.
+ * Requires n_scans <= the CNN's max_batch.  Workspace: uwb_learned_workspace_bytes.
+ */
+size_t uwb_learned_workspace_bytes(const uwb_grid *finest, const uwb_segment_tree *tree, int32_t n_scans);
+int uwb_learned_refine_batch(const uwb_scan_batch *scans, const uwb_grid *finest, int32_t window,
+                             const uwb_segment_tree *tree, uwb_cnn *cnn, float threshold,
+                             uwb_segment_result *out, float *roi_img, int64_t roi_capacity, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
+/*
+ * Training inputs of the proposer: for every scan and every level l of the
+ * per-level walk (g = 32) the aligned box of side N / 2^l holding targets[scan]
+ * (e.g. the full-resolution DMAS detection) is imaged on its 32 x 32 lattice
+ * (DAS, FP64, normalised by its maximum) into x [scan * L + l] (BF16), and
+ * labels[scan * L + l] receives the child that holds the target.  A target
+ * index outside the grid yields zero inputs and label -1 for that scan (masked
+ * out by the training calls).
+ * L = uwb_cnn_input_levels(finest) = log2(N / 32).
+ */
+int32_t uwb_cnn_input_levels(const uwb_grid *finest);
+int uwb_cnn_training_inputs(const uwb_scan_batch *scans, const uwb_grid *finest, int32_t window,
+                            const uwb_peak *targets, uint16_t *x, int32_t *labels, void *stream);
+
+/*
+ * GPU generator of seeded synthetic planar scans (training data of the learned
+ * proposer): one tumour and n_clutter point scatterers in a disc of `radius`
+ * around the origin, echoes of the pulse sin(2 pi f0 t) exp(-t^2/2 sigma^2) /
+ * pulse_peak (|t| <= 6 sigma) with 1/r^2 amplitude (1 at 1 cm), white noise at
+ * snr_db.  Scene parameters come from SplitMix64(seed ^ (salt << 56)), noise
+ * from Philox4x32-10 keyed by the seed, so the host generator draws the same
+ * scan for the same seed.
+ *   ant_pos  device [n_ant][3] fp32 (shared by every scan)
+ *   seeds    device [n] uint64
+ *   traces   device [n][n_ant][n_samp] fp32 (n_samp <= 2048)
+ *   tumours  device [n][3] fp64 tumour positions, or NULL
+ */
+typedef struct {
+    int32_t n_ant, n_samp, n_clutter;
+    double v, dt, t0, radius, snr_db;
+    double pulse_f0, pulse_sigma, pulse_peak;
+    uint64_t salt;
+} uwb_gen_recipe;
+int uwb_generate_disc_scans(const uwb_gen_recipe *recipe, const float *ant_pos, const uint64_t *seeds, int32_t n,
+                            float *traces, double *tumours, void *stream);
 
 /*
  * Automatic spatial decimation factor (Section III; worked example in

@@ -15,10 +15,10 @@ import torch
 
 from . import _abi
 from ._abi import (METRICS, TERMS, UWB_DAS, UWB_DMAS, UWB_MAX_LEVELS, WALKS, UwbBatchConfig,  # noqa: F401
-                   UwbBatchItem, UwbError, UwbGrid, UwbPeak, UwbScan, UwbScanBatch, UwbSegmentResult,
+                   UwbBatchItem, UwbError, UwbGenRecipe, UwbGrid, UwbPeak, UwbScan, UwbScanBatch, UwbSegmentResult,
                    UwbSegmentTree, check, lib)
 
-__all__ = ["BatchPlan", "CNN", "DeviceScan", "DeviceBatch", "das", "dmas", "image", "das_batch", "dmas_batch", "image_batch",
+__all__ = ["BatchPlan", "CNN", "generate_disc_scans", "learned_refine_batch", "cnn_training_inputs", "DeviceScan", "DeviceBatch", "das", "dmas", "image", "das_batch", "dmas_batch", "image_batch",
            "argmax", "argmax_batch", "segment_refine", "segment_refine_batch", "auto_decimation",
            "SegmentTree", "UwbError"]
 
@@ -245,6 +245,7 @@ class SegmentResult:
     argmax: int
     peak: float
     voxels_evaluated: int
+    learned_mask: int = 0
     roi_image: np.ndarray | None = None
 
 
@@ -261,7 +262,8 @@ def _results(buf: torch.Tensor, n: int, n_child: int):
             [tuple(int(x) for x in r.box[j]) for j in range(made + 1)],
             [[float(r.score[j][c]) for c in range(n_child)] for j in range(made)],
             [(float(r.wb[j][0]), float(r.wb[j][1])) for j in range(int(r.n_wb))],
-            tuple(int(x) for x in r.roi), int(r.argmax), float(r.peak), int(r.voxels_evaluated)))
+            tuple(int(x) for x in r.roi), int(r.argmax), float(r.peak), int(r.voxels_evaluated),
+            int(r.learned_mask)))
     return out
 
 
@@ -472,3 +474,99 @@ class CNN:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------------
+# learned walk, its training inputs, and the GPU scan generator
+# ----------------------------------------------------------------------------------
+
+def learned_refine_batch(batch: DeviceBatch, grid, tree: SegmentTree, cnn: CNN, threshold: float,
+                         window: int = 11, want_roi: bool = False, out=None, workspace=None, bc=None,
+                         sync: bool = True):
+    """The per-level walk (g = 32, planar, fixed depth) whose splits the CNN decides when confident."""
+    gc, tc = grid_c(grid), tree.c()
+    bc = bc if bc is not None else batch.c()
+    dev = batch.traces.device
+    cap = roi_capacity(grid, tree)
+    need = lib().uwb_learned_workspace_bytes(ctypes.byref(gc), ctypes.byref(tc), batch.n_scans)
+    if need == 0:
+        raise UwbError(-5, "uwb_learned_workspace_bytes")
+    ws = workspace if workspace is not None else _ws.get(need, dev)
+    if out is None:
+        out = torch.empty(ctypes.sizeof(UwbSegmentResult) * batch.n_scans, dtype=torch.uint8, device=dev)
+    roi = torch.empty(cap * batch.n_scans, dtype=torch.float32, device=dev) if want_roi else None
+    check(lib().uwb_learned_refine_batch(ctypes.byref(bc), ctypes.byref(gc), window, ctypes.byref(tc), cnn._h,
+                                         float(threshold), out.data_ptr(), roi.data_ptr() if roi is not None else 0,
+                                         cap, ws.data_ptr(), ws.numel(), _stream(dev)), "uwb_learned_refine_batch")
+    if not sync:
+        return out
+    res = _results(out, batch.n_scans, 4)
+    if want_roi:
+        r = roi.cpu().numpy()
+        for i, x in enumerate(res):
+            b = x.roi
+            shape = (b[5] - b[4], b[3] - b[2], b[1] - b[0])
+            x.roi_image = r[i * cap:i * cap + int(np.prod(shape))].reshape(shape)
+    return res
+
+
+def cnn_input_levels(grid) -> int:
+    gc = grid_c(grid)
+    n = int(lib().uwb_cnn_input_levels(ctypes.byref(gc)))
+    check(min(n, 0), "uwb_cnn_input_levels")
+    return n
+
+
+def cnn_training_inputs(batch: DeviceBatch, grid, peaks: torch.Tensor, window: int = 11, bc=None):
+    """Per-level 32 x 32 DAS lattices along the path to each scan's target voxel, and the true children.
+    peaks: device buffer of uwb_peak records (e.g. from argmax_batch_async).  Returns (x [n*L,32,32] bf16,
+    labels [n*L] int32)."""
+    gc = grid_c(grid)
+    bc = bc if bc is not None else batch.c()
+    dev = batch.traces.device
+    L = cnn_input_levels(grid)
+    n = batch.n_scans
+    x = torch.empty((n * L, 32, 32), dtype=torch.bfloat16, device=dev)
+    lab = torch.empty(n * L, dtype=torch.int32, device=dev)
+    check(lib().uwb_cnn_training_inputs(ctypes.byref(bc), ctypes.byref(gc), window, peaks.data_ptr(), x.data_ptr(),
+                                        lab.data_ptr(), _stream(dev)), "uwb_cnn_training_inputs")
+    return x, lab
+
+
+@dataclasses.dataclass
+class DiscRecipe:
+    """A planar disc recipe: ring antennas, tumour + clutter point scatterers, white noise."""
+    n_samp: int
+    n_clutter: int
+    v: float
+    dt: float
+    t0: float
+    radius: float
+    snr_db: float
+    pulse_f0: float
+    pulse_sigma: float
+    pulse_peak: float
+    salt: int
+
+    def c(self, n_ant: int) -> UwbGenRecipe:
+        return UwbGenRecipe(int(n_ant), int(self.n_samp), int(self.n_clutter), self.v, self.dt, self.t0,
+                            self.radius, self.snr_db, self.pulse_f0, self.pulse_sigma, self.pulse_peak,
+                            int(self.salt))
+
+
+def generate_disc_scans(recipe: DiscRecipe, ant_pos: torch.Tensor, seeds, want_tumours: bool = True):
+    """Synthesise len(seeds) scans on the GPU.  ant_pos [M,3] f32 on the device.  Returns (DeviceBatch,
+    tumours [n,3] f64 or None)."""
+    _need_cuda(ant_pos, "ant_pos")
+    dev = ant_pos.device
+    sd = torch.as_tensor(np.asarray(seeds, dtype=np.uint64).view(np.int64)).to(dev)
+    n, m = int(sd.numel()), int(ant_pos.shape[0])
+    tr = torch.empty((n, m, int(recipe.n_samp)), dtype=torch.float32, device=dev)
+    tum = torch.empty((n, 3), dtype=torch.float64, device=dev) if want_tumours else None
+    rc = recipe.c(m)
+    check(lib().uwb_generate_disc_scans(ctypes.byref(rc), ant_pos.data_ptr(), sd.data_ptr(), n, tr.data_ptr(),
+                                        tum.data_ptr() if tum is not None else 0, _stream(dev)),
+          "uwb_generate_disc_scans")
+    par = torch.tensor([[recipe.dt, recipe.t0, recipe.v]] * n, dtype=torch.float64, device=dev)
+    pos = ant_pos.unsqueeze(0).expand(n, m, 3).contiguous()
+    return DeviceBatch(pos, tr, par), tum

@@ -54,7 +54,7 @@ class UwbSegmentResult(ctypes.Structure):
                 ("child", c_i32 * UWB_MAX_LEVELS), ("box", (c_i32 * 6) * (UWB_MAX_LEVELS + 1)),
                 ("score", (c_f64 * 8) * UWB_MAX_LEVELS), ("wb", (c_f64 * 2) * (UWB_MAX_LEVELS + 1)),
                 ("n_wb", c_i32), ("roi", c_i32 * 6), ("argmax", c_i64), ("peak", c_f64),
-                ("voxels_evaluated", c_i64)]
+                ("voxels_evaluated", c_i64), ("learned_mask", c_i32), ("reserved", c_i32)]
 
 
 class UwbBatchItem(ctypes.Structure):
@@ -63,6 +63,12 @@ class UwbBatchItem(ctypes.Structure):
 
 class UwbBatchConfig(ctypes.Structure):
     _fields_ = [("vpl", c_i32), ("wgs_per_cu", c_i32), ("lds_kb", c_i32), ("order", c_i32)]
+
+
+class UwbGenRecipe(ctypes.Structure):
+    _fields_ = [("n_ant", c_i32), ("n_samp", c_i32), ("n_clutter", c_i32), ("v", c_f64), ("dt", c_f64),
+                ("t0", c_f64), ("radius", c_f64), ("snr_db", c_f64), ("pulse_f0", c_f64), ("pulse_sigma", c_f64),
+                ("pulse_peak", c_f64), ("salt", ctypes.c_uint64)]
 
 
 # name -> (restype, argtypes)
@@ -101,6 +107,15 @@ PROTOTYPES = {
     "uwb_cnn_get_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, ctypes.POINTER(c_i64), c_vp]),
     "uwb_cnn_set_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp]),
     "uwb_cnn_weights_bf16": (c_vp, [c_vp]),
+    "uwb_learned_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(UwbGrid), ctypes.POINTER(UwbSegmentTree),
+                                                      c_i32]),
+    "uwb_learned_refine_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32,
+                                         ctypes.POINTER(UwbSegmentTree), c_vp, c_f32, c_vp, c_vp, c_i64, c_vp,
+                                         ctypes.c_size_t, c_vp]),
+    "uwb_cnn_input_levels": (c_i32, [ctypes.POINTER(UwbGrid)]),
+    "uwb_cnn_training_inputs": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp,
+                                        c_vp, c_vp]),
+    "uwb_generate_disc_scans": (c_i32, [ctypes.POINTER(UwbGenRecipe), c_vp, c_vp, c_i32, c_vp, c_vp, c_vp]),
     "uwb_auto_decimation": (c_i32, [c_f64, c_f64]),
     "uwb_status_string": (ctypes.c_char_p, [c_i32]),
     "uwb_version": (ctypes.c_char_p, []),

@@ -123,6 +123,21 @@ static int walk_common(const ScanSet &ss, int n, const uwb_grid *finest, int32_t
     return launch_walk(a, n, (hipStream_t)stream);
 }
 
+int cnn_max_batch(const uwb_cnn *h);
+
+// The learned walk: per-level quadtree on a planar grid with g = 32 (the CNN's input), fixed depth.
+static int learned_plan(const GridView &g, const uwb_segment_tree *t, int n, WalkArgs *a, int64_t *bound,
+                        size_t *need) {
+    if (!t) return UWB_EINVAL;
+    if (t->walk != UWB_WALK_PER_LEVEL || t->coarse != 32 || g.dims[2] != 1 || t->term != UWB_TERM_FIXED_DEPTH)
+        return UWB_EUNSUPPORTED;
+    int st = plan_walk(g, t, n, a, bound, need);
+    if (st) return st;
+    if (a->depth < 1) return UWB_EUNSUPPORTED;
+    *need += (size_t)n * (32 * 32 * 2 + 4 * 4 + 4) + 3 * 256;
+    return UWB_OK;
+}
+
 }  // namespace uwb
 
 using namespace uwb;
@@ -214,6 +229,88 @@ int uwb_segment_refine_batch(const uwb_scan_batch *scans, const uwb_grid *finest
     return st ? st
               : walk_common(ss, scans->n_scans, finest, window, tree, out, roi_img, roi_capacity, workspace,
                             workspace_bytes, stream);
+}
+
+size_t uwb_learned_workspace_bytes(const uwb_grid *finest, const uwb_segment_tree *tree, int32_t n_scans) {
+    GridView g;
+    if (check_grid(finest, &g) || n_scans < 1) return 0;
+    WalkArgs a;
+    int64_t bound = 0;
+    size_t need = 0;
+    if (learned_plan(g, tree, n_scans, &a, &bound, &need)) return 0;
+    return need;
+}
+
+int uwb_learned_refine_batch(const uwb_scan_batch *scans, const uwb_grid *finest, int32_t window,
+                             const uwb_segment_tree *tree, uwb_cnn *cnn, float threshold, uwb_segment_result *out,
+                             float *roi_img, int64_t roi_capacity, void *workspace, size_t workspace_bytes,
+                             void *stream) {
+    ScanSet ss;
+    int st = batch_set(scans, &ss);
+    if (st) return st;
+    GridView g;
+    if ((st = check_grid(finest, &g))) return st;
+    if ((st = check_window(window))) return st;
+    if (!cnn || !out || !workspace || !std::isfinite(threshold)) return UWB_EINVAL;
+    const int n = scans->n_scans;
+    if (n > cnn_max_batch(cnn)) return UWB_ERANGE;
+    WalkArgs a;
+    int64_t bound = 0;
+    size_t need = 0;
+    if ((st = learned_plan(g, tree, n, &a, &bound, &need))) return st;
+    if (roi_img && roi_capacity < bound) return UWB_ERANGE;
+    if (workspace_bytes < need) return UWB_ERANGE;
+    a.ss = ss;
+    a.window = window;
+    a.out = out;
+    a.roi_img = roi_img;
+    a.roi_img_stride = roi_img ? roi_capacity : 0;
+    uintptr_t p = ((uintptr_t)workspace + 255) & ~(uintptr_t)255;
+    a.roi64 = reinterpret_cast<double *>(p);
+    a.dec64 = nullptr;
+    p += (size_t)n * bound * 8;
+    p = (p + 255) & ~(uintptr_t)255;
+    uint16_t *xin = reinterpret_cast<uint16_t *>(p);
+    p += (size_t)n * 32 * 32 * 2;
+    p = (p + 255) & ~(uintptr_t)255;
+    float *probs = reinterpret_cast<float *>(p);
+    p += (size_t)n * 16;
+    p = (p + 255) & ~(uintptr_t)255;
+    int *fb = reinterpret_cast<int *>(p);
+    size_walk_lds(&a, ss.n_ant);
+    return launch_learned(a, n, cnn, threshold, xin, probs, fb, tree->beamformer, (hipStream_t)stream);
+}
+
+int uwb_cnn_training_inputs(const uwb_scan_batch *scans, const uwb_grid *finest, int32_t window,
+                            const uwb_peak *targets, uint16_t *x, int32_t *labels, void *stream) {
+    ScanSet ss;
+    int st = batch_set(scans, &ss);
+    if (st) return st;
+    GridView g;
+    if ((st = check_grid(finest, &g))) return st;
+    if ((st = check_window(window))) return st;
+    if (!targets || !x || !labels) return UWB_EINVAL;
+    uwb_segment_tree t = {UWB_DAS, UWB_WALK_PER_LEVEL, 32, 0, 0.01, 0, UWB_MAX, UWB_TERM_FIXED_DEPTH, 0.0, 0.0};
+    WalkArgs a;
+    int64_t bound = 0;
+    size_t need = 0;
+    if ((st = learned_plan(g, &t, scans->n_scans, &a, &bound, &need))) return st;
+    a.ss = ss;
+    a.window = window;
+    size_walk_lds(&a, ss.n_ant);
+    return launch_cnn_inputs(a, scans->n_scans, targets, x, labels, (hipStream_t)stream);
+}
+
+int32_t uwb_cnn_input_levels(const uwb_grid *finest) {
+    GridView g;
+    int st = check_grid(finest, &g);
+    if (st) return st;
+    uwb_segment_tree t = {UWB_DAS, UWB_WALK_PER_LEVEL, 32, 0, 0.01, 0, UWB_MAX, UWB_TERM_FIXED_DEPTH, 0.0, 0.0};
+    WalkArgs a;
+    int64_t bound = 0;
+    size_t need = 0;
+    if ((st = learned_plan(g, &t, 1, &a, &bound, &need))) return st;
+    return a.depth;
 }
 
 int uwb_auto_decimation(double min_tumour, double pitch) {

@@ -34,13 +34,6 @@ constexpr int OFF_B = 288 + 3 * 9216;          // 27936
 constexpr int OFF_WL = OFF_B + 4 * C;          // 28064
 constexpr int OFF_BL = OFF_WL + C;             // 28096
 
-__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return (uint16_t)((u >> 16) | 0x40);   // NaN
-    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest, ties to even
-    return (uint16_t)(u >> 16);
-}
 
 // ------------------------------------------------------------------------------
 // forward convolution: X [N][CIN][HIN][HIN] bf16 -> Y [N][32][HO][HO] bf16 (ReLU)
@@ -139,9 +132,12 @@ __global__ __launch_bounds__(256) void k_readout(const uint16_t *__restrict__ A4
         }
         if (labels) {
             const int lab = labels[s];
-            lsum += -(z[lab] - mx - logf(se));
+            const bool valid = lab >= 0 && lab < 4;    // other labels mask the sample out
+            float zl = z[0];
+            for (int c = 1; c < 4; ++c) zl = c == lab ? z[c] : zl;
+            if (valid) lsum += -(zl - mx - logf(se));
             float dl[4];
-            for (int c = 0; c < 4; ++c) dl[c] = (pr[c] - (c == lab ? 1.f : 0.f)) / (float)n;
+            for (int c = 0; c < 4; ++c) dl[c] = valid ? (pr[c] - (c == lab ? 1.f : 0.f)) / (float)n : 0.f;
             for (int c = 0; c < 4; ++c) {
                 dbl += dl[c];
                 for (int k = 0; k < C; ++k) dwl[k] = fmaf(dl[c], feat[c][k], dwl[k]);
@@ -372,6 +368,10 @@ hipError_t backward(uwb_cnn *h, const uint16_t *x, const int *labels, int n, hip
 }
 
 }  // namespace
+}  // namespace uwb
+
+namespace uwb {
+int cnn_max_batch(const uwb_cnn *h) { return h ? h->max_batch : 0; }
 }  // namespace uwb
 
 extern "C" {

@@ -55,6 +55,15 @@ __device__ __forceinline__ ScanConst scan_const(const ScanSet &ss, int scan) {
     return c;
 }
 
+// BF16 <-> FP32 (BF16 stored as its 16-bit pattern).
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return (uint16_t)((u >> 16) | 0x40);   // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+
 // Wave-level reductions (wave64).
 __device__ __forceinline__ double wave_sum(double x) {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);

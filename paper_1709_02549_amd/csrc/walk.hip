@@ -197,6 +197,131 @@ __global__ __launch_bounds__(kBlock) void k_lattice64(const WalkArgs a, int from
     }
 }
 
+// FP64 energies of every point of lattice L into lv (LDS), trace spans staged in LDS.
+__device__ void eval_lattice(const WalkArgs &a, const ScanConst &sc, const Lattice &L, double *lv, Stage &st,
+                             int *tmp) {
+    const int tid = threadIdx.x;
+    const int P = L.count();
+    int blo[3], bhi[3];
+    for (int d = 0; d < 3; ++d) { blo[d] = L.x0[d]; bhi[d] = L.x0[d] + L.step * (L.cnt[d] - 1); }
+    const bool staged = stage_box(st, tmp, sc, a.ss.n_ant, a.ss.n_samp, a.window, a.g, blo, bhi);
+    int G = kBlock / P;                 // lanes per point
+    if (G > 64) G = 64;
+    if (G < 1) G = 1;
+    G = 1 << (31 - __clz(G));
+    const int per = kBlock / G;
+    for (int q0 = 0; q0 < P; q0 += per) {
+        const int p = q0 + tid / G;
+        const bool ok = p < P;
+        int x, y, z;
+        L.coord(ok ? p : 0, x, y, z);
+        const double rx = a.g.origin[0] + x * a.g.pitch[0];
+        const double ry = a.g.origin[1] + y * a.g.pitch[1];
+        const double rz = a.g.origin[2] + z * a.g.pitch[2];
+        const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, tid % G, G,
+                                           staged ? &st : nullptr);
+        if (ok && tid % G == 0) lv[p] = e;
+    }
+    __syncthreads();
+}
+
+struct LevelStats {
+    double pn, pmean, pm2;
+    double count[8];
+};
+
+// Parent (current box) and child statistics of one level and the children's metric (Section III).
+// cbox receives the children boxes, sc8 their scores under a.metric.
+__device__ LevelStats level_stats(const WalkArgs &a, const Lattice &L, const double *src, const int *box, int nact,
+                              int side, bool paper, double *red, int cbox[8][6], double sc8[8]) {
+    const int tid = threadIdx.x;
+    const int nchild = 1 << nact;
+    const int P = L.count();
+    // children boxes and their scoring boxes
+    int sbx[8][6];
+    const int half = side / 2;
+    const int efr = paper ? 0 : (int)floor(a.frame_level * (double)half);
+    for (int c = 0; c < nchild; ++c) {
+        split_box(box, c, nact, cbox[c]);
+        for (int i = 0; i < 6; ++i) sbx[c][i] = cbox[c][i];
+        if (!paper) {
+            for (int d = 0; d < nact; ++d) {
+                sbx[c][2 * d] = max(box[2 * d], cbox[c][2 * d] - efr);
+                sbx[c][2 * d + 1] = min(box[2 * d + 1], cbox[c][2 * d + 1] + efr);
+            }
+        }
+    }
+
+    // pass 1: counts, sums, maxima of the parent (current box) and children
+    double s1[18], mx[9];
+    for (int i = 0; i < 18; ++i) s1[i] = 0.0;
+    for (int i = 0; i < 9; ++i) mx[i] = -INFINITY;
+    for (int p = tid; p < P; p += kBlock) {
+        int x, y, z;
+        L.coord(p, x, y, z);
+        if (!in_box(box, x, y, z)) continue;
+        const double v = src[p];
+        s1[0] += 1.0; s1[1] += v; mx[0] = fmax(mx[0], v);
+        for (int c = 0; c < nchild; ++c)
+            if (in_box(sbx[c], x, y, z)) { s1[2 + 2 * c] += 1.0; s1[3 + 2 * c] += v; mx[1 + c] = fmax(mx[1 + c], v); }
+    }
+    block_sum(s1, red);
+    block_max(mx, red);
+    const double pn = s1[0], pmean = s1[1] / pn, pmax = mx[0];
+    const double scale = pmax > 0.0 ? pmax : 1.0;    // Eq. (5) normalisation
+    double cmean[8];
+    for (int c = 0; c < nchild; ++c) cmean[c] = s1[3 + 2 * c] / s1[2 + 2 * c];
+    // pass 2: normalised sums (Eq. 5) and raw squared deviations
+    double s2[18];
+    for (int i = 0; i < 18; ++i) s2[i] = 0.0;
+    for (int p = tid; p < P; p += kBlock) {
+        int x, y, z;
+        L.coord(p, x, y, z);
+        if (!in_box(box, x, y, z)) continue;
+        const double v = src[p];
+        const double vn = pmax > 0.0 ? v / scale : v;
+        s2[0] += (v - pmean) * (v - pmean); s2[1] += vn;
+        for (int c = 0; c < nchild; ++c)
+            if (in_box(sbx[c], x, y, z)) {
+                s2[2 + 2 * c] += (v - cmean[c]) * (v - cmean[c]);
+                s2[3 + 2 * c] += vn;
+            }
+    }
+    block_sum(s2, red);
+    const double pm2 = s2[0];
+    const double pnmean = s2[1] / pn;
+    double cnmean[8];
+    for (int c = 0; c < nchild; ++c) cnmean[c] = s2[3 + 2 * c] / s1[2 + 2 * c];
+    // pass 3: normalised squared deviations (Eq. 5 variances)
+    double s3[9];
+    for (int i = 0; i < 9; ++i) s3[i] = 0.0;
+    if (a.metric == UWB_EQ5 || a.metric == UWB_EQ5_CLAMPED) {
+        for (int p = tid; p < P; p += kBlock) {
+            int x, y, z;
+            L.coord(p, x, y, z);
+            if (!in_box(box, x, y, z)) continue;
+            const double v = src[p];
+            const double vn = pmax > 0.0 ? v / scale : v;
+            s3[0] += (vn - pnmean) * (vn - pnmean);
+            for (int c = 0; c < nchild; ++c)
+                if (in_box(sbx[c], x, y, z)) s3[1 + c] += (vn - cnmean[c]) * (vn - cnmean[c]);
+        }
+        block_sum(s3, red);
+    }
+
+    LevelStats out;
+    out.pn = pn;
+    out.pmean = pmean;
+    out.pm2 = pm2;
+    for (int c = 0; c < nchild; ++c) {
+        out.count[c] = s1[2 + 2 * c];
+        const double n = s1[2 + 2 * c];
+        const double nvar = s3[1 + c] / n;
+        sc8[c] = metric_value(a.metric, n, cmean[c], s2[2 + 2 * c], mx[1 + c], cnmean[c], nvar, s3[0] / pn);
+    }
+    return out;
+}
+
 // ----------------------------------------------------------------------------
 // k_walk: the ROI-selection loop, one workgroup per scan.
 // ----------------------------------------------------------------------------
@@ -250,103 +375,16 @@ __global__ __launch_bounds__(kBlock) void k_walk(const WalkArgs a) {
                 L.cnt[d] = d < nact ? a.coarse : 1;
             }
             L.step = step;
-            const int P = L.count();
-            int blo[3], bhi[3];
-            for (int d = 0; d < 3; ++d) { blo[d] = L.x0[d]; bhi[d] = L.x0[d] + step * (L.cnt[d] - 1); }
-            const bool staged = stage_box(st, tmp, sc, a.ss.n_ant, a.ss.n_samp, a.window, a.g, blo, bhi);
-            int G = kBlock / P;                 // lanes per point
-            if (G > 64) G = 64;
-            if (G < 1) G = 1;
-            G = 1 << (31 - __clz(G));
-            const int per = kBlock / G;
-            for (int q0 = 0; q0 < P; q0 += per) {
-                const int p = q0 + tid / G;
-                const bool ok = p < P;
-                int x, y, z;
-                L.coord(ok ? p : 0, x, y, z);
-                const double rx = a.g.origin[0] + x * a.g.pitch[0];
-                const double ry = a.g.origin[1] + y * a.g.pitch[1];
-                const double rz = a.g.origin[2] + z * a.g.pitch[2];
-                const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, tid % G, G,
-                                                   staged ? &st : nullptr);
-                if (ok && tid % G == 0) lv[p] = e;
-            }
-            __syncthreads();
-            nvox += P;
-        }
-        const int P = L.count();
-
-        // children boxes and their scoring boxes
-        int cbox[8][6], sbx[8][6];
-        const int half = side / 2;
-        const int efr = paper ? 0 : (int)floor(a.frame_level * (double)half);
-        for (int c = 0; c < nchild; ++c) {
-            split_box(box, c, nact, cbox[c]);
-            for (int i = 0; i < 6; ++i) sbx[c][i] = cbox[c][i];
-            if (!paper) {
-                for (int d = 0; d < nact; ++d) {
-                    sbx[c][2 * d] = max(box[2 * d], cbox[c][2 * d] - efr);
-                    sbx[c][2 * d + 1] = min(box[2 * d + 1], cbox[c][2 * d + 1] + efr);
-                }
-            }
+            eval_lattice(a, sc, L, lv, st, tmp);
+            nvox += L.count();
         }
 
-        // pass 1: counts, sums, maxima of the parent (current box) and children
-        double s1[18], mx[9];
-        for (int i = 0; i < 18; ++i) s1[i] = 0.0;
-        for (int i = 0; i < 9; ++i) mx[i] = -INFINITY;
-        for (int p = tid; p < P; p += kBlock) {
-            int x, y, z;
-            L.coord(p, x, y, z);
-            if (!in_box(box, x, y, z)) continue;
-            const double v = src[p];
-            s1[0] += 1.0; s1[1] += v; mx[0] = fmax(mx[0], v);
-            for (int c = 0; c < nchild; ++c)
-                if (in_box(sbx[c], x, y, z)) { s1[2 + 2 * c] += 1.0; s1[3 + 2 * c] += v; mx[1 + c] = fmax(mx[1 + c], v); }
-        }
-        block_sum(s1, red);
-        block_max(mx, red);
-        const double pn = s1[0], pmean = s1[1] / pn, pmax = mx[0];
-        const double scale = pmax > 0.0 ? pmax : 1.0;    // Eq. (5) normalisation
-        double cmean[8];
-        for (int c = 0; c < nchild; ++c) cmean[c] = s1[3 + 2 * c] / s1[2 + 2 * c];
-        // pass 2: normalised sums (Eq. 5) and raw squared deviations
-        double s2[18];
-        for (int i = 0; i < 18; ++i) s2[i] = 0.0;
-        for (int p = tid; p < P; p += kBlock) {
-            int x, y, z;
-            L.coord(p, x, y, z);
-            if (!in_box(box, x, y, z)) continue;
-            const double v = src[p];
-            const double vn = pmax > 0.0 ? v / scale : v;
-            s2[0] += (v - pmean) * (v - pmean); s2[1] += vn;
-            for (int c = 0; c < nchild; ++c)
-                if (in_box(sbx[c], x, y, z)) {
-                    s2[2 + 2 * c] += (v - cmean[c]) * (v - cmean[c]);
-                    s2[3 + 2 * c] += vn;
-                }
-        }
-        block_sum(s2, red);
-        const double pm2 = s2[0];
-        const double pnmean = s2[1] / pn;
-        double cnmean[8];
-        for (int c = 0; c < nchild; ++c) cnmean[c] = s2[3 + 2 * c] / s1[2 + 2 * c];
-        // pass 3: normalised squared deviations (Eq. 5 variances)
-        double s3[9];
-        for (int i = 0; i < 9; ++i) s3[i] = 0.0;
-        if (a.metric == UWB_EQ5 || a.metric == UWB_EQ5_CLAMPED) {
-            for (int p = tid; p < P; p += kBlock) {
-                int x, y, z;
-                L.coord(p, x, y, z);
-                if (!in_box(box, x, y, z)) continue;
-                const double v = src[p];
-                const double vn = pmax > 0.0 ? v / scale : v;
-                s3[0] += (vn - pnmean) * (vn - pnmean);
-                for (int c = 0; c < nchild; ++c)
-                    if (in_box(sbx[c], x, y, z)) s3[1 + c] += (vn - cnmean[c]) * (vn - cnmean[c]);
-            }
-            block_sum(s3, red);
-        }
+        int cbox[8][6];
+        double sc8[8];
+        const LevelStats ls = level_stats(a, L, src, box, nact, side, paper, red, cbox, sc8);
+        const double pn = ls.pn, pmean = ls.pmean, pm2 = ls.pm2;
+        double cmin = INFINITY;
+        for (int c = 0; c < nchild; ++c) cmin = fmin(cmin, ls.count[c]);
 
         // Eq. (6)-(7) stop on the previous and the current box's samples
         bool stop = false;
@@ -365,20 +403,10 @@ __global__ __launch_bounds__(kBlock) void k_walk(const WalkArgs a) {
         prev_mean = pmean;
         prev_m2 = pm2;
         if (lev == a.depth) { n_kept = a.depth; break; }
-        if (paper) {
-            double cmin = INFINITY;
-            for (int c = 0; c < nchild; ++c) cmin = fmin(cmin, s1[2 + 2 * c]);
-            if (cmin < kMinChildSamples) { n_kept = lev; break; }
-        }
-        // score the children and select (lowest index within the tie band)
-        double sc8[8];
+        if (paper && cmin < kMinChildSamples) { n_kept = lev; break; }
+        // select the child (lowest index within the tie band)
         double best = -INFINITY;
-        for (int c = 0; c < nchild; ++c) {
-            const double n = s1[2 + 2 * c];
-            const double nvar = s3[1 + c] / n;
-            sc8[c] = metric_value(a.metric, n, cmean[c], s2[2 + 2 * c], mx[1 + c], cnmean[c], nvar, s3[0] / pn);
-            best = fmax(best, sc8[c]);
-        }
+        for (int c = 0; c < nchild; ++c) best = fmax(best, sc8[c]);
         const double thr = best - kTieRel * fabs(best);
         int sel = 0;
         for (int c = nchild - 1; c >= 0; --c)
@@ -408,6 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(const WalkArgs a) {
         R.voxels_evaluated = nvox + rv;
         R.argmax = -1;
         R.peak = 0.0;
+        R.learned_mask = 0;
     }
 }
 
@@ -455,6 +484,153 @@ __global__ __launch_bounds__(kBlock) void k_roi_argmax(const WalkArgs a) {
     }
 }
 
+
+// ----------------------------------------------------------------------------
+// Learned walk (per-level quadtree, g = 32, planar): each level images the box's
+// 32 x 32 lattice (DAS, FP64), scores the children with the configured metric,
+// and writes the lattice normalised by its maximum as the CNN's BF16 input; after
+// the batched CNN forward, k_learn_decide keeps the CNN's child when its
+// probability reaches the threshold and the metric's child otherwise.
+// ----------------------------------------------------------------------------
+constexpr int kLearnG = 32;
+
+__device__ void lattice_of_box(const int *box, int side, Lattice &L) {
+    const int step = side / kLearnG;
+    L.x0[0] = box[0] + step / 2;
+    L.x0[1] = box[2] + step / 2;
+    L.x0[2] = 0;
+    L.cnt[0] = kLearnG;
+    L.cnt[1] = kLearnG;
+    L.cnt[2] = 1;
+    L.step = step;
+}
+
+// normalise lv (kLearnG^2 values) by its maximum and store it as BF16 [y][x]
+__device__ void write_cnn_input(const double *lv, double *red, uint16_t *x) {
+    double m[1] = {-INFINITY};
+    for (int p = threadIdx.x; p < kLearnG * kLearnG; p += kBlock) m[0] = fmax(m[0], lv[p]);
+    block_max(m, red);
+    const double inv = m[0] > 0.0 ? 1.0 / m[0] : 1.0;
+    for (int p = threadIdx.x; p < kLearnG * kLearnG; p += kBlock) x[p] = f2bf((float)(lv[p] * inv));
+}
+
+__global__ __launch_bounds__(kBlock) void k_learn_level(const WalkArgs a, int lev, uint16_t *xin, int *fb_child) {
+    extern __shared__ __align__(16) unsigned char dsm[];
+    double *lv = reinterpret_cast<double *>(dsm);
+    __shared__ double red[kWaves * 32];
+    __shared__ int tmp[kWaves];
+    Stage st;
+    st.lo = reinterpret_cast<int *>(dsm + sizeof(double) * a.pmax);
+    st.off = st.lo + a.stage_ant;
+    st.len = st.off + a.stage_ant;
+    st.buf = reinterpret_cast<float *>(st.len + a.stage_ant);
+    st.cap = a.stage_cap;
+    const int scan = blockIdx.x, tid = threadIdx.x;
+    uwb_segment_result &R = a.out[scan];
+    const ScanConst sc = scan_const(a.ss, scan);
+    int box[6];
+    if (lev == 0) {
+        box[0] = 0; box[1] = a.g.dims[0]; box[2] = 0; box[3] = a.g.dims[1]; box[4] = 0; box[5] = 1;
+        if (tid == 0)
+            for (int i = 0; i < 6; ++i) R.box[0][i] = box[i];
+    } else {
+        for (int i = 0; i < 6; ++i) box[i] = R.box[lev][i];
+    }
+    const int side = a.g.dims[0] >> lev;
+    Lattice L;
+    lattice_of_box(box, side, L);
+    eval_lattice(a, sc, L, lv, st, tmp);
+    int cbox[8][6];
+    double sc8[8];
+    level_stats(a, L, lv, box, 2, side, false, red, cbox, sc8);
+    double best = -INFINITY;
+    for (int c = 0; c < 4; ++c) best = fmax(best, sc8[c]);
+    const double thr = best - kTieRel * fabs(best);
+    int sel = 0;
+    for (int c = 3; c >= 0; --c)
+        if (sc8[c] >= thr) sel = c;
+    if (tid == 0) {
+        fb_child[scan] = sel;
+        for (int c = 0; c < 8; ++c) R.score[lev][c] = c < 4 ? sc8[c] : 0.0;
+    }
+    write_cnn_input(lv, red, xin + (size_t)scan * kLearnG * kLearnG);
+}
+
+__global__ void k_learn_decide(const WalkArgs a, int lev, int n_scans, const float *probs, const int *fb_child,
+                               float threshold) {
+    const int scan = blockIdx.x * blockDim.x + threadIdx.x;
+    if (scan >= n_scans) return;
+    uwb_segment_result &R = a.out[scan];
+    const float *p = probs + 4 * scan;
+    float pm = p[0];
+    int arg = 0;
+    for (int c = 1; c < 4; ++c)
+        if (p[c] > pm) { pm = p[c]; arg = c; }
+    int child = fb_child[scan];
+    int mask = lev == 0 ? 0 : R.learned_mask;
+    if (pm >= threshold) {
+        child = arg;
+        mask |= 1 << lev;
+    }
+    R.learned_mask = mask;
+    R.child[lev] = child;
+    int nb[6];
+    split_box(R.box[lev], child, 2, nb);
+    for (int i = 0; i < 6; ++i) R.box[lev + 1][i] = nb[i];
+}
+
+__global__ void k_learn_finish(const WalkArgs a, int depth, int n_scans) {
+    const int scan = blockIdx.x * blockDim.x + threadIdx.x;
+    if (scan >= n_scans) return;
+    uwb_segment_result &R = a.out[scan];
+    int roi[6];
+    const int dims[3] = {a.g.dims[0], a.g.dims[1], a.g.dims[2]};
+    expand_box(R.box[depth], a.frame_final, 2, dims, roi);
+    R.n_levels = depth;
+    R.term_level = depth;
+    R.decimation = 0;
+    R.n_samples_level0 = kLearnG * kLearnG;
+    R.n_wb = 0;
+    for (int i = 0; i < 6; ++i) R.roi[i] = roi[i];
+    const int64_t rv = (int64_t)(roi[1] - roi[0]) * (roi[3] - roi[2]) * (roi[5] - roi[4]);
+    R.voxels_evaluated = (int64_t)depth * kLearnG * kLearnG + rv;
+    R.argmax = -1;
+    R.peak = 0.0;
+}
+
+// Training inputs: the coarse DAS lattice of every box on the path to `target`
+// (the aligned boxes of side N / 2^l that contain it), and the child holding it.
+__global__ __launch_bounds__(kBlock) void k_cnn_inputs(const WalkArgs a, const uwb_peak *targets, int depth,
+                                                       uint16_t *xin, int *labels) {
+    extern __shared__ __align__(16) unsigned char dsm[];
+    double *lv = reinterpret_cast<double *>(dsm);
+    __shared__ double red[kWaves * 32];
+    __shared__ int tmp[kWaves];
+    Stage st;
+    st.lo = reinterpret_cast<int *>(dsm + sizeof(double) * a.pmax);
+    st.off = st.lo + a.stage_ant;
+    st.len = st.off + a.stage_ant;
+    st.buf = reinterpret_cast<float *>(st.len + a.stage_ant);
+    st.cap = a.stage_cap;
+    const int lev = blockIdx.x, scan = blockIdx.y;
+    const ScanConst sc = scan_const(a.ss, scan);
+    const int64_t t = targets[scan].index;
+    const int nx = a.g.dims[0];
+    const size_t k = (size_t)scan * depth + lev;
+    if (t < 0 || t >= (int64_t)nx * a.g.dims[1]) {     // no target: zero input, masked label
+        for (int p = threadIdx.x; p < kLearnG * kLearnG; p += kBlock) xin[k * kLearnG * kLearnG + p] = 0;
+        if (threadIdx.x == 0) labels[k] = -1;
+        return;
+    }
+    const int tx = (int)(t % nx), ty = (int)(t / nx);
+    const int side = a.g.dims[0] >> lev;
+    int box[6] = {(tx / side) * side, (tx / side) * side + side, (ty / side) * side, (ty / side) * side + side, 0, 1};
+    Lattice L;
+    lattice_of_box(box, side, L);
+    eval_lattice(a, sc, L, lv, st, tmp);
+    write_cnn_input(lv, red, xin + k * kLearnG * kLearnG);
+    if (threadIdx.x == 0) labels[k] = (tx >= box[0] + side / 2 ? 1 : 0) + (ty >= box[2] + side / 2 ? 2 : 0);
+}
 }  // namespace
 
 static int64_t lattice_points(int n, int step) {   // points D*k + floor(D/2) < n
@@ -593,6 +769,41 @@ int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st) {
     const unsigned nr = (unsigned)((a.roi_cap + kPointsPerBlock - 1) / kPointsPerBlock);
     hipLaunchKernelGGL(k_lattice64, dim3(nr, n_scans), dim3(kBlock), a.lds_lattice, st, a, 1);
     hipLaunchKernelGGL(k_roi_argmax, dim3(n_scans), dim3(kBlock), 0, st, a);
+    return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
+}
+
+}  // namespace uwb
+
+
+namespace uwb {
+
+int launch_learned(const WalkArgs &a, int n_scans, uwb_cnn *cnn, float threshold, uint16_t *xin, float *probs,
+                   int *fb_child, int roi_bf, hipStream_t st) {
+    WalkArgs levels = a;
+    levels.bf = UWB_DAS;     // the proposer and the fallback metric look at the coarse DAS image
+    for (int lev = 0; lev < a.depth; ++lev) {
+        hipLaunchKernelGGL(k_learn_level, dim3(n_scans), dim3(kBlock), a.lds_walk, st, levels, lev, xin, fb_child);
+        if (hipGetLastError() != hipSuccess) return UWB_EHIP;
+        const int s = uwb_cnn_forward(cnn, xin, n_scans, probs, (void *)st);
+        if (s) return s;
+        hipLaunchKernelGGL(k_learn_decide, dim3((n_scans + 255) / 256), dim3(256), 0, st, levels, lev, n_scans, probs,
+                           fb_child, threshold);
+    }
+    hipLaunchKernelGGL(k_learn_finish, dim3((n_scans + 255) / 256), dim3(256), 0, st, levels, a.depth, n_scans);
+    WalkArgs roi = a;
+    roi.bf = roi_bf;
+    const unsigned nr = (unsigned)((a.roi_cap + kPointsPerBlock - 1) / kPointsPerBlock);
+    hipLaunchKernelGGL(k_lattice64, dim3(nr, n_scans), dim3(kBlock), a.lds_lattice, st, roi, 1);
+    hipLaunchKernelGGL(k_roi_argmax, dim3(n_scans), dim3(kBlock), 0, st, roi);
+    return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
+}
+
+int launch_cnn_inputs(const WalkArgs &a, int n_scans, const uwb_peak *targets, uint16_t *xin, int *labels,
+                      hipStream_t st) {
+    WalkArgs w = a;
+    w.bf = UWB_DAS;
+    hipLaunchKernelGGL(k_cnn_inputs, dim3(a.depth, n_scans), dim3(kBlock), a.lds_walk, st, w, targets, a.depth, xin,
+                       labels);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }
 

@@ -32,6 +32,10 @@ struct WalkArgs {
 };
 
 int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st);
+int launch_learned(const WalkArgs &a, int n_scans, uwb_cnn *cnn, float threshold, uint16_t *xin, float *probs,
+                   int *fb_child, int roi_bf, hipStream_t st);
+int launch_cnn_inputs(const WalkArgs &a, int n_scans, const uwb_peak *targets, uint16_t *xin, int *labels,
+                      hipStream_t st);
 void size_walk_lds(WalkArgs *a, int n_ant);
 
 // Host planning of a walk: validates the tree against the grid and fills the

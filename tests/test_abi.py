@@ -39,7 +39,8 @@ def test_struct_layouts_match_header(tmp_path):
     a = _abi()
     structs = {"uwb_scan": a.UwbScan, "uwb_scan_batch": a.UwbScanBatch, "uwb_grid": a.UwbGrid,
                "uwb_peak": a.UwbPeak, "uwb_segment_tree": a.UwbSegmentTree, "uwb_segment_result": a.UwbSegmentResult,
-               "uwb_batch_item": a.UwbBatchItem, "uwb_batch_config": a.UwbBatchConfig}
+               "uwb_batch_item": a.UwbBatchItem, "uwb_batch_config": a.UwbBatchConfig,
+               "uwb_gen_recipe": a.UwbGenRecipe}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void) {']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')

@@ -119,3 +119,21 @@ def test_first_adam_step_moves_each_weight_against_its_gradient():
     assert np.mean(np.sign(d[big]) == -np.sign(go[big])) > 0.99
     assert np.allclose(np.abs(d[big]), 1e-3, rtol=1e-2)
     net.close()
+
+
+def test_masked_labels_drop_out_of_loss_and_gradient():
+    """A label outside 0..3 removes its sample; the mean still divides by the whole batch."""
+    flat, p = _params(5)
+    net = uwb().CNN(16, flat)
+    xg, xb, lab = _inputs(16, 6)
+    lab = lab.copy()
+    lab[[2, 7, 11]] = [-1, 4, -7]
+    keep = np.array([i not in (2, 7, 11) for i in range(16)])
+    g, loss = net.gradients(xg, torch.tensor(lab, dtype=torch.int32, device="cuda"))
+    lo, go, _ = ocnn.loss_and_grad(p, xb[keep], lab[keep], act_round=ocnn.bf16_round)
+    scale = keep.sum() / 16.0
+    assert float(loss.cpu()) == pytest.approx(lo * scale, rel=2e-3)
+    g = g.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(g - go * scale) / np.linalg.norm(go * scale)
+    assert rel <= 2e-2
+    net.close()

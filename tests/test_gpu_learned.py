@@ -1,0 +1,249 @@
+"""GPU parity of the learned walk, its training inputs and the GPU scan generator against the oracle and
+the host generator."""
+import ctypes
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from oracle import cnn as ocnn  # noqa: E402
+from oracle import learned as olearned  # noqa: E402
+from oracle.walk import _expand, _inside, _select, _split, metric_value  # noqa: E402
+import synth  # noqa: E402
+from synth import scans as sscans  # noqa: E402
+
+
+def uwb():
+    import paper_1709_02549_amd as m
+    return m
+
+
+def _net(seed=7):
+    p = ocnn.Params.init(seed)
+    rng = np.random.default_rng(seed + 100)
+    p.b = [rng.normal(0, 0.05, ocnn.CH) for _ in range(4)]
+    p.bl = 0.0
+    flat32 = p.flat().astype(np.float32)
+    return flat32, ocnn.Params.from_flat(ocnn.bf16_round(flat32))
+
+
+def _peaks(indices):
+    """A device buffer of uwb_peak records holding the given target indices."""
+    P = uwb().UwbPeak
+    arr = (P * len(indices))(*[P(int(i), 0.0, 0.0, 0) for i in indices])
+    raw = np.frombuffer(bytes(arr), dtype=np.uint8)
+    return torch.tensor(raw, device="cuda")
+
+
+# ----------------------------------------------------------------------------------
+# training inputs
+# ----------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_training_inputs_match_oracle(cfg):
+    if cfg == "c1":
+        scans = [synth.c1_scan(k) for k in range(4)]
+    else:
+        scans = [synth.c2_scan(k, n_grid=256) for k in range(3)]
+    grid = scans[0].grid
+    n = int(grid.dims[0])
+    rng = np.random.default_rng(1)
+    targets = [int(rng.integers(0, n * n)) for _ in scans]
+    targets[0] = 0
+    targets[-1] = n * n - 1
+    u = uwb()
+    b = u.DeviceBatch.from_host(scans)
+    x, lab = u.cnn_training_inputs(b, grid, _peaks(targets))
+    L = u.cnn_input_levels(grid)
+    assert L == int(np.log2(n // 32))
+    xg = x.float().cpu().numpy().astype(np.float64).reshape(len(scans), L, 32, 32)
+    lg = lab.cpu().numpy().reshape(len(scans), L)
+    for i, s in enumerate(scans):
+        xo, lo = olearned.training_inputs(s, targets[i])
+        np.testing.assert_array_equal(lg[i], lo)
+        want = ocnn.bf16_round(xo)
+        diff = np.abs(xg[i] - want)
+        # same BF16 value except where the FP64 lattices round across a BF16 boundary (one ulp)
+        assert np.all(diff <= 2.0 ** -8 * np.maximum(np.abs(want), 2.0 ** -126))
+        assert np.mean(diff == 0) >= 0.999
+
+
+def test_training_inputs_mask_missing_targets():
+    scans = [synth.c1_scan(k) for k in range(3)]
+    u = uwb()
+    b = u.DeviceBatch.from_host(scans)
+    x, lab = u.cnn_training_inputs(b, scans[0].grid, _peaks([5, -1, 128 * 128]))
+    lab = lab.cpu().numpy().reshape(3, 2)
+    assert list(lab[1]) == [-1, -1] and list(lab[2]) == [-1, -1]
+    assert np.all(lab[0] >= 0)
+    xv = x.float().cpu().numpy().reshape(3, 2, 32, 32)
+    assert np.all(xv[1:] == 0) and xv[0].max() == 1.0
+
+
+# ----------------------------------------------------------------------------------
+# learned walk
+# ----------------------------------------------------------------------------------
+
+def _check_against_oracle(s, g, tree_o, p_oracle, threshold, margin=0.02):
+    """Follow the GPU's path level by level and check every step against the oracle."""
+    dims = tuple(int(x) for x in s.grid.dims)
+    depth = len(g.child)
+    assert g.boxes[0] == (0, dims[0], 0, dims[1], 0, 1)
+    decided = 0
+    for lev in range(depth):
+        box = g.boxes[lev]
+        assert g.boxes[lev + 1] == _split(box, g.child[lev], (0, 1))
+        side = dims[0] >> lev
+        idx = olearned.box_lattice(box, side)
+        vals = oracle.image_indices(s, oracle.DAS, idx)
+        sc = []
+        for c in range(4):
+            cb = _split(box, c, (0, 1))
+            sc.append(metric_value(tree_o.metric, vals[_inside(idx, cb)], vals))
+        np.testing.assert_allclose(g.scores[lev], sc, rtol=1e-9, atol=1e-300)
+        logits, _ = ocnn.forward(p_oracle, olearned.cnn_input(vals)[None], act_round=ocnn.bf16_round)
+        pr = ocnn.softmax(logits)[0]
+        top = np.sort(pr)[::-1]
+        bit = (g.learned_mask >> lev) & 1
+        if pr.max() >= threshold + margin:
+            assert bit == 1
+            if top[0] - top[1] > margin:
+                assert g.child[lev] == int(np.argmax(pr))
+            decided += 1
+        elif pr.max() <= threshold - margin:
+            assert bit == 0
+        if bit == 0:
+            srt = np.sort(sc)[::-1]
+            if srt[0] - srt[1] > 1e-9 * abs(srt[0]):
+                assert g.child[lev] == _select(sc)
+    roi = _expand(g.boxes[depth], tree_o.frame_final, dims, (0, 1))
+    assert tuple(g.roi) == tuple(roi)
+    ridx = oracle.box_indices(roi)
+    rv = oracle.image_indices(s, tree_o.beamformer, ridx)
+    arg, peak = oracle.select_max(rv, oracle.linear_index(ridx, dims))
+    assert g.argmax == arg
+    assert g.peak == pytest.approx(peak, rel=1e-9)
+    return decided
+
+
+@pytest.mark.parametrize("bf", [0, 1])
+def test_learned_walk_matches_oracle(bf):
+    scans = [synth.c2_scan(k, n_grid=256) for k in range(6)]
+    flat, p = _net()
+    u = uwb()
+    net = u.CNN(64, flat)
+    b = u.DeviceBatch.from_host(scans)
+    tree_o = oracle.TreeParams(beamformer=bf, coarse=32, metric="max", frame_final=0.25)
+    tree_g = u.SegmentTree(beamformer=bf, coarse=32, metric="max", frame_final=0.25)
+    # a threshold near the middle of the network's confidences exercises both branches
+    probs = []
+    for s in scans[:2]:
+        vals = oracle.image_indices(s, oracle.DAS, olearned.box_lattice((0, 256, 0, 256, 0, 1), 256))
+        lg, _ = ocnn.forward(p, olearned.cnn_input(vals)[None], act_round=ocnn.bf16_round)
+        probs.append(ocnn.softmax(lg)[0].max())
+    threshold = float(np.mean(probs))
+    res = u.learned_refine_batch(b, scans[0].grid, tree_g, net, threshold, want_roi=True)
+    for s, g in zip(scans, res):
+        assert g.n_levels == g.term_level == 3
+        _check_against_oracle(s, g, tree_o, p, threshold)
+        assert g.voxels_evaluated == 3 * 1024 + (g.roi[1] - g.roi[0]) * (g.roi[3] - g.roi[2])
+    net.close()
+
+
+def test_learned_walk_untrusted_equals_metric_walk():
+    """A threshold above one never trusts the network: the GPU metric walk (DAS, g = 32), bit for bit."""
+    scans = [synth.c2_scan(k) for k in range(4)]
+    flat, _ = _net()
+    u = uwb()
+    net = u.CNN(8, flat)
+    b = u.DeviceBatch.from_host(scans)
+    for metric in ("max", "eq5_clamped"):
+        tree = u.SegmentTree(beamformer=0, coarse=32, metric=metric, frame_final=0.25)
+        a = u.learned_refine_batch(b, scans[0].grid, tree, net, 2.0)
+        m = u.segment_refine_batch(b, scans[0].grid, tree)
+        for x, y in zip(a, m):
+            assert x.learned_mask == 0
+            assert x.child == y.child and x.boxes == y.boxes and x.roi == y.roi
+            assert x.argmax == y.argmax and x.peak == y.peak
+            assert x.scores == y.scores
+    net.close()
+
+
+def test_learned_walk_constant_network():
+    """Zero convolutions: the four children score alike, p = 1/4, the first child is taken at every level."""
+    p = ocnn.Params.init(0)
+    p.w = [np.zeros_like(w) for w in p.w]
+    p.b = [np.full(ocnn.CH, 0.5) for _ in range(4)]
+    u = uwb()
+    net = u.CNN(4, p.flat().astype(np.float32))
+    scans = [synth.c1_scan(k) for k in range(2)]
+    b = u.DeviceBatch.from_host(scans)
+    tree = u.SegmentTree(beamformer=1, coarse=32, metric="max", frame_final=0.25)
+    for g in u.learned_refine_batch(b, scans[0].grid, tree, net, 0.25):
+        assert g.learned_mask == 0b11 and g.child == [0, 0]
+        assert g.roi == (0, 40, 0, 40, 0, 1)
+    net.close()
+
+
+def test_learned_walk_argument_errors():
+    u = uwb()
+    flat, _ = _net()
+    net = u.CNN(2, flat)
+    scans = [synth.c1_scan(k) for k in range(3)]
+    b = u.DeviceBatch.from_host(scans)
+    tree = u.SegmentTree(beamformer=0, coarse=32, metric="max")
+    with pytest.raises(u.UwbError):          # more scans than the network's batch
+        u.learned_refine_batch(b, scans[0].grid, tree, net, 0.5)
+    b2 = u.DeviceBatch.from_host(scans[:2])
+    with pytest.raises(u.UwbError):
+        u.learned_refine_batch(b2, scans[0].grid, u.SegmentTree(coarse=16), net, 0.5)
+    with pytest.raises(u.UwbError):
+        u.learned_refine_batch(b2, scans[0].grid, u.SegmentTree(coarse=32, term="wb"), net, 0.5)
+    net.close()
+
+
+# ----------------------------------------------------------------------------------
+# GPU generator
+# ----------------------------------------------------------------------------------
+
+def _recipe(cfg):
+    u = uwb()
+    if cfg == "c1":
+        return u.DiscRecipe(1024, 0, sscans.C0 / 3.0, sscans.DT, 0.0, sscans.REGION, 30.0, sscans.PULSE_F0,
+                            sscans.PULSE_SIGMA, sscans._PEAK["sin_gauss"], 0x01), sscans.ring_antennas(16)
+    return u.DiscRecipe(2048, 200, sscans.C0 / 3.0, sscans.DT, 0.0, sscans.REGION, 20.0, sscans.PULSE_F0,
+                        sscans.PULSE_SIGMA, sscans._PEAK["sin_gauss"], 0x02), sscans.ring_antennas(32)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_generator_matches_host_generator(cfg):
+    u = uwb()
+    rec, ant = _recipe(cfg)
+    seeds = [0, 1, 2, 12345, 2 ** 40 + 7]
+    b, tum = u.generate_disc_scans(rec, torch.tensor(ant, dtype=torch.float32, device="cuda"), seeds)
+    tr = b.traces.cpu().numpy()
+    tum = tum.cpu().numpy()
+    for i, sd in enumerate(seeds):
+        h = synth.c1_scan(sd) if cfg == "c1" else synth.c2_scan(sd)
+        np.testing.assert_allclose(tum[i], h.tumour, rtol=1e-13, atol=1e-16)
+        scale = np.abs(h.traces).max()
+        np.testing.assert_allclose(tr[i], h.traces, rtol=0, atol=2e-5 * scale)
+    assert b.params[:, 2].cpu().numpy() == pytest.approx(rec.v)
+
+
+def test_generator_argument_errors():
+    u = uwb()
+    rec, ant = _recipe("c1")
+    a = torch.tensor(ant, dtype=torch.float32, device="cuda")
+    bad = u.DiscRecipe(**{**rec.__dict__, "n_samp": 4096})
+    with pytest.raises(u.UwbError):
+        u.generate_disc_scans(bad, a, [1])
+    bad = u.DiscRecipe(**{**rec.__dict__, "n_clutter": 2000})
+    with pytest.raises(u.UwbError):
+        u.generate_disc_scans(bad, a, [1])
+    bad = u.DiscRecipe(**{**rec.__dict__, "v": float("nan")})
+    with pytest.raises(u.UwbError):
+        u.generate_disc_scans(bad, a, [1])
