@@ -10,7 +10,12 @@ processes the whole batch, inputs already resident in HBM:
 value = full-resolution voxel*antenna pairs (DAS + DMAS) per second over the
 whole step (walks and argmax included in the time).
 
-Prints one JSON line.  Only N = 1 GPU is supported.
+After the timed steps (outside them) the learned proposer is trained on GPU-
+generated scans of the same recipe (labels from full-resolution DMAS) and the
+learned walk, the metric walks and full-resolution DMAS are compared on held-out
+seeds: fraction within one voxel (L-inf) of the full-DMAS detection, and scans/s.
+
+Prints one JSON line (progress goes to stderr).  Only N = 1 GPU is supported.
 """
 from __future__ import annotations
 
@@ -62,6 +67,10 @@ def main():
     ap.add_argument("--coarse", type=int, default=16, help="walk lattice points per side (g)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--c5-train", type=int, default=200_000, help="training scans of the learned proposer")
+    ap.add_argument("--c5-eval", type=int, default=10_000, help="held-out scans for its localisation error")
+    ap.add_argument("--c5-epochs", type=float, default=1.0)
+    ap.add_argument("--no-c5", action="store_true", help="skip training / evaluating the learned proposer")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (HBM counter reference)")
     args = ap.parse_args()
@@ -204,6 +213,9 @@ def main():
         "input_generation_s": round(gen_s, 2),
     }
 
+    if not args.no_c5:
+        out["learned"] = learned_block(args, uwb, synth, dev)
+
     if not args.no_cpu:
         import oracle
         t_start = time.perf_counter()
@@ -223,6 +235,47 @@ def main():
                                "sample": f"{n_done} full 512x512 scans, DAS + direct-pairwise DMAS, FP64, "
                                          f"{el:.1f} s"}
     print(json.dumps(out), flush=True)
+
+
+def learned_block(args, uwb, synth, dev):
+    """Train the proposer (C2 recipe, 200k scans, seeds 1,000,000 + i) and evaluate on held-out seeds
+    2,000,000 + i against full-resolution DMAS."""
+    import torch
+    from paper_1709_02549_amd import proposer as P
+    from synth import scans as S
+
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    rec = uwb.DiscRecipe(2048, 200, S.C0 / 3.0, S.DT, 0.0, S.REGION, 20.0, S.PULSE_F0, S.PULSE_SIGMA,
+                         S._PEAK["sin_gauss"], 0x02)
+    ant = torch.tensor(S.ring_antennas(32), dtype=torch.float32, device=dev)
+    grid = S.square_grid(512)
+    t0 = time.time()
+    ts = P.build_training_set(rec, ant, list(range(1_000_000, 1_000_000 + args.c5_train)), grid)
+    note(f"training set: {args.c5_train} scans x {ts.levels} levels in {time.time() - t0:.1f} s")
+    net = uwb.CNN(512, P.he_init(0))
+    steps = max(1, int(args.c5_epochs * ts.x.shape[0] / 256))
+    hist, ms_step = P.train(net, ts, steps, 256, log_every=max(steps // 5, 1))
+    note(f"trained {steps} steps, {ms_step:.3f} ms/step, loss {hist[-1][1]:.4f}")
+    methods = {}
+    for m in ("max", "mean"):
+        tree = uwb.SegmentTree(beamformer=1, coarse=32, metric=m, frame_final=0.25)
+        methods[f"learned_{m}_fallback"] = P.learned_method(net, tree, grid, 0.9)
+        methods[f"das_levels_{m}_no_cnn"] = P.learned_method(net, tree, grid, 2.0)
+    for g in (8, 16, 32):
+        methods[f"walk_g{g}_max"] = P.walk_method(uwb.SegmentTree(beamformer=1, coarse=g, metric="max",
+                                                                  frame_final=0.25), grid)
+    ev = P.evaluate(rec, ant, list(range(2_000_000, 2_000_000 + args.c5_eval)), grid, methods)
+    note("held-out evaluation done")
+    n_train_samples = int(ts.x.shape[0])
+    net.close()
+    del ts
+    torch.cuda.empty_cache()
+    return {"train_scans": args.c5_train, "train_samples": n_train_samples, "steps": steps, "batch": 256,
+            "ms_per_train_step": round(ms_step, 4), "train_samples_per_s": round(256 / ms_step * 1e3, 1),
+            "final_loss": round(hist[-1][1], 5), "threshold": 0.9, "held_out_scans": args.c5_eval,
+            "methods": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in ev.items()}}
 
 
 if __name__ == "__main__":

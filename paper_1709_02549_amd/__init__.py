@@ -517,17 +517,26 @@ def cnn_input_levels(grid) -> int:
     return n
 
 
-def cnn_training_inputs(batch: DeviceBatch, grid, peaks: torch.Tensor, window: int = 11, bc=None):
+def cnn_training_inputs(batch: DeviceBatch, grid, peaks: torch.Tensor, window: int = 11, bc=None, x=None,
+                        labels=None):
     """Per-level 32 x 32 DAS lattices along the path to each scan's target voxel, and the true children.
     peaks: device buffer of uwb_peak records (e.g. from argmax_batch_async).  Returns (x [n*L,32,32] bf16,
-    labels [n*L] int32)."""
+    labels [n*L] int32), written into x / labels when given."""
     gc = grid_c(grid)
     bc = bc if bc is not None else batch.c()
     dev = batch.traces.device
     L = cnn_input_levels(grid)
     n = batch.n_scans
-    x = torch.empty((n * L, 32, 32), dtype=torch.bfloat16, device=dev)
-    lab = torch.empty(n * L, dtype=torch.int32, device=dev)
+    if x is None:
+        x = torch.empty((n * L, 32, 32), dtype=torch.bfloat16, device=dev)
+    if labels is None:
+        labels = torch.empty(n * L, dtype=torch.int32, device=dev)
+    lab = labels
+    if not (x.is_cuda and x.dtype == torch.bfloat16 and x.is_contiguous() and x.numel() >= n * L * 1024):
+        raise TypeError("x must be a contiguous CUDA bfloat16 tensor of n * levels * 1024 elements")
+    _need_cuda(lab, "labels", torch.int32)
+    if lab.numel() < n * L:
+        raise ValueError("labels smaller than n * levels")
     check(lib().uwb_cnn_training_inputs(ctypes.byref(bc), ctypes.byref(gc), window, peaks.data_ptr(), x.data_ptr(),
                                         lab.data_ptr(), _stream(dev)), "uwb_cnn_training_inputs")
     return x, lab
