@@ -116,9 +116,7 @@ static int walk_common(const ScanSet &ss, int n, const uwb_grid *finest, int32_t
     a.out = out;
     a.roi_img = roi_img;
     a.roi_img_stride = roi_img ? roi_capacity : 0;
-    const uintptr_t p = ((uintptr_t)ws + 255) & ~(uintptr_t)255;
-    a.roi64 = reinterpret_cast<double *>(p);
-    a.dec64 = a.roi64 + (size_t)n * bound;
+    assign_walk_ws(&a, ws, n);
     size_walk_lds(&a, ss.n_ant);
     return launch_walk(a, n, (hipStream_t)stream);
 }
@@ -265,10 +263,8 @@ int uwb_learned_refine_batch(const uwb_scan_batch *scans, const uwb_grid *finest
     a.out = out;
     a.roi_img = roi_img;
     a.roi_img_stride = roi_img ? roi_capacity : 0;
-    uintptr_t p = ((uintptr_t)workspace + 255) & ~(uintptr_t)255;
-    a.roi64 = reinterpret_cast<double *>(p);
-    a.dec64 = nullptr;
-    p += (size_t)n * bound * 8;
+    assign_walk_ws(&a, workspace, n);
+    uintptr_t p = (uintptr_t)(a.state + n);
     p = (p + 255) & ~(uintptr_t)255;
     uint16_t *xin = reinterpret_cast<uint16_t *>(p);
     p += (size_t)n * 32 * 32 * 2;

@@ -3,15 +3,16 @@
 // frame, final full-resolution imaging of the ROI.
 //
 // Launch sequence per batch (stream-ordered, no host round trip):
-//   [paper walk]  k_lattice64   decimated image of the whole grid      -> ws
-//   k_walk        one workgroup per scan runs every level: (per-level walk:
-//                 re-image the box on a g^d lattice in LDS), parent / child
-//                 statistics by block reductions, W/B test, selection, frame
-//                 -> uwb_segment_result (boxes, children, scores, ROI)
-//   k_lattice64   ROI at full resolution, box read from the result    -> ws, roi_img
-//   k_roi_argmax  maximal-energy voxel of the ROI                      -> result
-// Every energy here is evaluated in FP64 (the walk is latency-bound: a few
-// thousand focal points per scan), so each decision is taken in the same
+//   per-level walk, for every level l:
+//     k_grid64      g^d lattice of every active scan's box, FP64      -> ws
+//     k_pl_level    one workgroup per scan: parent / child statistics by
+//                   block reductions, W/B test, selection             -> result, state
+//   paper walk:
+//     k_grid64      decimated image of the whole grid                  -> ws
+//     k_walk_paper  one workgroup per scan runs every level on those samples
+//   k_grid64        ROI at full resolution, box read from the result   -> ws, roi_img
+//   k_roi_argmax    maximal-energy voxel of the ROI                    -> result
+// Every energy here is evaluated in FP64, so each decision is taken in the same
 // precision as a double-precision reference and does not hinge on FP32 rounding.
 #include <climits>
 #include <cmath>
@@ -123,78 +124,6 @@ __device__ double metric_value(int metric, double n, double mean, double m2, dou
         }
     }
     return 0.0;
-}
-
-// ----------------------------------------------------------------------------
-// k_lattice64: FP64 energies on a lattice (decimated image, or the ROI read
-// from the walk result).  8 lanes cooperate on a point (antennas split 8 ways).
-// ----------------------------------------------------------------------------
-constexpr int kGroup = 8;
-constexpr int kPointsPerBlock = 4 * (kBlock / kGroup);   // 128
-
-__global__ __launch_bounds__(kBlock) void k_lattice64(const WalkArgs a, int from_result) {
-    const int scan = blockIdx.y;
-    Lattice L;
-    int64_t cap;
-    double *dst;
-    float *dst32 = nullptr;
-    if (from_result) {
-        const uwb_segment_result &r = a.out[scan];
-        for (int d = 0; d < 3; ++d) { L.x0[d] = r.roi[2 * d]; L.cnt[d] = r.roi[2 * d + 1] - r.roi[2 * d]; }
-        L.step = 1;
-        cap = a.roi_cap;
-        dst = a.roi64 + (int64_t)scan * a.roi_cap;
-        if (a.roi_img) dst32 = a.roi_img + (int64_t)scan * a.roi_img_stride;
-    } else {
-        for (int d = 0; d < 3; ++d) { L.x0[d] = a.dec_x0[d]; L.cnt[d] = a.dec_cnt[d]; }
-        L.step = a.decimation;
-        cap = a.dec_count;
-        dst = a.dec64 + (int64_t)scan * a.dec_count;
-    }
-    const int64_t n = min((int64_t)L.count(), cap);
-    const int64_t p0 = (int64_t)blockIdx.x * kPointsPerBlock;
-    if (p0 >= n) return;
-    const ScanConst sc = scan_const(a.ss, scan);
-    const int gl = threadIdx.x % kGroup;
-    // stage the samples of this workgroup's points (bounding box of points p0 .. p1)
-    extern __shared__ __align__(16) unsigned char dsm[];
-    __shared__ int tmp[kWaves];
-    Stage st;
-    st.lo = reinterpret_cast<int *>(dsm);
-    st.off = st.lo + a.stage_ant;
-    st.len = st.off + a.stage_ant;
-    st.buf = reinterpret_cast<float *>(st.len + a.stage_ant);
-    st.cap = a.lattice_stage_cap;
-    int blo[3], bhi[3];
-    {
-        const int p1 = (int)min(p0 + kPointsPerBlock - 1, n - 1);
-        int f[3], l[3];
-        L.coord((int)p0, f[0], f[1], f[2]);
-        L.coord(p1, l[0], l[1], l[2]);
-        const bool same_z = f[2] == l[2], same_row = same_z && f[1] == l[1];
-        blo[0] = same_row ? f[0] : L.x0[0];
-        bhi[0] = same_row ? l[0] : L.x0[0] + L.step * (L.cnt[0] - 1);
-        blo[1] = same_z ? f[1] : L.x0[1];
-        bhi[1] = same_z ? l[1] : L.x0[1] + L.step * (L.cnt[1] - 1);
-        blo[2] = f[2];
-        bhi[2] = l[2];
-    }
-    const bool staged = stage_box(st, tmp, sc, a.ss.n_ant, a.ss.n_samp, a.window, a.g, blo, bhi);
-    for (int it = 0; it < kPointsPerBlock / (kBlock / kGroup); ++it) {
-        const int64_t p = p0 + it * (kBlock / kGroup) + threadIdx.x / kGroup;
-        const bool ok = p < n;
-        int x, y, z;
-        L.coord(ok ? (int)p : 0, x, y, z);
-        const double rx = a.g.origin[0] + x * a.g.pitch[0];
-        const double ry = a.g.origin[1] + y * a.g.pitch[1];
-        const double rz = a.g.origin[2] + z * a.g.pitch[2];
-        const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, gl, kGroup,
-                                           staged ? &st : nullptr);
-        if (ok && gl == 0) {
-            dst[p] = e;
-            if (dst32) dst32[p] = (float)e;
-        }
-    }
 }
 
 // FP64 energies of every point of lattice L into lv (LDS), trace spans staged in LDS.
@@ -323,65 +252,35 @@ __device__ LevelStats level_stats(const WalkArgs &a, const Lattice &L, const dou
 }
 
 // ----------------------------------------------------------------------------
-// k_walk: the ROI-selection loop, one workgroup per scan.
+// k_walk_paper: the ROI-selection loop of the three-phase walk, one workgroup
+// per scan, over the samples of the decimated image (computed once).
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_walk(const WalkArgs a) {
-    extern __shared__ __align__(16) unsigned char dsm[];
-    double *lv = reinterpret_cast<double *>(dsm);     // per-level lattice values (per-level walk)
+__global__ __launch_bounds__(kBlock) void k_walk_paper(const WalkArgs a) {
     __shared__ double red[kWaves * 32];
-    __shared__ int tmp[kWaves];
-    Stage st;
-    st.lo = reinterpret_cast<int *>(dsm + sizeof(double) * a.pmax);
-    st.off = st.lo + a.stage_ant;
-    st.len = st.off + a.stage_ant;
-    st.buf = reinterpret_cast<float *>(st.len + a.stage_ant);
-    st.cap = a.stage_cap;
     const int scan = blockIdx.x;
     const int tid = threadIdx.x;
     const int nact = a.g.dims[2] > 1 ? 3 : 2;
     const int nchild = 1 << nact;
     const int dims[3] = {a.g.dims[0], a.g.dims[1], a.g.dims[2]};
     uwb_segment_result &R = a.out[scan];
-    const ScanConst sc = scan_const(a.ss, scan);
-    const bool paper = a.walk == UWB_WALK_PAPER;
 
     int box[6] = {0, dims[0], 0, dims[1], 0, dims[2]};
-    int boxes[UWB_MAX_LEVELS + 1][6];
-    for (int i = 0; i < 6; ++i) boxes[0][i] = box[i];
+    if (tid == 0)
+        for (int i = 0; i < 6; ++i) R.box[0][i] = box[i];
     double prev_n = 0, prev_mean = 0, prev_m2 = 0, prevW = 0, prevB = 0;
     int n_kept = 0, made = 0, n_wb = 0;
-    int64_t nvox = 0;
 
     Lattice L;
-    const double *src;
-    if (paper) {
-        for (int d = 0; d < 3; ++d) { L.x0[d] = a.dec_x0[d]; L.cnt[d] = a.dec_cnt[d]; }
-        L.step = a.decimation;
-        src = a.dec64 + (int64_t)scan * a.dec_count;
-        nvox = L.count();
-    } else {
-        src = lv;
-    }
+    for (int d = 0; d < 3; ++d) { L.x0[d] = a.dec_x0[d]; L.cnt[d] = a.dec_cnt[d]; }
+    L.step = a.decimation;
+    const double *src = a.dec64 + (int64_t)scan * a.dec_count;
+    const int64_t nvox = L.count();
 
     for (int lev = 0; lev <= a.depth; ++lev) {
         if (lev == a.depth && a.term != UWB_TERM_WB) { n_kept = a.depth; break; }
-        int side = 0, step = 1;
-        if (!paper) {
-            // image the current box on its g^d lattice
-            side = dims[0] >> lev;
-            step = side / a.coarse;
-            for (int d = 0; d < 3; ++d) {
-                L.x0[d] = d < nact ? box[2 * d] + step / 2 : 0;
-                L.cnt[d] = d < nact ? a.coarse : 1;
-            }
-            L.step = step;
-            eval_lattice(a, sc, L, lv, st, tmp);
-            nvox += L.count();
-        }
-
         int cbox[8][6];
         double sc8[8];
-        const LevelStats ls = level_stats(a, L, src, box, nact, side, paper, red, cbox, sc8);
+        const LevelStats ls = level_stats(a, L, src, box, nact, 0, true, red, cbox, sc8);
         const double pn = ls.pn, pmean = ls.pmean, pm2 = ls.pm2;
         double cmin = INFINITY;
         for (int c = 0; c < nchild; ++c) cmin = fmin(cmin, ls.count[c]);
@@ -403,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(const WalkArgs a) {
         prev_mean = pmean;
         prev_m2 = pm2;
         if (lev == a.depth) { n_kept = a.depth; break; }
-        if (paper && cmin < kMinChildSamples) { n_kept = lev; break; }
+        if (cmin < kMinChildSamples) { n_kept = lev; break; }
         // select the child (lowest index within the tie band)
         double best = -INFINITY;
         for (int c = 0; c < nchild; ++c) best = fmax(best, sc8[c]);
@@ -411,26 +310,22 @@ __global__ __launch_bounds__(kBlock) void k_walk(const WalkArgs a) {
         int sel = 0;
         for (int c = nchild - 1; c >= 0; --c)
             if (sc8[c] >= thr) sel = c;
+        expand_box(cbox[sel], a.frame_level, nact, dims, box);
         if (tid == 0) {
             R.child[made] = sel;
             for (int c = 0; c < 8; ++c) R.score[made][c] = c < nchild ? sc8[c] : 0.0;
+            for (int i = 0; i < 6; ++i) R.box[lev + 1][i] = box[i];
         }
         ++made;
-        if (paper) expand_box(cbox[sel], a.frame_level, nact, dims, box);
-        else for (int i = 0; i < 6; ++i) box[i] = cbox[sel][i];
-        for (int i = 0; i < 6; ++i) boxes[lev + 1][i] = box[i];
-        __syncthreads();   // lv is rewritten by the next level
     }
-    int roi[6];
-    expand_box(boxes[n_kept], a.frame_final, nact, dims, roi);
     if (tid == 0) {
+        int roi[6];
+        expand_box(R.box[n_kept], a.frame_final, nact, dims, roi);
         R.n_levels = n_kept;
         R.term_level = made;
-        R.decimation = paper ? a.decimation : 0;
-        R.n_samples_level0 = paper ? a.dec_count : (int)(nact == 3 ? a.coarse * a.coarse * a.coarse : a.coarse * a.coarse);
+        R.decimation = a.decimation;
+        R.n_samples_level0 = (int)a.dec_count;
         R.n_wb = n_wb;
-        for (int l = 0; l <= made; ++l)
-            for (int i = 0; i < 6; ++i) R.box[l][i] = boxes[l][i];
         for (int i = 0; i < 6; ++i) R.roi[i] = roi[i];
         const int64_t rv = (int64_t)(roi[1] - roi[0]) * (roi[3] - roi[2]) * (roi[5] - roi[4]);
         R.voxels_evaluated = nvox + rv;
@@ -438,6 +333,113 @@ __global__ __launch_bounds__(kBlock) void k_walk(const WalkArgs a) {
         R.peak = 0.0;
         R.learned_mask = 0;
     }
+}
+
+// ----------------------------------------------------------------------------
+// Level-synchronous per-level walk: for every level, k_grid64 images the g^d
+// lattice of each active scan's box (many workgroups per scan) and k_pl_level
+// takes that level's statistics, W/B test and decision (one workgroup per
+// scan), carrying the previous level's figures in PLState.  Same decisions,
+// same arithmetic as the single-workgroup walk, far more parallelism.
+// ----------------------------------------------------------------------------
+__global__ void k_pl_init(const WalkArgs a, int n_scans) {
+    const int scan = blockIdx.x * blockDim.x + threadIdx.x;
+    if (scan >= n_scans) return;
+    PLState &S = a.state[scan];
+    S.prev_n = S.prev_mean = S.prev_m2 = S.prev_w = S.prev_b = 0.0;
+    S.nvox = 0;
+    S.active = 1;
+    S.n_kept = a.depth;
+    S.made = 0;
+    S.n_wb = 0;
+    uwb_segment_result &R = a.out[scan];
+    const int full[6] = {0, a.g.dims[0], 0, a.g.dims[1], 0, a.g.dims[2]};
+    for (int i = 0; i < 6; ++i) R.box[0][i] = full[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_pl_level(const WalkArgs a, int lev) {
+    __shared__ double red[kWaves * 32];
+    const int scan = blockIdx.x, tid = threadIdx.x;
+    PLState &S = a.state[scan];
+    if (!S.active) return;                    // uniform per workgroup
+    const int nact = a.g.dims[2] > 1 ? 3 : 2;
+    const int nchild = 1 << nact;
+    uwb_segment_result &R = a.out[scan];
+    int box[6];
+    for (int i = 0; i < 6; ++i) box[i] = R.box[lev][i];
+    const int side = a.g.dims[0] >> lev;
+    const int step = side / a.coarse;
+    Lattice L;
+    for (int d = 0; d < 3; ++d) {
+        L.x0[d] = d < nact ? box[2 * d] + step / 2 : 0;
+        L.cnt[d] = d < nact ? a.coarse : 1;
+    }
+    L.step = step;
+    const int P = L.count();
+    const double *src = a.lat64 + (int64_t)scan * P;
+    int cbox[8][6];
+    double sc8[8];
+    const LevelStats ls = level_stats(a, L, src, box, nact, side, false, red, cbox, sc8);
+    if (tid != 0) return;                      // the rest is one lane's bookkeeping
+    PLState st = S;
+    st.nvox += P;
+    bool stop = false;
+    if (a.term == UWB_TERM_WB && lev >= 1) {
+        const double pooled = (st.prev_n * st.prev_mean + ls.pn * ls.pmean) / (st.prev_n + ls.pn);
+        const double W = st.prev_m2 + ls.pm2;
+        const double B = st.prev_n * (st.prev_mean - pooled) * (st.prev_mean - pooled) +
+                         ls.pn * (ls.pmean - pooled) * (ls.pmean - pooled);
+        R.wb[st.n_wb][0] = W;
+        R.wb[st.n_wb][1] = B;
+        ++st.n_wb;
+        if (lev >= 2 && (B <= st.prev_b || W >= st.prev_w)) { st.n_kept = lev - 1; stop = true; }
+        st.prev_w = W;
+        st.prev_b = B;
+    }
+    if (!stop) {
+        st.prev_n = ls.pn;
+        st.prev_mean = ls.pmean;
+        st.prev_m2 = ls.pm2;
+        if (lev == a.depth) {
+            st.n_kept = a.depth;
+            stop = true;
+        } else {
+            double best = -INFINITY;
+            for (int c = 0; c < nchild; ++c) best = fmax(best, sc8[c]);
+            const double thr = best - kTieRel * fabs(best);
+            int sel = 0;
+            for (int c = nchild - 1; c >= 0; --c)
+                if (sc8[c] >= thr) sel = c;
+            R.child[st.made] = sel;
+            for (int c = 0; c < 8; ++c) R.score[st.made][c] = c < nchild ? sc8[c] : 0.0;
+            ++st.made;
+            for (int i = 0; i < 6; ++i) R.box[lev + 1][i] = cbox[sel][i];
+        }
+    }
+    if (stop) st.active = 0;
+    S = st;
+}
+
+__global__ void k_pl_finish(const WalkArgs a, int n_scans) {
+    const int scan = blockIdx.x * blockDim.x + threadIdx.x;
+    if (scan >= n_scans) return;
+    const int nact = a.g.dims[2] > 1 ? 3 : 2;
+    const int dims[3] = {a.g.dims[0], a.g.dims[1], a.g.dims[2]};
+    const PLState st = a.state[scan];
+    uwb_segment_result &R = a.out[scan];
+    int roi[6];
+    expand_box(R.box[st.n_kept], a.frame_final, nact, dims, roi);
+    R.n_levels = st.n_kept;
+    R.term_level = st.made;
+    R.decimation = 0;
+    R.n_samples_level0 = (int)(nact == 3 ? a.coarse * a.coarse * a.coarse : a.coarse * a.coarse);
+    R.n_wb = st.n_wb;
+    for (int i = 0; i < 6; ++i) R.roi[i] = roi[i];
+    const int64_t rv = (int64_t)(roi[1] - roi[0]) * (roi[3] - roi[2]) * (roi[5] - roi[4]);
+    R.voxels_evaluated = st.nvox + rv;
+    R.argmax = -1;
+    R.peak = 0.0;
+    R.learned_mask = 0;
 }
 
 // Maximal-energy voxel of the ROI (rule: lowest finest-grid index within the 1e-12 band).
@@ -515,31 +517,15 @@ __device__ void write_cnn_input(const double *lv, double *red, uint16_t *x) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_learn_level(const WalkArgs a, int lev, uint16_t *xin, int *fb_child) {
-    extern __shared__ __align__(16) unsigned char dsm[];
-    double *lv = reinterpret_cast<double *>(dsm);
     __shared__ double red[kWaves * 32];
-    __shared__ int tmp[kWaves];
-    Stage st;
-    st.lo = reinterpret_cast<int *>(dsm + sizeof(double) * a.pmax);
-    st.off = st.lo + a.stage_ant;
-    st.len = st.off + a.stage_ant;
-    st.buf = reinterpret_cast<float *>(st.len + a.stage_ant);
-    st.cap = a.stage_cap;
     const int scan = blockIdx.x, tid = threadIdx.x;
     uwb_segment_result &R = a.out[scan];
-    const ScanConst sc = scan_const(a.ss, scan);
     int box[6];
-    if (lev == 0) {
-        box[0] = 0; box[1] = a.g.dims[0]; box[2] = 0; box[3] = a.g.dims[1]; box[4] = 0; box[5] = 1;
-        if (tid == 0)
-            for (int i = 0; i < 6; ++i) R.box[0][i] = box[i];
-    } else {
-        for (int i = 0; i < 6; ++i) box[i] = R.box[lev][i];
-    }
+    for (int i = 0; i < 6; ++i) box[i] = R.box[lev][i];
     const int side = a.g.dims[0] >> lev;
     Lattice L;
     lattice_of_box(box, side, L);
-    eval_lattice(a, sc, L, lv, st, tmp);
+    const double *lv = a.lat64 + (int64_t)scan * kLearnG * kLearnG;
     int cbox[8][6];
     double sc8[8];
     level_stats(a, L, lv, box, 2, side, false, red, cbox, sc8);
@@ -633,6 +619,10 @@ __global__ __launch_bounds__(kBlock) void k_cnn_inputs(const WalkArgs a, const u
 }
 }  // namespace
 
+static int64_t lattice_size(const WalkArgs *a) {   // coarse^d points of a per-level lattice
+    return (int64_t)a->coarse * a->coarse * (a->g.dims[2] > 1 ? a->coarse : 1);
+}
+
 static int64_t lattice_points(int n, int step) {   // points D*k + floor(D/2) < n
     const int first = step / 2;
     return first < n ? (int64_t)(n - 1 - first) / step + 1 : 0;
@@ -690,6 +680,7 @@ int plan_walk(const GridView &g, const uwb_segment_tree *t, int n_scans, WalkArg
         if (side > n) side = n;
         bound = 1;
         for (int d = 0; d < nact; ++d) bound *= side;
+        for (int d = 0; d < 3; ++d) a->roi_side[d] = d < nact ? (int)side : 1;
     } else {
         int dec = t->decimation;
         if (dec < 0) return UWB_EINVAL;
@@ -724,12 +715,15 @@ int plan_walk(const GridView &g, const uwb_segment_tree *t, int n_scans, WalkArg
         const int lmin = (depth >= 1 && cmin >= (int64_t)kMinChildSamples) ? 1 : 0;
         // largest box side per axis at each level, then the largest ROI over reachable levels
         int64_t side[3] = {g.dims[0], g.dims[1], g.dims[2]};
+        for (int d = 0; d < 3; ++d) a->roi_side[d] = 1;
         for (int l = 0; l <= depth; ++l) {
             if (l >= lmin) {
                 int64_t v = 1;
                 for (int d = 0; d < nact; ++d) {
                     int64_t r = side[d] + 2 * (int64_t)std::floor(t->frame_final * (double)side[d]);
-                    v *= r < g.dims[d] ? r : g.dims[d];
+                    r = r < g.dims[d] ? r : g.dims[d];
+                    v *= r;
+                    if (r > a->roi_side[d]) a->roi_side[d] = (int)r;
                 }
                 bound = v > bound ? v : bound;
             }
@@ -742,8 +736,22 @@ int plan_walk(const GridView &g, const uwb_segment_tree *t, int n_scans, WalkArg
     }
     *roi_bound = bound;
     a->roi_cap = bound;
-    *ws_bytes = 256 + (size_t)n_scans * 8 * (size_t)(bound + a->dec_count) + 256;
+    const size_t lat = t->walk == UWB_WALK_PER_LEVEL ? (size_t)lattice_size(a) : 0;
+    *ws_bytes = 4 * 256 + (size_t)n_scans * (8 * ((size_t)bound + (size_t)a->dec_count + lat) + sizeof(PLState));
     return UWB_OK;
+}
+
+static uintptr_t align256(uintptr_t p) { return (p + 255) & ~(uintptr_t)255; }
+
+void assign_walk_ws(WalkArgs *a, void *ws, int n_scans) {
+    uintptr_t p = align256((uintptr_t)ws);
+    a->roi64 = reinterpret_cast<double *>(p);
+    p = align256(p + (size_t)n_scans * a->roi_cap * 8);
+    a->dec64 = reinterpret_cast<double *>(p);
+    p = align256(p + (size_t)n_scans * a->dec_count * 8);
+    a->lat64 = reinterpret_cast<double *>(p);
+    p = align256(p + (size_t)n_scans * (a->walk == UWB_WALK_PER_LEVEL ? lattice_size(a) : 0) * 8);
+    a->state = reinterpret_cast<PLState *>(p);
 }
 
 // LDS sizes of the walk kernels for M antennas (stage tables for up to kStageMaxAnt).
@@ -760,14 +768,66 @@ void size_walk_lds(WalkArgs *a, int n_ant) {
     a->lds_lattice = (size_t)12 * a->stage_ant + 4 * (size_t)a->lattice_stage_cap;
 }
 
+static Grid64Args grid_args(const WalkArgs &a, int mode) {
+    Grid64Args g;
+    g.ss = a.ss;
+    g.g = a.g;
+    g.window = a.window;
+    g.bf = a.bf;
+    g.mode = mode;
+    g.lev = 0;
+    g.coarse = a.coarse;
+    g.step = 1;
+    for (int d = 0; d < 3; ++d) { g.x0[d] = 0; g.cnt[d] = 1; }
+    g.res = a.out;
+    g.state = nullptr;
+    g.out64 = nullptr;
+    g.out_stride = 0;
+    g.out32 = nullptr;
+    g.out32_stride = 0;
+    return g;
+}
+
+// Full-resolution ROI of every scan (box read from its result) into roi64 (and roi_img).
+static int launch_roi(const WalkArgs &a, int bf, int n_scans, hipStream_t st) {
+    Grid64Args g = grid_args(a, kGridRoi);
+    g.bf = bf;
+    g.out64 = a.roi64;
+    g.out_stride = a.roi_cap;
+    g.out32 = a.roi_img;
+    g.out32_stride = a.roi_img_stride;
+    return launch_grid64(g, a.roi_side, 1, n_scans, st);
+}
+
 int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st) {
+    int rc;
     if (a.walk == UWB_WALK_PAPER) {
-        const unsigned nb = (unsigned)((a.dec_count + kPointsPerBlock - 1) / kPointsPerBlock);
-        hipLaunchKernelGGL(k_lattice64, dim3(nb, n_scans), dim3(kBlock), a.lds_lattice, st, a, 0);
+        Grid64Args g = grid_args(a, kGridFixed);
+        g.step = a.decimation;
+        for (int d = 0; d < 3; ++d) { g.x0[d] = a.dec_x0[d]; g.cnt[d] = a.dec_cnt[d]; }
+        g.out64 = a.dec64;
+        g.out_stride = a.dec_count;
+        if ((rc = launch_grid64(g, a.dec_cnt, a.decimation, n_scans, st))) return rc;
+        hipLaunchKernelGGL(k_walk_paper, dim3(n_scans), dim3(kBlock), 0, st, a);
+    } else {
+        const unsigned nb = (unsigned)((n_scans + 255) / 256);
+        hipLaunchKernelGGL(k_pl_init, dim3(nb), dim3(256), 0, st, a, n_scans);
+        const int levels = a.term == UWB_TERM_WB ? a.depth + 1 : a.depth;
+        const int nact = a.g.dims[2] > 1 ? 3 : 2;
+        const int cnt[3] = {a.coarse, a.coarse, nact == 3 ? a.coarse : 1};
+        for (int lev = 0; lev < levels; ++lev) {
+            Grid64Args g = grid_args(a, kGridBox);
+            g.lev = lev;
+            g.step = (a.g.dims[0] >> lev) / a.coarse;
+            g.state = a.state;
+            g.out64 = a.lat64;
+            g.out_stride = cnt[0] * cnt[1] * cnt[2];
+            if ((rc = launch_grid64(g, cnt, g.step, n_scans, st))) return rc;
+            hipLaunchKernelGGL(k_pl_level, dim3(n_scans), dim3(kBlock), 0, st, a, lev);
+        }
+        hipLaunchKernelGGL(k_pl_finish, dim3(nb), dim3(256), 0, st, a, n_scans);
     }
-    hipLaunchKernelGGL(k_walk, dim3(n_scans), dim3(kBlock), a.lds_walk, st, a);
-    const unsigned nr = (unsigned)((a.roi_cap + kPointsPerBlock - 1) / kPointsPerBlock);
-    hipLaunchKernelGGL(k_lattice64, dim3(nr, n_scans), dim3(kBlock), a.lds_lattice, st, a, 1);
+    if ((rc = launch_roi(a, a.bf, n_scans, st))) return rc;
     hipLaunchKernelGGL(k_roi_argmax, dim3(n_scans), dim3(kBlock), 0, st, a);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }
@@ -781,8 +841,18 @@ int launch_learned(const WalkArgs &a, int n_scans, uwb_cnn *cnn, float threshold
                    int *fb_child, int roi_bf, hipStream_t st) {
     WalkArgs levels = a;
     levels.bf = UWB_DAS;     // the proposer and the fallback metric look at the coarse DAS image
+    const unsigned nb = (unsigned)((n_scans + 255) / 256);
+    hipLaunchKernelGGL(k_pl_init, dim3(nb), dim3(256), 0, st, levels, n_scans);
+    const int cnt[3] = {kLearnG, kLearnG, 1};
+    int rc;
     for (int lev = 0; lev < a.depth; ++lev) {
-        hipLaunchKernelGGL(k_learn_level, dim3(n_scans), dim3(kBlock), a.lds_walk, st, levels, lev, xin, fb_child);
+        Grid64Args g = grid_args(levels, kGridBox);
+        g.lev = lev;
+        g.step = (a.g.dims[0] >> lev) / kLearnG;
+        g.out64 = a.lat64;
+        g.out_stride = kLearnG * kLearnG;
+        if ((rc = launch_grid64(g, cnt, g.step, n_scans, st))) return rc;
+        hipLaunchKernelGGL(k_learn_level, dim3(n_scans), dim3(kBlock), 0, st, levels, lev, xin, fb_child);
         if (hipGetLastError() != hipSuccess) return UWB_EHIP;
         const int s = uwb_cnn_forward(cnn, xin, n_scans, probs, (void *)st);
         if (s) return s;
@@ -790,11 +860,8 @@ int launch_learned(const WalkArgs &a, int n_scans, uwb_cnn *cnn, float threshold
                            fb_child, threshold);
     }
     hipLaunchKernelGGL(k_learn_finish, dim3((n_scans + 255) / 256), dim3(256), 0, st, levels, a.depth, n_scans);
-    WalkArgs roi = a;
-    roi.bf = roi_bf;
-    const unsigned nr = (unsigned)((a.roi_cap + kPointsPerBlock - 1) / kPointsPerBlock);
-    hipLaunchKernelGGL(k_lattice64, dim3(nr, n_scans), dim3(kBlock), a.lds_lattice, st, roi, 1);
-    hipLaunchKernelGGL(k_roi_argmax, dim3(n_scans), dim3(kBlock), 0, st, roi);
+    if ((rc = launch_roi(a, roi_bf, n_scans, st))) return rc;
+    hipLaunchKernelGGL(k_roi_argmax, dim3(n_scans), dim3(kBlock), 0, st, a);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }
 

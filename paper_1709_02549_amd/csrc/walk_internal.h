@@ -8,6 +8,13 @@ namespace uwb {
 constexpr int kMaxCoarsePoints = 4096;   // g^d lattice values held in LDS per level
 constexpr double kMinChildSamples = 4;   // paper walk: stop when a child holds fewer samples
 
+// Per-scan state of the level-synchronous per-level walk (workspace).
+struct PLState {
+    double prev_n, prev_mean, prev_m2, prev_w, prev_b;   // previous level's samples and W/B
+    int64_t nvox;                                       // focal points evaluated so far
+    int active, n_kept, made, n_wb;
+};
+
 struct WalkArgs {
     ScanSet ss;
     GridView g;
@@ -21,15 +28,41 @@ struct WalkArgs {
     double *dec64;             // [n_scans][dec_count]
     // ROI
     int64_t roi_cap;           // ROI bound: stride of roi64
+    int roi_side[3];           // largest ROI side per axis
     double *roi64;             // [n_scans][roi_cap]
     float *roi_img;            // optional, scan s at s * roi_img_stride
     int64_t roi_img_stride;
     uwb_segment_result *out;   // [n_scans]
+    // per-level walk: lattice values of the current level and per-scan state
+    double *lat64;             // [n_scans][coarse^d]
+    PLState *state;            // [n_scans]
     // dynamic LDS layout: [coarse values: pmax doubles][stage tables: 3 * stage_ant ints][stage: stage_cap floats]
     int pmax, stage_ant, stage_cap;
     size_t lds_walk, lds_lattice;
     int lattice_stage_cap;
 };
+
+// FP64 energies on regular lattices (walk_grid.hip).
+enum { kGridBox = 0, kGridRoi = 1, kGridFixed = 2 };
+struct Grid64Args {
+    ScanSet ss;
+    GridView g;
+    int window, bf;
+    int mode;
+    int lev, coarse, step;             // kGridBox: coarse^d lattice of res[s].box[lev], step D; kGridFixed: step
+    int x0[3], cnt[3];                 // kGridFixed: first point (finest indices) and points per axis
+    const uwb_segment_result *res;     // kGridBox, kGridRoi
+    const PLState *state;              // kGridBox: inactive scans are skipped (null: none)
+    double *out64;                     // scan s at s * out_stride, lattice order (x fastest)
+    int64_t out_stride;
+    float *out32;                      // optional FP32 copy
+    int64_t out32_stride;
+    int tiles[3], rs, chunk;           // filled by launch_grid64
+};
+int launch_grid64(Grid64Args a, const int *max_cnt, int max_step, int n_scans, hipStream_t st);
+
+// Points the workspace pointers of a planned walk into ws (size from plan_walk).
+void assign_walk_ws(WalkArgs *a, void *ws, int n_scans);
 
 int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st);
 int launch_learned(const WalkArgs &a, int n_scans, uwb_cnn *cnn, float threshold, uint16_t *xin, float *probs,
