@@ -251,6 +251,113 @@ __device__ LevelStats level_stats(const WalkArgs &a, const Lattice &L, const dou
     return out;
 }
 
+// The same statistics for one scan on one wavefront (no workgroup barriers), for
+// the per-level walk where every level's lattice lies inside its box.  Passes 2
+// and 3 run only when the metric or the W/B stop needs them.  Every lane returns
+// the result.
+template <int NACT>
+__device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, const double *src, const int *box,
+                                       int side, int cbox[8][6], double sc8[8]) {
+    constexpr int NCH = 1 << NACT;
+    const int lane = threadIdx.x & 63;
+    const int P = L.count();
+    int sbx[NCH][6];
+    const int half = side / 2;
+    const int efr = (int)floor(a.frame_level * (double)half);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        split_box(box, c, NACT, cbox[c]);
+        for (int i = 0; i < 6; ++i) sbx[c][i] = cbox[c][i];
+        for (int d = 0; d < NACT; ++d) {
+            sbx[c][2 * d] = max(box[2 * d], cbox[c][2 * d] - efr);
+            sbx[c][2 * d + 1] = min(box[2 * d + 1], cbox[c][2 * d + 1] + efr);
+        }
+    }
+    const bool need2 = a.term == UWB_TERM_WB || a.metric == UWB_VAR || a.metric == UWB_EQ5 ||
+                       a.metric == UWB_EQ5_CLAMPED;
+    const bool need3 = a.metric == UWB_EQ5 || a.metric == UWB_EQ5_CLAMPED;
+    // pass 1: counts, sums, maxima
+    double pn = 0.0, psum = 0.0, pmax = -INFINITY;
+    double cn[NCH], csum[NCH], cmx[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) { cn[c] = 0.0; csum[c] = 0.0; cmx[c] = -INFINITY; }
+    for (int p = lane; p < P; p += 64) {
+        int x, y, z;
+        L.coord(p, x, y, z);
+        if (!in_box(box, x, y, z)) continue;
+        const double v = src[p];
+        pn += 1.0; psum += v; pmax = fmax(pmax, v);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+            if (in_box(sbx[c], x, y, z)) { cn[c] += 1.0; csum[c] += v; cmx[c] = fmax(cmx[c], v); }
+    }
+    pn = wave_sum(pn);
+    psum = wave_sum(psum);
+    pmax = wave_max(pmax);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) { cn[c] = wave_sum(cn[c]); csum[c] = wave_sum(csum[c]); cmx[c] = wave_max(cmx[c]); }
+    const double pmean = psum / pn;
+    const double scale = pmax > 0.0 ? pmax : 1.0;    // Eq. (5) normalisation
+    double cmean[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) cmean[c] = csum[c] / cn[c];
+    // pass 2: raw squared deviations and normalised sums
+    double pm2 = 0.0, pnsum = 0.0, cm2[NCH], cnsum[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) { cm2[c] = 0.0; cnsum[c] = 0.0; }
+    if (need2) {
+        for (int p = lane; p < P; p += 64) {
+            int x, y, z;
+            L.coord(p, x, y, z);
+            if (!in_box(box, x, y, z)) continue;
+            const double v = src[p];
+            const double vn = pmax > 0.0 ? v / scale : v;
+            pm2 += (v - pmean) * (v - pmean);
+            pnsum += vn;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+                if (in_box(sbx[c], x, y, z)) { cm2[c] += (v - cmean[c]) * (v - cmean[c]); cnsum[c] += vn; }
+        }
+        pm2 = wave_sum(pm2);
+        pnsum = wave_sum(pnsum);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) { cm2[c] = wave_sum(cm2[c]); cnsum[c] = wave_sum(cnsum[c]); }
+    }
+    const double pnmean = pnsum / pn;
+    double cnmean[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) cnmean[c] = cnsum[c] / cn[c];
+    // pass 3: normalised squared deviations (Eq. 5 variances)
+    double pv = 0.0, cv[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) cv[c] = 0.0;
+    if (need3) {
+        for (int p = lane; p < P; p += 64) {
+            int x, y, z;
+            L.coord(p, x, y, z);
+            if (!in_box(box, x, y, z)) continue;
+            const double vn = pmax > 0.0 ? src[p] / scale : src[p];
+            pv += (vn - pnmean) * (vn - pnmean);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+                if (in_box(sbx[c], x, y, z)) cv[c] += (vn - cnmean[c]) * (vn - cnmean[c]);
+        }
+        pv = wave_sum(pv);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) cv[c] = wave_sum(cv[c]);
+    }
+    LevelStats out;
+    out.pn = pn;
+    out.pmean = pmean;
+    out.pm2 = pm2;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        out.count[c] = cn[c];
+        sc8[c] = metric_value(a.metric, cn[c], cmean[c], cm2[c], cmx[c], cnmean[c], cv[c] / cn[c], pv / pn);
+    }
+    return out;
+}
+
 // ----------------------------------------------------------------------------
 // k_walk_paper: the ROI-selection loop of the three-phase walk, one workgroup
 // per scan, over the samples of the decimated image (computed once).
@@ -357,13 +464,13 @@ __global__ void k_pl_init(const WalkArgs a, int n_scans) {
     for (int i = 0; i < 6; ++i) R.box[0][i] = full[i];
 }
 
-__global__ __launch_bounds__(kBlock) void k_pl_level(const WalkArgs a, int lev) {
-    __shared__ double red[kWaves * 32];
-    const int scan = blockIdx.x, tid = threadIdx.x;
+template <int NACT>
+__global__ __launch_bounds__(kBlock) void k_pl_level(const WalkArgs a, int lev, int n_scans) {
+    constexpr int NCH = 1 << NACT;
+    const int scan = blockIdx.x * kWaves + (threadIdx.x >> 6);   // one wavefront per scan
+    if (scan >= n_scans) return;
     PLState &S = a.state[scan];
-    if (!S.active) return;                    // uniform per workgroup
-    const int nact = a.g.dims[2] > 1 ? 3 : 2;
-    const int nchild = 1 << nact;
+    if (!S.active) return;                     // uniform per wavefront; no workgroup barriers below
     uwb_segment_result &R = a.out[scan];
     int box[6];
     for (int i = 0; i < 6; ++i) box[i] = R.box[lev][i];
@@ -371,16 +478,16 @@ __global__ __launch_bounds__(kBlock) void k_pl_level(const WalkArgs a, int lev) 
     const int step = side / a.coarse;
     Lattice L;
     for (int d = 0; d < 3; ++d) {
-        L.x0[d] = d < nact ? box[2 * d] + step / 2 : 0;
-        L.cnt[d] = d < nact ? a.coarse : 1;
+        L.x0[d] = d < NACT ? box[2 * d] + step / 2 : 0;
+        L.cnt[d] = d < NACT ? a.coarse : 1;
     }
     L.step = step;
     const int P = L.count();
     const double *src = a.lat64 + (int64_t)scan * P;
     int cbox[8][6];
     double sc8[8];
-    const LevelStats ls = level_stats(a, L, src, box, nact, side, false, red, cbox, sc8);
-    if (tid != 0) return;                      // the rest is one lane's bookkeeping
+    const LevelStats ls = wave_level_stats<NACT>(a, L, src, box, side, cbox, sc8);
+    if ((threadIdx.x & 63) != 0) return;       // the rest is one lane's bookkeeping
     PLState st = S;
     st.nvox += P;
     bool stop = false;
@@ -405,13 +512,13 @@ __global__ __launch_bounds__(kBlock) void k_pl_level(const WalkArgs a, int lev) 
             stop = true;
         } else {
             double best = -INFINITY;
-            for (int c = 0; c < nchild; ++c) best = fmax(best, sc8[c]);
+            for (int c = 0; c < NCH; ++c) best = fmax(best, sc8[c]);
             const double thr = best - kTieRel * fabs(best);
             int sel = 0;
-            for (int c = nchild - 1; c >= 0; --c)
+            for (int c = NCH - 1; c >= 0; --c)
                 if (sc8[c] >= thr) sel = c;
             R.child[st.made] = sel;
-            for (int c = 0; c < 8; ++c) R.score[st.made][c] = c < nchild ? sc8[c] : 0.0;
+            for (int c = 0; c < 8; ++c) R.score[st.made][c] = c < NCH ? sc8[c] : 0.0;
             ++st.made;
             for (int i = 0; i < 6; ++i) R.box[lev + 1][i] = cbox[sel][i];
         }
@@ -516,9 +623,11 @@ __device__ void write_cnn_input(const double *lv, double *red, uint16_t *x) {
     for (int p = threadIdx.x; p < kLearnG * kLearnG; p += kBlock) x[p] = f2bf((float)(lv[p] * inv));
 }
 
-__global__ __launch_bounds__(kBlock) void k_learn_level(const WalkArgs a, int lev, uint16_t *xin, int *fb_child) {
-    __shared__ double red[kWaves * 32];
-    const int scan = blockIdx.x, tid = threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_learn_level(const WalkArgs a, int lev, int n_scans, uint16_t *xin,
+                                                        int *fb_child) {
+    const int scan = blockIdx.x * kWaves + (threadIdx.x >> 6);   // one wavefront per scan
+    if (scan >= n_scans) return;
+    const int lane = threadIdx.x & 63;
     uwb_segment_result &R = a.out[scan];
     int box[6];
     for (int i = 0; i < 6; ++i) box[i] = R.box[lev][i];
@@ -528,18 +637,24 @@ __global__ __launch_bounds__(kBlock) void k_learn_level(const WalkArgs a, int le
     const double *lv = a.lat64 + (int64_t)scan * kLearnG * kLearnG;
     int cbox[8][6];
     double sc8[8];
-    level_stats(a, L, lv, box, 2, side, false, red, cbox, sc8);
+    wave_level_stats<2>(a, L, lv, box, side, cbox, sc8);
     double best = -INFINITY;
     for (int c = 0; c < 4; ++c) best = fmax(best, sc8[c]);
     const double thr = best - kTieRel * fabs(best);
     int sel = 0;
     for (int c = 3; c >= 0; --c)
         if (sc8[c] >= thr) sel = c;
-    if (tid == 0) {
+    if (lane == 0) {
         fb_child[scan] = sel;
         for (int c = 0; c < 8; ++c) R.score[lev][c] = c < 4 ? sc8[c] : 0.0;
     }
-    write_cnn_input(lv, red, xin + (size_t)scan * kLearnG * kLearnG);
+    // the CNN input: the lattice divided by its maximum, BF16, [y][x]
+    double m = -INFINITY;
+    for (int p = lane; p < kLearnG * kLearnG; p += 64) m = fmax(m, lv[p]);
+    m = wave_max(m);
+    const double inv = m > 0.0 ? 1.0 / m : 1.0;
+    uint16_t *x = xin + (size_t)scan * kLearnG * kLearnG;
+    for (int p = lane; p < kLearnG * kLearnG; p += 64) x[p] = f2bf((float)(lv[p] * inv));
 }
 
 __global__ void k_learn_decide(const WalkArgs a, int lev, int n_scans, const float *probs, const int *fb_child,
@@ -823,7 +938,9 @@ int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st) {
             g.out64 = a.lat64;
             g.out_stride = cnt[0] * cnt[1] * cnt[2];
             if ((rc = launch_grid64(g, cnt, g.step, n_scans, st))) return rc;
-            hipLaunchKernelGGL(k_pl_level, dim3(n_scans), dim3(kBlock), 0, st, a, lev);
+            const dim3 gw((unsigned)((n_scans + kWaves - 1) / kWaves));
+            if (nact == 3) hipLaunchKernelGGL(k_pl_level<3>, gw, dim3(kBlock), 0, st, a, lev, n_scans);
+            else hipLaunchKernelGGL(k_pl_level<2>, gw, dim3(kBlock), 0, st, a, lev, n_scans);
         }
         hipLaunchKernelGGL(k_pl_finish, dim3(nb), dim3(256), 0, st, a, n_scans);
     }
@@ -852,7 +969,8 @@ int launch_learned(const WalkArgs &a, int n_scans, uwb_cnn *cnn, float threshold
         g.out64 = a.lat64;
         g.out_stride = kLearnG * kLearnG;
         if ((rc = launch_grid64(g, cnt, g.step, n_scans, st))) return rc;
-        hipLaunchKernelGGL(k_learn_level, dim3(n_scans), dim3(kBlock), 0, st, levels, lev, xin, fb_child);
+        hipLaunchKernelGGL(k_learn_level, dim3((unsigned)((n_scans + kWaves - 1) / kWaves)), dim3(kBlock), 0, st,
+                           levels, lev, n_scans, xin, fb_child);
         if (hipGetLastError() != hipSuccess) return UWB_EHIP;
         const int s = uwb_cnn_forward(cnn, xin, n_scans, probs, (void *)st);
         if (s) return s;
