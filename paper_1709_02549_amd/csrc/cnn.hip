@@ -87,6 +87,110 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t *__restrict__ X
 }
 
 // ------------------------------------------------------------------------------
+// forward convolution 32 -> 32 channels, stride 2 (+bias, ReLU), on BF16 MFMA.
+// An implicit GEMM: rows = output pixels, columns = the 32 output channels,
+// K = 288 ordered (tap, input channel), so a 16-wide K step is one tap and 16
+// consecutive input channels.  A workgroup takes units of 128 output pixels
+// (NS samples x RB output rows); it stages their input rows into LDS as
+// [sample][row][column][channel] (channel stride padded to 40), and each wave
+// runs 18 v_mfma_f32_32x32x16_bf16 for its 32 pixels x 32 channels.  The weight
+// fragments are loaded into registers once per workgroup.  Lane layouts:
+//   A (32 x 16): lane l holds row l % 32, k = 8 (l / 32) .. + 7
+//   B (16 x 32): lane l holds column l % 32, k = 8 (l / 32) .. + 7
+//   D (32 x 32): lane l holds column l % 32, rows 8 (v / 4) + 4 (l / 32) + v % 4
+// ------------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+template <int HIN, int NS, int RB>
+__global__ __launch_bounds__(256) void k_conv_mfma(const uint16_t *__restrict__ X, const uint16_t *__restrict__ Wb,
+                                                  const uint16_t *__restrict__ Bb, uint16_t *__restrict__ Y, int n) {
+    constexpr int HO = HIN / 2;
+    constexpr int NR = 2 * RB + 1;     // staged input rows per sample (top padding row included)
+    constexpr int WP = HIN + 1;        // staged columns: input columns -1 .. HIN-1
+    constexpr int CP = 40;             // channel stride of a staged pixel (bf16 elements)
+    constexpr int UPS = HO / RB;       // units per sample
+    static_assert(NS * RB * HO == 128 && HO % RB == 0 && HO % 4 == 0, "unit shape");
+    __shared__ __align__(16) uint16_t xs[NS * NR * WP * CP];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int co = lane & 31, kh = lane >> 5;
+    bf16x8_t bfr[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int ci = 16 * h + 8 * kh + j;
+                bfr[t][h][j] = __builtin_bit_cast(__bf16, Wb[(co * C + ci) * 9 + t]);
+            }
+    const float bias = bf2f(Bb[co]);
+    // the left padding column is zero for every unit
+    for (int e = tid; e < NS * NR * C; e += 256) xs[(e / C) * WP * CP + e % C] = 0;
+    constexpr int VPR = HIN / 8;       // 16-byte vectors per input row
+    const int units = ((n + NS - 1) / NS) * UPS;
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        const int n0 = (u / UPS) * NS, r0 = (u % UPS) * RB;
+        __syncthreads();   // the previous unit's tile is consumed
+        // each task: 8 consecutive input pixels of one (sample, channel, row), one 16-byte load,
+        // transposed into the [pixel][channel] staging layout
+        for (int task = tid; task < NS * C * NR * VPR; task += 256) {
+            const int vx = task % VPR, yr = (task / VPR) % NR, ci = (task / (VPR * NR)) % C;
+            const int sm = task / (VPR * NR * C);
+            const int yi = 2 * r0 - 1 + yr, nn = n0 + sm;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (nn < n && yi >= 0 && yi < HIN)
+                v = *reinterpret_cast<const uint4 *>(X + (((size_t)nn * C + ci) * HIN + yi) * HIN + 8 * vx);
+            uint16_t *dst = xs + ((sm * NR + yr) * WP + 1 + 8 * vx) * CP + ci;
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                dst[(2 * j) * CP] = (uint16_t)(w[j] & 0xffffu);
+                dst[(2 * j + 1) * CP] = (uint16_t)(w[j] >> 16);
+            }
+        }
+        __syncthreads();
+        const int m = 32 * wave + (lane & 31);
+        const int sm = m / (RB * HO), oy = (m % (RB * HO)) / HO, ox = m % HO;
+        f32x16_t acc;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ky = t / 3, kx = t % 3;
+            const uint16_t *pa = xs + ((sm * NR + 2 * oy + ky) * WP + 2 * ox + kx) * CP + 8 * kh;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(pa + 16 * h);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[t][h], acc, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int mm = 32 * wave + 8 * g + 4 * kh;        // first of 4 consecutive pixels (same row)
+            const int s2 = mm / (RB * HO), oy2 = (mm % (RB * HO)) / HO, ox2 = mm % HO;
+            const int nn = n0 + s2;
+            if (nn < n) {
+                uint2 packed;
+                packed.x = (uint32_t)f2bf(fmaxf(acc[4 * g + 0] + bias, 0.f)) |
+                           ((uint32_t)f2bf(fmaxf(acc[4 * g + 1] + bias, 0.f)) << 16);
+                packed.y = (uint32_t)f2bf(fmaxf(acc[4 * g + 2] + bias, 0.f)) |
+                           ((uint32_t)f2bf(fmaxf(acc[4 * g + 3] + bias, 0.f)) << 16);
+                *reinterpret_cast<uint2 *>(Y + (((size_t)nn * C + co) * HO + r0 + oy2) * HO + ox2) = packed;
+            }
+        }
+    }
+}
+
+template <int HIN, int NS, int RB>
+void launch_conv_mfma(const uint16_t *X, const uint16_t *Wb, const uint16_t *Bb, uint16_t *Y, int n, hipStream_t st) {
+    constexpr int UPS = (HIN / 2) / RB;
+    const int units = ((n + NS - 1) / NS) * UPS;
+    const int grid = units < 2048 ? units : 2048;
+    hipLaunchKernelGGL((k_conv_mfma<HIN, NS, RB>), dim3(grid), dim3(256), 0, st, X, Wb, Bb, Y, n);
+}
+
+// ------------------------------------------------------------------------------
 // readout: A4 [N][32][4][4] -> logits, softmax, (loss and gradients)
 // One workgroup processes all samples in a fixed order; per-sample terms are
 // summed per lane and reduced across the block in a fixed order.
@@ -112,7 +216,8 @@ __global__ __launch_bounds__(256) void k_readout(const uint16_t *__restrict__ A4
     float dwl[C];
     for (int k = 0; k < C; ++k) dwl[k] = 0.f;
     float dbl = 0.f, lsum = 0.f;
-    for (int s = threadIdx.x; s < n; s += 256) {
+    // inference runs on many workgroups; with labels a single workgroup keeps the reductions' order fixed
+    for (int s = blockIdx.x * 256 + threadIdx.x; s < n; s += gridDim.x * 256) {
         const uint16_t *a4 = A4 + (size_t)s * C * 16;
         float feat[4][C];
         quad_feats(a4, feat);
@@ -337,12 +442,9 @@ bool dalloc(uwb_cnn *h, T **p, size_t count) {
 hipError_t forward(uwb_cnn *h, const uint16_t *x, int n, hipStream_t st) {
     hipLaunchKernelGGL((k_conv_fwd<1, 32, 1, 8>), dim3(4, n), dim3(256), 0, st, x, h->wb + OFF_W[0],
                        h->wb + OFF_B + 0 * C, h->a[1]);
-    hipLaunchKernelGGL((k_conv_fwd<C, 32, 2, 4>), dim3(4, n), dim3(256), 0, st, h->a[1], h->wb + OFF_W[1],
-                       h->wb + OFF_B + 1 * C, h->a[2]);
-    hipLaunchKernelGGL((k_conv_fwd<C, 16, 2, 8>), dim3(1, n), dim3(256), 0, st, h->a[2], h->wb + OFF_W[2],
-                       h->wb + OFF_B + 2 * C, h->a[3]);
-    hipLaunchKernelGGL((k_conv_fwd<C, 8, 2, 4>), dim3(1, n), dim3(256), 0, st, h->a[3], h->wb + OFF_W[3],
-                       h->wb + OFF_B + 3 * C, h->a[4]);
+    launch_conv_mfma<32, 1, 8>(h->a[1], h->wb + OFF_W[1], h->wb + OFF_B + 1 * C, h->a[2], n, st);
+    launch_conv_mfma<16, 2, 8>(h->a[2], h->wb + OFF_W[2], h->wb + OFF_B + 2 * C, h->a[3], n, st);
+    launch_conv_mfma<8, 8, 4>(h->a[3], h->wb + OFF_W[3], h->wb + OFF_B + 3 * C, h->a[4], n, st);
     return hipGetLastError();
 }
 
@@ -419,8 +521,8 @@ int uwb_cnn_forward(uwb_cnn *h, const uint16_t *x, int32_t n, float *probs, void
     if (n > h->max_batch) return UWB_ERANGE;
     const hipStream_t st = (hipStream_t)stream;
     if (forward(h, x, n, st) != hipSuccess) return UWB_EHIP;
-    hipLaunchKernelGGL(k_readout, dim3(1), dim3(256), 0, st, h->a[4], h->wb, (const int *)nullptr, n, probs,
-                       (float *)nullptr, (float *)nullptr, (float *)nullptr);
+    hipLaunchKernelGGL(k_readout, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, h->a[4], h->wb,
+                       (const int *)nullptr, n, probs, (float *)nullptr, (float *)nullptr, (float *)nullptr);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }
 
