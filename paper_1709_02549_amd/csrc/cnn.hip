@@ -344,19 +344,25 @@ __global__ __launch_bounds__(256) void k_conv_bwd_data(const float *__restrict__
 
 // ------------------------------------------------------------------------------
 // backward weight: dW[co][ci][k] = sum_n sum_pixels dZ[n][co][p] * X[n][ci][shifted p],
-// db[co] = sum dZ.  One workgroup per (co, ci); lanes stride over (n, pixel).
+// db[co] = sum dZ.  Two deterministic stages: workgroup (co, ci, chunk) reduces a
+// fixed chunk of the (sample, pixel) range into part[chunk][co][ci][10]; then
+// k_reduce_parts sums the chunks in order.
 // ------------------------------------------------------------------------------
+constexpr int kMaxChunks = 64;
+constexpr int kChunkElems = 4096;
+
 template <int CIN, int HIN, int S>
 __global__ __launch_bounds__(256) void k_conv_bwd_weight(const float *__restrict__ dZ, const uint16_t *__restrict__ X,
-                                                        int n, float *__restrict__ dW, float *__restrict__ db) {
+                                                        int n, int chunk_len, float *__restrict__ part) {
     constexpr int HO = HIN / S;
     __shared__ float red[256];
-    const int co = blockIdx.x, ci = blockIdx.y;
+    const int co = blockIdx.x, ci = blockIdx.y, ch = blockIdx.z;
     float acc[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) acc[k] = 0.f;
     const int total = n * HO * HO;
-    for (int e = threadIdx.x; e < total; e += 256) {
+    const int e0 = ch * chunk_len, e1 = min(total, e0 + chunk_len);
+    for (int e = e0 + threadIdx.x; e < e1; e += 256) {
         const int s = e / (HO * HO), p = e % (HO * HO);
         const int yo = p / HO, xo = p % HO;
         const float d = dZ[((size_t)s * C + co) * HO * HO + p];
@@ -375,19 +381,38 @@ __global__ __launch_bounds__(256) void k_conv_bwd_weight(const float *__restrict
         acc[9] += d;
     }
     for (int k = 0; k < 10; ++k) {
-        if (k == 9 && ci != 0) break;
         red[threadIdx.x] = acc[k];
         __syncthreads();
         for (int o = 128; o > 0; o >>= 1) {
             if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
             __syncthreads();
         }
-        if (threadIdx.x == 0) {
-            if (k < 9) dW[(co * CIN + ci) * 9 + k] = red[0];
-            else db[co] = red[0];
-        }
+        if (threadIdx.x == 0) part[(((size_t)ch * C + co) * CIN + ci) * 10 + k] = red[0];
         __syncthreads();
     }
+}
+
+__global__ void k_reduce_parts(const float *__restrict__ part, int nch, int cin, float *__restrict__ dW,
+                               float *__restrict__ db) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;   // (co, ci, k)
+    if (i >= C * cin * 10) return;
+    const int k = i % 10, ci = (i / 10) % cin, co = i / (10 * cin);
+    float sum = 0.f;
+    for (int ch = 0; ch < nch; ++ch) sum += part[(size_t)ch * C * cin * 10 + i];
+    if (k < 9) dW[(co * cin + ci) * 9 + k] = sum;
+    else if (ci == 0) db[co] = sum;
+}
+
+template <int CIN, int HIN, int S>
+void launch_bwd_weight(const float *dZ, const uint16_t *X, int n, float *part, float *dW, float *db, hipStream_t st) {
+    constexpr int HO = HIN / S;
+    const int total = n * HO * HO;
+    int nch = (total + kChunkElems - 1) / kChunkElems;
+    nch = nch < 1 ? 1 : (nch > kMaxChunks ? kMaxChunks : nch);
+    const int chunk_len = (total + nch - 1) / nch;
+    hipLaunchKernelGGL((k_conv_bwd_weight<CIN, HIN, S>), dim3(C, CIN, nch), dim3(256), 0, st, dZ, X, n, chunk_len,
+                       part);
+    hipLaunchKernelGGL(k_reduce_parts, dim3((C * CIN * 10 + 255) / 256), dim3(256), 0, st, part, nch, CIN, dW, db);
 }
 
 // Adam on FP32 masters, then the BF16 compute copy.
@@ -421,6 +446,7 @@ struct uwb_cnn {
     int64_t step = 0;
     // device buffers
     float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *loss = nullptr;
+    float *part = nullptr;   // per-chunk partial weight gradients
     uint16_t *wb = nullptr;
     uint16_t *a[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // a[0] = input copy not kept: a[1..4]
     float *dz[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};     // dZ of layers 1..4
@@ -452,20 +478,16 @@ hipError_t backward(uwb_cnn *h, const uint16_t *x, const int *labels, int n, hip
     hipLaunchKernelGGL(k_readout, dim3(1), dim3(256), 0, st, h->a[4], h->wb, labels, n, (float *)nullptr, h->dz[4],
                        h->grad, h->loss);
     // layer 4 (8 -> 4), layer 3 (16 -> 8), layer 2 (32 -> 16): weight grads, then data grads
-    hipLaunchKernelGGL((k_conv_bwd_weight<C, 8, 2>), dim3(C, C), dim3(256), 0, st, h->dz[4], h->a[3], n,
-                       h->grad + OFF_W[3], h->grad + OFF_B + 3 * C);
+    launch_bwd_weight<C, 8, 2>(h->dz[4], h->a[3], n, h->part, h->grad + OFF_W[3], h->grad + OFF_B + 3 * C, st);
     hipLaunchKernelGGL((k_conv_bwd_data<8, 2, 8>), dim3(1, n), dim3(256), 0, st, h->dz[4], h->wb + OFF_W[3], h->a[3],
                        h->dz[3]);
-    hipLaunchKernelGGL((k_conv_bwd_weight<C, 16, 2>), dim3(C, C), dim3(256), 0, st, h->dz[3], h->a[2], n,
-                       h->grad + OFF_W[2], h->grad + OFF_B + 2 * C);
+    launch_bwd_weight<C, 16, 2>(h->dz[3], h->a[2], n, h->part, h->grad + OFF_W[2], h->grad + OFF_B + 2 * C, st);
     hipLaunchKernelGGL((k_conv_bwd_data<16, 2, 4>), dim3(4, n), dim3(256), 0, st, h->dz[3], h->wb + OFF_W[2],
                        h->a[2], h->dz[2]);
-    hipLaunchKernelGGL((k_conv_bwd_weight<C, 32, 2>), dim3(C, C), dim3(256), 0, st, h->dz[2], h->a[1], n,
-                       h->grad + OFF_W[1], h->grad + OFF_B + 1 * C);
+    launch_bwd_weight<C, 32, 2>(h->dz[2], h->a[1], n, h->part, h->grad + OFF_W[1], h->grad + OFF_B + 1 * C, st);
     hipLaunchKernelGGL((k_conv_bwd_data<32, 2, 2>), dim3(16, n), dim3(256), 0, st, h->dz[2], h->wb + OFF_W[1],
                        h->a[1], h->dz[1]);
-    hipLaunchKernelGGL((k_conv_bwd_weight<1, 32, 1>), dim3(C, 1), dim3(256), 0, st, h->dz[1], x, n,
-                       h->grad + OFF_W[0], h->grad + OFF_B + 0 * C);
+    launch_bwd_weight<1, 32, 1>(h->dz[1], x, n, h->part, h->grad + OFF_W[0], h->grad + OFF_B + 0 * C, st);
     return hipGetLastError();
 }
 
@@ -489,7 +511,8 @@ int uwb_cnn_create(uwb_cnn **out, int32_t max_batch, const float *init_params) {
     h->max_batch = max_batch;
     const size_t nb = (size_t)max_batch;
     bool ok = dalloc(h, &h->theta, NPARAM) && dalloc(h, &h->m, NPARAM) && dalloc(h, &h->v, NPARAM) &&
-              dalloc(h, &h->grad, NPARAM) && dalloc(h, &h->loss, 1) && dalloc(h, &h->wb, NPARAM);
+              dalloc(h, &h->grad, NPARAM) && dalloc(h, &h->loss, 1) && dalloc(h, &h->wb, NPARAM) &&
+              dalloc(h, &h->part, (size_t)kMaxChunks * C * C * 10);
     for (int i = 1; i <= 4 && ok; ++i) {
         ok = dalloc(h, &h->a[i], nb * C * kSide[i] * kSide[i]) && dalloc(h, &h->dz[i], nb * C * kSide[i] * kSide[i]);
     }
