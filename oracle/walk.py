@@ -325,3 +325,45 @@ def walk(scan, params: TreeParams, window: int = 11, image_fn=None, n_threads: i
     arg, peak = select_max(rvals, linear_index(ridx, dims))
     rimg = rvals.reshape(roi[5] - roi[4], roi[3] - roi[2], roi[1] - roi[0])
     return WalkResult(n_kept, len(child), child, boxes, scores, wbs, roi, arg, peak, nvox, decim, samples, rimg)
+
+
+# ----------------------------------------------------------------------------------
+# the mixed-resolution image of the final-imaging phase
+# ----------------------------------------------------------------------------------
+
+def composite(scan, params: TreeParams, res: WalkResult) -> np.ndarray:
+    """Image [nz, ny, nx] with one region at full resolution and the rest at low resolution (Section III,
+    final imaging).  Every coarse sample paints its block of finest voxels, coarse levels first so that finer
+    ones overwrite them; the ROI then receives its full-resolution image.
+
+    Blocks: paper walk, lattice point k of an axis covers [D k, D (k + 1)) and the last one runs to the end of
+    the grid; per-level walk, point k of level l covers [x0 + D_l k, x0 + D_l (k + 1)) of that level's box."""
+    dims = tuple(int(x) for x in scan.grid.dims)
+    active = _active_dims(dims)
+    img = np.zeros((dims[2], dims[1], dims[0]))
+    if params.walk == "paper":
+        D = res.decimation
+        idx, vals = res.samples[0]
+        last = [(dims[d] - 1 - D // 2) // D if d in active else 0 for d in range(3)]
+        for (x, y, z), v in zip(idx, vals):
+            lo, hi = [], []
+            for d, c in enumerate((x, y, z)):
+                if d not in active:
+                    lo.append(0)
+                    hi.append(1)
+                    continue
+                k = (int(c) - D // 2) // D
+                lo.append(D * k)
+                hi.append(dims[d] if k == last[d] else D * (k + 1))
+            img[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = v
+    else:
+        g = int(params.coarse)
+        for lev, (idx, vals) in enumerate(res.samples):
+            step = (dims[0] >> lev) // g
+            for (x, y, z), v in zip(idx, vals):
+                lo = [int(c) - step // 2 if d in active else 0 for d, c in enumerate((x, y, z))]
+                hi = [lo[d] + step if d in active else 1 for d in range(3)]
+                img[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = v
+    r = res.roi
+    img[r[4]:r[5], r[2]:r[3], r[0]:r[1]] = res.roi_image
+    return img

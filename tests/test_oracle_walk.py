@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from oracle.walk import TreeParams, metric_value, within_between
+from oracle.walk import TreeParams, composite, metric_value, within_between
 from synth import Grid, Scan
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -307,3 +307,37 @@ def test_walk_rejects_bad_shapes():
         oracle.walk(_fake_scan(_grid(100)), TreeParams(coarse=8))            # 100 is not 8 * 2^L
     with pytest.raises(ValueError):
         oracle.walk(_fake_scan(_grid(64)), TreeParams(coarse=8, metric="median"))
+
+
+# ----------------------------------------------------------------------------------
+# mixed-resolution composite (final imaging)
+# ----------------------------------------------------------------------------------
+
+def test_composite_decimation_one_is_the_full_image():
+    s = synth.c1_scan(2, n_grid=32)
+    p = oracle.TreeParams(beamformer=1, walk="paper", decimation=1, frame_final=0.25)
+    res = oracle.walk(s, p)
+    np.testing.assert_array_equal(composite(s, p, res), oracle.image_grid(s, 1))
+
+
+@pytest.mark.parametrize("walk,kw", [("paper", dict(decimation=7)), ("per_level", dict(coarse=8))])
+def test_composite_samples_roi_and_blocks(walk, kw):
+    s = synth.c1_scan(5)
+    p = oracle.TreeParams(beamformer=0, walk=walk, frame_final=0.25, **kw)
+    res = oracle.walk(s, p)
+    comp = composite(s, p, res)
+    full = oracle.image_grid(s, 0)
+    r = res.roi
+    # inside the ROI: the full-resolution image
+    np.testing.assert_array_equal(comp[:, r[2]:r[3], r[0]:r[1]], full[:, r[2]:r[3], r[0]:r[1]])
+    # the finest samples outside the ROI carry their own energy
+    idx, vals = res.samples[-1] if walk == "per_level" else res.samples[0]
+    outside = ~((idx[:, 0] >= r[0]) & (idx[:, 0] < r[1]) & (idx[:, 1] >= r[2]) & (idx[:, 1] < r[3]))
+    assert outside.sum() > 0
+    np.testing.assert_array_equal(comp[idx[outside, 2], idx[outside, 1], idx[outside, 0]],
+                                  full[idx[outside, 2], idx[outside, 1], idx[outside, 0]])
+    # only the ROI varies at full resolution: outside it, at most one value per sample
+    mask = np.ones(comp.shape, bool)
+    mask[:, r[2]:r[3], r[0]:r[1]] = False
+    n_samples = sum(len(v) for _, v in res.samples)
+    assert len(np.unique(comp[mask])) <= n_samples
