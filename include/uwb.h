@@ -232,6 +232,22 @@ int uwb_segment_refine_batch(const uwb_scan_batch *scans, const uwb_grid *finest
                              void *stream);
 
 /*
+ * The walk of uwb_segment_refine_batch plus its mixed-resolution image (the
+ * final-imaging phase of Section III: one region at full resolution, the rest
+ * at low resolution).  composite: device [n_scans][nz][ny][nx] fp32.  Inside
+ * each scan's ROI it holds the full-resolution energy; elsewhere every voxel
+ * holds the coarse sample whose block contains it: the decimated lattice of the
+ * paper walk (block [D k, D k + D) per axis, the last block running to the
+ * grid's end), or, for the per-level walk, the deepest imaged level whose box
+ * contains the voxel (block [x0 + D_l k, x0 + D_l (k + 1)) of that box).
+ * Other arguments, sizes and errors as uwb_segment_refine_batch.
+ */
+int uwb_segment_composite_batch(const uwb_scan_batch *scans, const uwb_grid *finest, int32_t window,
+                                const uwb_segment_tree *tree, uwb_segment_result *out, float *roi_img,
+                                int64_t roi_capacity, void *workspace, size_t workspace_bytes, float *composite,
+                                void *stream);
+
+/*
  * Batched serving of uneven scans: many scans, each with its own antenna
  * count, trace length and grid, imaged (DAS or DMAS, as uwb_das / uwb_dmas)
  * by one persistent launch that is captured once into a HIP graph.

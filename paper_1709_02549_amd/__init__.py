@@ -313,6 +313,22 @@ def segment_refine_batch(batch, grid, tree: SegmentTree, window=11, want_roi=Fal
     return res
 
 
+def segment_composite_batch(batch: DeviceBatch, grid, tree: SegmentTree, window: int = 11):
+    """The batched walk plus its mixed-resolution image: (results, composite [n, nz, ny, nx] fp32 tensor)."""
+    gc, tc = grid_c(grid), tree.c()
+    bc = batch.c()
+    dev = batch.traces.device
+    cap = roi_capacity(grid, tree)
+    need = lib().uwb_segment_workspace_bytes(ctypes.byref(gc), ctypes.byref(tc), batch.n_scans)
+    ws = _ws.get(need, dev)
+    out = torch.empty(ctypes.sizeof(UwbSegmentResult) * batch.n_scans, dtype=torch.uint8, device=dev)
+    img = torch.empty((batch.n_scans,) + _img_shape(grid), dtype=torch.float32, device=dev)
+    check(lib().uwb_segment_composite_batch(ctypes.byref(bc), ctypes.byref(gc), window, ctypes.byref(tc),
+                                            out.data_ptr(), 0, cap, ws.data_ptr(), ws.numel(), img.data_ptr(),
+                                            _stream(dev)), "uwb_segment_composite_batch")
+    return _results(out, batch.n_scans, 4 if int(grid.dims[2]) == 1 else 8), img
+
+
 def segment_refine(scan: DeviceScan, grid, tree: SegmentTree, window=11, want_roi=False):
     gc, tc, sc = grid_c(grid), tree.c(), scan.c()
     dev = scan.traces.device

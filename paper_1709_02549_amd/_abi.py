@@ -90,6 +90,9 @@ PROTOTYPES = {
     "uwb_segment_refine_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32,
                                          ctypes.POINTER(UwbSegmentTree), c_vp, c_vp, c_i64, c_vp, ctypes.c_size_t,
                                          c_vp]),
+    "uwb_segment_composite_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32,
+                                            ctypes.POINTER(UwbSegmentTree), c_vp, c_vp, c_i64, c_vp,
+                                            ctypes.c_size_t, c_vp, c_vp]),
     "uwb_batch_plan_create": (c_i32, [ctypes.POINTER(c_vp), ctypes.POINTER(UwbBatchItem), c_i32, c_i32, c_i32,
                                       ctypes.POINTER(UwbBatchConfig)]),
     "uwb_batch_run": (c_i32, [c_vp, c_vp]),

@@ -98,7 +98,7 @@ static int argmax_common(const ScanSet &ss, int n, const uwb_grid *grid, int32_t
 
 static int walk_common(const ScanSet &ss, int n, const uwb_grid *finest, int32_t window,
                        const uwb_segment_tree *tree, uwb_segment_result *out, float *roi_img, int64_t roi_capacity,
-                       void *ws, size_t ws_bytes, void *stream) {
+                       void *ws, size_t ws_bytes, void *stream, float *composite = nullptr) {
     GridView g;
     int st = check_grid(finest, &g);
     if (st) return st;
@@ -118,7 +118,8 @@ static int walk_common(const ScanSet &ss, int n, const uwb_grid *finest, int32_t
     a.roi_img_stride = roi_img ? roi_capacity : 0;
     assign_walk_ws(&a, ws, n);
     size_walk_lds(&a, ss.n_ant);
-    return launch_walk(a, n, (hipStream_t)stream);
+    if ((st = launch_walk(a, n, (hipStream_t)stream))) return st;
+    return composite ? launch_composite(a, n, composite, (hipStream_t)stream) : UWB_OK;
 }
 
 int cnn_max_batch(const uwb_cnn *h);
@@ -227,6 +228,18 @@ int uwb_segment_refine_batch(const uwb_scan_batch *scans, const uwb_grid *finest
     return st ? st
               : walk_common(ss, scans->n_scans, finest, window, tree, out, roi_img, roi_capacity, workspace,
                             workspace_bytes, stream);
+}
+
+int uwb_segment_composite_batch(const uwb_scan_batch *scans, const uwb_grid *finest, int32_t window,
+                                const uwb_segment_tree *tree, uwb_segment_result *out, float *roi_img,
+                                int64_t roi_capacity, void *workspace, size_t workspace_bytes, float *composite,
+                                void *stream) {
+    if (!composite) return UWB_EINVAL;
+    ScanSet ss;
+    int st = batch_set(scans, &ss);
+    return st ? st
+              : walk_common(ss, scans->n_scans, finest, window, tree, out, roi_img, roi_capacity, workspace,
+                            workspace_bytes, stream, composite);
 }
 
 size_t uwb_learned_workspace_bytes(const uwb_grid *finest, const uwb_segment_tree *tree, int32_t n_scans) {

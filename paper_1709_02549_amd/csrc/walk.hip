@@ -483,7 +483,7 @@ __global__ __launch_bounds__(kBlock) void k_pl_level(const WalkArgs a, int lev, 
     }
     L.step = step;
     const int P = L.count();
-    const double *src = a.lat64 + (int64_t)scan * P;
+    const double *src = a.lat64 + (int64_t)scan * a.lat_stride + (int64_t)lev * P;
     int cbox[8][6];
     double sc8[8];
     const LevelStats ls = wave_level_stats<NACT>(a, L, src, box, side, cbox, sc8);
@@ -547,6 +547,44 @@ __global__ void k_pl_finish(const WalkArgs a, int n_scans) {
     R.argmax = -1;
     R.peak = 0.0;
     R.learned_mask = 0;
+}
+
+// ----------------------------------------------------------------------------
+// k_composite: the mixed-resolution image of the final-imaging phase (Section III):
+// full resolution inside the ROI; elsewhere every voxel takes the coarse sample
+// whose block holds it -- for the paper walk the decimated lattice (block
+// [D k, D k + D), the last block running to the grid's end), for the per-level
+// walk the deepest imaged level whose box holds the voxel.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_composite(const WalkArgs a, float *img) {
+    const int scan = blockIdx.y;
+    const int nx = a.g.dims[0], ny = a.g.dims[1], nz = a.g.dims[2];
+    const int64_t nv = (int64_t)nx * ny * nz;
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nv) return;
+    const int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((int64_t)nx * ny));
+    const uwb_segment_result &R = a.out[scan];
+    double val;
+    if (in_box(R.roi, x, y, z)) {
+        const int rnx = R.roi[1] - R.roi[0], rny = R.roi[3] - R.roi[2];
+        val = a.roi64[(int64_t)scan * a.roi_cap + ((int64_t)(z - R.roi[4]) * rny + (y - R.roi[2])) * rnx + (x - R.roi[0])];
+    } else if (a.walk == UWB_WALK_PAPER) {
+        const int D = a.decimation;
+        const int kx = min(x / D, a.dec_cnt[0] - 1), ky = min(y / D, a.dec_cnt[1] - 1);
+        const int kz = nz > 1 ? min(z / D, a.dec_cnt[2] - 1) : 0;
+        val = a.dec64[(int64_t)scan * a.dec_count + ((int64_t)kz * a.dec_cnt[1] + ky) * a.dec_cnt[0] + kx];
+    } else {
+        const int nact = nz > 1 ? 3 : 2;
+        const int P = a.coarse * a.coarse * (nact == 3 ? a.coarse : 1);
+        const int imaged = a.term == UWB_TERM_WB ? R.term_level + 1 : R.term_level;
+        int l = imaged - 1;
+        while (l > 0 && !in_box(R.box[l], x, y, z)) --l;
+        const int step = (nx >> l) / a.coarse;
+        const int kx = (x - R.box[l][0]) / step, ky = (y - R.box[l][2]) / step;
+        const int kz = nact == 3 ? (z - R.box[l][4]) / step : 0;
+        val = a.lat64[(int64_t)scan * a.lat_stride + (int64_t)l * P + ((int64_t)kz * a.coarse + ky) * a.coarse + kx];
+    }
+    img[(int64_t)scan * nv + v] = (float)val;
 }
 
 // Maximal-energy voxel of the ROI (rule: lowest finest-grid index within the 1e-12 band).
@@ -634,7 +672,7 @@ __global__ __launch_bounds__(kBlock) void k_learn_level(const WalkArgs a, int le
     const int side = a.g.dims[0] >> lev;
     Lattice L;
     lattice_of_box(box, side, L);
-    const double *lv = a.lat64 + (int64_t)scan * kLearnG * kLearnG;
+    const double *lv = a.lat64 + (int64_t)scan * a.lat_stride + (int64_t)lev * kLearnG * kLearnG;
     int cbox[8][6];
     double sc8[8];
     wave_level_stats<2>(a, L, lv, box, side, cbox, sc8);
@@ -736,6 +774,10 @@ __global__ __launch_bounds__(kBlock) void k_cnn_inputs(const WalkArgs a, const u
 
 static int64_t lattice_size(const WalkArgs *a) {   // coarse^d points of a per-level lattice
     return (int64_t)a->coarse * a->coarse * (a->g.dims[2] > 1 ? a->coarse : 1);
+}
+
+static int64_t lattice_slot(const WalkArgs *a) {   // every level's lattice of one scan
+    return a->walk == UWB_WALK_PER_LEVEL ? (int64_t)(a->depth + 1) * lattice_size(a) : 0;
 }
 
 static int64_t lattice_points(int n, int step) {   // points D*k + floor(D/2) < n
@@ -851,7 +893,7 @@ int plan_walk(const GridView &g, const uwb_segment_tree *t, int n_scans, WalkArg
     }
     *roi_bound = bound;
     a->roi_cap = bound;
-    const size_t lat = t->walk == UWB_WALK_PER_LEVEL ? (size_t)lattice_size(a) : 0;
+    const size_t lat = (size_t)lattice_slot(a);
     *ws_bytes = 4 * 256 + (size_t)n_scans * (8 * ((size_t)bound + (size_t)a->dec_count + lat) + sizeof(PLState));
     return UWB_OK;
 }
@@ -865,7 +907,8 @@ void assign_walk_ws(WalkArgs *a, void *ws, int n_scans) {
     a->dec64 = reinterpret_cast<double *>(p);
     p = align256(p + (size_t)n_scans * a->dec_count * 8);
     a->lat64 = reinterpret_cast<double *>(p);
-    p = align256(p + (size_t)n_scans * (a->walk == UWB_WALK_PER_LEVEL ? lattice_size(a) : 0) * 8);
+    a->lat_stride = lattice_slot(a);
+    p = align256(p + (size_t)n_scans * a->lat_stride * 8);
     a->state = reinterpret_cast<PLState *>(p);
 }
 
@@ -898,6 +941,7 @@ static Grid64Args grid_args(const WalkArgs &a, int mode) {
     g.state = nullptr;
     g.out64 = nullptr;
     g.out_stride = 0;
+    g.out_offset = 0;
     g.out32 = nullptr;
     g.out32_stride = 0;
     return g;
@@ -912,6 +956,14 @@ static int launch_roi(const WalkArgs &a, int bf, int n_scans, hipStream_t st) {
     g.out32 = a.roi_img;
     g.out32_stride = a.roi_img_stride;
     return launch_grid64(g, a.roi_side, 1, n_scans, st);
+}
+
+int launch_composite(const WalkArgs &a, int n_scans, float *img, hipStream_t st) {
+    const int64_t nv = (int64_t)a.g.dims[0] * a.g.dims[1] * a.g.dims[2];
+    const int64_t nb = (nv + kBlock - 1) / kBlock;
+    if (nb > 0x7fffffff || n_scans > 65535) return UWB_EUNSUPPORTED;
+    hipLaunchKernelGGL(k_composite, dim3((unsigned)nb, n_scans), dim3(kBlock), 0, st, a, img);
+    return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }
 
 int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st) {
@@ -936,7 +988,8 @@ int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st) {
             g.step = (a.g.dims[0] >> lev) / a.coarse;
             g.state = a.state;
             g.out64 = a.lat64;
-            g.out_stride = cnt[0] * cnt[1] * cnt[2];
+            g.out_stride = a.lat_stride;
+            g.out_offset = (int64_t)lev * cnt[0] * cnt[1] * cnt[2];
             if ((rc = launch_grid64(g, cnt, g.step, n_scans, st))) return rc;
             const dim3 gw((unsigned)((n_scans + kWaves - 1) / kWaves));
             if (nact == 3) hipLaunchKernelGGL(k_pl_level<3>, gw, dim3(kBlock), 0, st, a, lev, n_scans);
@@ -967,7 +1020,8 @@ int launch_learned(const WalkArgs &a, int n_scans, uwb_cnn *cnn, float threshold
         g.lev = lev;
         g.step = (a.g.dims[0] >> lev) / kLearnG;
         g.out64 = a.lat64;
-        g.out_stride = kLearnG * kLearnG;
+        g.out_stride = a.lat_stride;
+        g.out_offset = (int64_t)lev * kLearnG * kLearnG;
         if ((rc = launch_grid64(g, cnt, g.step, n_scans, st))) return rc;
         hipLaunchKernelGGL(k_learn_level, dim3((unsigned)((n_scans + kWaves - 1) / kWaves)), dim3(kBlock), 0, st,
                            levels, lev, n_scans, xin, fb_child);

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_grid64(const Grid64Args a) {
         L.step = a.step;
     }
     // a lattice larger than its output slot (never, for a planned walk) is not written
-    if ((int64_t)L.cnt[0] * L.cnt[1] * L.cnt[2] > a.out_stride) return;
+    if ((int64_t)L.cnt[0] * L.cnt[1] * L.cnt[2] + a.out_offset > a.out_stride) return;
     const int t = blockIdx.x;
     const int tx0 = (t % a.tiles[0]) * TS::X;
     const int ty0 = ((t / a.tiles[0]) % a.tiles[1]) * TS::Y;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_grid64(const Grid64Args a) {
     if (!fits) e = __builtin_nan("");
     if (valid) {
         const int64_t p = ((int64_t)kz * L.cnt[1] + ky) * L.cnt[0] + kx;
-        a.out64[(int64_t)scan * a.out_stride + p] = e;
+        a.out64[(int64_t)scan * a.out_stride + a.out_offset + p] = e;
         if (a.out32) a.out32[(int64_t)scan * a.out32_stride + p] = (float)e;
     }
 }

@@ -34,7 +34,8 @@ struct WalkArgs {
     int64_t roi_img_stride;
     uwb_segment_result *out;   // [n_scans]
     // per-level walk: lattice values of the current level and per-scan state
-    double *lat64;             // [n_scans][coarse^d]
+    double *lat64;             // [n_scans][depth + 1][coarse^d]: every level's lattice is kept
+    int64_t lat_stride;        // doubles per scan in lat64
     PLState *state;            // [n_scans]
     // dynamic LDS layout: [coarse values: pmax doubles][stage tables: 3 * stage_ant ints][stage: stage_cap floats]
     int pmax, stage_ant, stage_cap;
@@ -53,8 +54,8 @@ struct Grid64Args {
     int x0[3], cnt[3];                 // kGridFixed: first point (finest indices) and points per axis
     const uwb_segment_result *res;     // kGridBox, kGridRoi
     const PLState *state;              // kGridBox: inactive scans are skipped (null: none)
-    double *out64;                     // scan s at s * out_stride, lattice order (x fastest)
-    int64_t out_stride;
+    double *out64;                     // scan s at s * out_stride + out_offset, lattice order (x fastest)
+    int64_t out_stride, out_offset;
     float *out32;                      // optional FP32 copy
     int64_t out32_stride;
     int tiles[3], rs, chunk;           // filled by launch_grid64
@@ -65,6 +66,8 @@ int launch_grid64(Grid64Args a, const int *max_cnt, int max_step, int n_scans, h
 void assign_walk_ws(WalkArgs *a, void *ws, int n_scans);
 
 int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st);
+// Mixed-resolution image [n_scans][nz][ny][nx] from a finished walk's results and workspace.
+int launch_composite(const WalkArgs &a, int n_scans, float *img, hipStream_t st);
 int launch_learned(const WalkArgs &a, int n_scans, uwb_cnn *cnn, float threshold, uint16_t *xin, float *probs,
                    int *fb_child, int roi_bf, hipStream_t st);
 int launch_cnn_inputs(const WalkArgs &a, int n_scans, const uwb_peak *targets, uint16_t *xin, int *labels,

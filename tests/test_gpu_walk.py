@@ -113,3 +113,35 @@ def test_walk_deterministic():
     b = u.segment_refine(ds, s.grid, gp, want_roi=True)
     assert a.child == b.child and a.scores == b.scores and a.argmax == b.argmax
     assert np.array_equal(a.roi_image, b.roi_image)
+
+
+# ----------------------------------------------------------------------------------
+# mixed-resolution composite (final imaging)
+# ----------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("walk,kw", [("paper", dict(min_tumour=0.01)), ("paper", dict(decimation=5, frame_level=0.25)),
+                                     ("per_level", dict(coarse=8)), ("per_level", dict(coarse=16, term="wb"))])
+@pytest.mark.parametrize("bf", [0, 1])
+def test_composite_matches_oracle(walk, kw, bf):
+    from oracle.walk import composite
+    scans = [synth.c1_scan(k) for k in range(3)]
+    u = uwb()
+    op, gp = _params(beamformer=bf, walk=walk, frame_final=0.25, **kw)
+    res, img = u.segment_composite_batch(u.DeviceBatch.from_host(scans), scans[0].grid, gp)
+    img = img.cpu().numpy()
+    for i, s in enumerate(scans):
+        o = oracle.walk(s, op)
+        assert res[i].child == o.child and tuple(res[i].roi) == tuple(o.roi)
+        want = composite(s, op, o)
+        np.testing.assert_allclose(img[i], want, rtol=1e-6, atol=1e-30)
+
+
+def test_composite_c3_octree():
+    from oracle.walk import composite
+    s = synth.c3_scan(0, n_grid=64)
+    u = uwb()
+    op, gp = _params(beamformer=0, coarse=8, frame_final=0.25)
+    res, img = u.segment_composite_batch(u.DeviceBatch.from_host([s]), s.grid, gp)
+    o = oracle.walk(s, op)
+    assert res[0].child == o.child
+    np.testing.assert_allclose(img.cpu().numpy()[0], composite(s, op, o), rtol=1e-6, atol=1e-30)
