@@ -367,3 +367,23 @@ def composite(scan, params: TreeParams, res: WalkResult) -> np.ndarray:
     r = res.roi
     img[r[4]:r[5], r[2]:r[3], r[0]:r[1]] = res.roi_image
     return img
+
+
+# ----------------------------------------------------------------------------------
+# the two-decimation check for scans that may hold no tumour
+# ----------------------------------------------------------------------------------
+
+def rois_intersect(a, b) -> bool:
+    """Whether two boxes [x0, x1, y0, y1, z0, z1) share a voxel."""
+    return all(max(a[2 * d], b[2 * d]) < min(a[2 * d + 1], b[2 * d + 1]) for d in range(3))
+
+
+def tumour_check(scan, params: TreeParams, d1: int, d2: int, window: int = 11, image_fn=None):
+    """Section IV, last paragraph: run the three-phase walk with two decimation factors; matching ROIs confirm the
+    detection, ROIs in different places mean the walks followed artifacts (no tumour).  "Same location" is read
+    as: the two final ROI boxes intersect.  Returns (agree, result with d1, result with d2)."""
+    if params.walk != "paper" or d1 < 1 or d2 < 1 or d1 == d2:
+        raise ValueError("the check runs the paper walk with two different decimation factors")
+    r1 = walk(scan, dataclasses.replace(params, decimation=int(d1)), window, image_fn)
+    r2 = walk(scan, dataclasses.replace(params, decimation=int(d2)), window, image_fn)
+    return rois_intersect(r1.roi, r2.roi), r1, r2

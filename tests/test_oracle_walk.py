@@ -341,3 +341,51 @@ def test_composite_samples_roi_and_blocks(walk, kw):
     mask[:, r[2]:r[3], r[0]:r[1]] = False
     n_samples = sum(len(v) for _, v in res.samples)
     assert len(np.unique(comp[mask])) <= n_samples
+
+
+# ----------------------------------------------------------------------------------
+# the two-decimation check (no-tumour test)
+# ----------------------------------------------------------------------------------
+
+def test_rois_intersect_by_hand():
+    from oracle.walk import rois_intersect
+    assert rois_intersect((0, 10, 0, 10, 0, 1), (9, 20, 5, 6, 0, 1))
+    assert not rois_intersect((0, 10, 0, 10, 0, 1), (10, 20, 0, 10, 0, 1))    # touching is not sharing
+    assert not rois_intersect((0, 10, 0, 10, 0, 1), (0, 10, 10, 12, 0, 1))
+    assert not rois_intersect((0, 4, 0, 4, 0, 2), (0, 4, 0, 4, 2, 3))
+
+
+def _landscape(spike, bump, n):
+    """Energy: a broad bump at `bump` (peak 1) plus a one-voxel spike of 10 at `spike`."""
+    def fn(idx):
+        idx = np.asarray(idx, dtype=np.float64)
+        d2 = (idx[:, 0] - bump[0]) ** 2 + (idx[:, 1] - bump[1]) ** 2
+        v = np.exp(-d2 / (2 * (n / 8.0) ** 2))
+        hit = (idx[:, 0] == spike[0]) & (idx[:, 1] == spike[1])
+        return v + 10.0 * hit
+    return fn
+
+
+def test_tumour_check_on_constructed_landscapes():
+    from oracle.walk import tumour_check
+    s = synth.c1_scan(0, n_grid=128)
+    p = TreeParams(walk="paper", metric="max", frame_final=0.1)
+    # the spike sits on the D = 7 lattice (7 k + 3) but on no D = 5 lattice point (5 k + 2): the D = 7 walk
+    # goes to the spike, the D = 5 walk to the bump far away -> the ROIs differ: artifacts
+    spike, bump = (7 * 3 + 3, 7 * 3 + 3), (100, 100)
+    assert (spike[0] - 2) % 5 != 0
+    agree, r1, r2 = tumour_check(s, p, 7, 5, image_fn=_landscape(spike, bump, 128))
+    assert r1.roi[0] <= spike[0] < r1.roi[1] and r2.roi[0] <= bump[0] < r2.roi[1]
+    assert not agree
+    # a broad bump alone: both walks find it -> confirmed
+    agree, r1, r2 = tumour_check(s, p, 7, 5, image_fn=_landscape((-50, -50), bump, 128))
+    assert agree
+    with pytest.raises(ValueError):
+        tumour_check(s, p, 5, 5)
+
+
+def test_tumour_check_confirms_a_real_scatterer():
+    from oracle.walk import tumour_check
+    s = synth.c1_scan(3, noiseless=True)
+    agree, r1, r2 = tumour_check(s, TreeParams(beamformer=1, walk="paper", metric="max", frame_final=0.25), 9, 5)
+    assert agree
