@@ -232,6 +232,23 @@ int uwb_segment_refine_batch(const uwb_scan_batch *scans, const uwb_grid *finest
                              void *stream);
 
 /*
+ * The check the paper proposes for scans that may hold no tumour (Section IV,
+ * last paragraph): run the three-phase walk (tree->walk must be
+ * UWB_WALK_PAPER) with two different decimation factors d1 != d2 (>= 1); the
+ * detection is confirmed when the two final ROIs point to the same place,
+ * read here as: the two ROI boxes intersect.
+ *   out      device uwb_segment_result [2][n_scans]: the d1 walks, then the d2 walks
+ *   agree    device int32 [n_scans]: 1 = ROIs intersect (confirmed), 0 = they do not
+ *            (the walks followed artifacts: no tumour)
+ * Workspace: uwb_tumour_check_workspace_bytes (0 for invalid arguments).
+ */
+size_t uwb_tumour_check_workspace_bytes(const uwb_grid *finest, const uwb_segment_tree *tree, int32_t d1, int32_t d2,
+                                        int32_t n_scans);
+int uwb_tumour_check_batch(const uwb_scan_batch *scans, const uwb_grid *finest, int32_t window,
+                           const uwb_segment_tree *tree, int32_t d1, int32_t d2, uwb_segment_result *out,
+                           int32_t *agree, void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * The walk of uwb_segment_refine_batch plus its mixed-resolution image (the
  * final-imaging phase of Section III: one region at full resolution, the rest
  * at low resolution).  composite: device [n_scans][nz][ny][nx] fp32.  Inside

@@ -329,6 +329,26 @@ def segment_composite_batch(batch: DeviceBatch, grid, tree: SegmentTree, window:
     return _results(out, batch.n_scans, 4 if int(grid.dims[2]) == 1 else 8), img
 
 
+def tumour_check_batch(batch: DeviceBatch, grid, tree: SegmentTree, d1: int, d2: int, window: int = 11):
+    """The two-decimation check of the three-phase walk: (agree [n] bool array, results with d1, results with d2)."""
+    gc, tc = grid_c(grid), tree.c()
+    bc = batch.c()
+    dev = batch.traces.device
+    n = batch.n_scans
+    need = lib().uwb_tumour_check_workspace_bytes(ctypes.byref(gc), ctypes.byref(tc), int(d1), int(d2), n)
+    if need == 0:
+        raise UwbError(-1, "uwb_tumour_check_workspace_bytes")
+    ws = _ws.get(need, dev)
+    out = torch.empty(ctypes.sizeof(UwbSegmentResult) * 2 * n, dtype=torch.uint8, device=dev)
+    agree = torch.empty(n, dtype=torch.int32, device=dev)
+    check(lib().uwb_tumour_check_batch(ctypes.byref(bc), ctypes.byref(gc), window, ctypes.byref(tc), int(d1), int(d2),
+                                       out.data_ptr(), agree.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev)),
+          "uwb_tumour_check_batch")
+    nc = 4 if int(grid.dims[2]) == 1 else 8
+    res = _results(out, 2 * n, nc)
+    return agree.cpu().numpy().astype(bool), res[:n], res[n:]
+
+
 def segment_refine(scan: DeviceScan, grid, tree: SegmentTree, window=11, want_roi=False):
     gc, tc, sc = grid_c(grid), tree.c(), scan.c()
     dev = scan.traces.device

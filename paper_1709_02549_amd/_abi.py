@@ -93,6 +93,11 @@ PROTOTYPES = {
     "uwb_segment_composite_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32,
                                             ctypes.POINTER(UwbSegmentTree), c_vp, c_vp, c_i64, c_vp,
                                             ctypes.c_size_t, c_vp, c_vp]),
+    "uwb_tumour_check_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(UwbGrid), ctypes.POINTER(UwbSegmentTree),
+                                                           c_i32, c_i32, c_i32]),
+    "uwb_tumour_check_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32,
+                                       ctypes.POINTER(UwbSegmentTree), c_i32, c_i32, c_vp, c_vp, c_vp,
+                                       ctypes.c_size_t, c_vp]),
     "uwb_batch_plan_create": (c_i32, [ctypes.POINTER(c_vp), ctypes.POINTER(UwbBatchItem), c_i32, c_i32, c_i32,
                                       ctypes.POINTER(UwbBatchConfig)]),
     "uwb_batch_run": (c_i32, [c_vp, c_vp]),

@@ -242,6 +242,41 @@ int uwb_segment_composite_batch(const uwb_scan_batch *scans, const uwb_grid *fin
                             workspace_bytes, stream, composite);
 }
 
+size_t uwb_tumour_check_workspace_bytes(const uwb_grid *finest, const uwb_segment_tree *tree, int32_t d1, int32_t d2,
+                                        int32_t n_scans) {
+    if (!tree || tree->walk != UWB_WALK_PAPER) return 0;
+    size_t need = 0;
+    for (int32_t d : {d1, d2}) {
+        uwb_segment_tree t = *tree;
+        t.decimation = d;
+        const size_t b = uwb_segment_workspace_bytes(finest, &t, n_scans);
+        if (b == 0) return 0;
+        need = b > need ? b : need;
+    }
+    return need;
+}
+
+int uwb_tumour_check_batch(const uwb_scan_batch *scans, const uwb_grid *finest, int32_t window,
+                           const uwb_segment_tree *tree, int32_t d1, int32_t d2, uwb_segment_result *out,
+                           int32_t *agree, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!tree || !out || !agree) return UWB_EINVAL;
+    if (tree->walk != UWB_WALK_PAPER) return UWB_EUNSUPPORTED;
+    if (d1 < 1 || d2 < 1 || d1 == d2) return UWB_EINVAL;
+    ScanSet ss;
+    int st = batch_set(scans, &ss);
+    if (st) return st;
+    const int n = scans->n_scans;
+    if (workspace_bytes < uwb_tumour_check_workspace_bytes(finest, tree, d1, d2, n)) return UWB_ERANGE;
+    for (int k = 0; k < 2; ++k) {
+        uwb_segment_tree t = *tree;
+        t.decimation = k == 0 ? d1 : d2;
+        if ((st = walk_common(ss, n, finest, window, &t, out + (size_t)k * n, nullptr, 0, workspace, workspace_bytes,
+                              stream)))
+            return st;
+    }
+    return launch_roi_overlap(out, out + n, agree, n, (hipStream_t)stream);
+}
+
 size_t uwb_learned_workspace_bytes(const uwb_grid *finest, const uwb_segment_tree *tree, int32_t n_scans) {
     GridView g;
     if (check_grid(finest, &g) || n_scans < 1) return 0;

@@ -958,6 +958,22 @@ static int launch_roi(const WalkArgs &a, int bf, int n_scans, hipStream_t st) {
     return launch_grid64(g, a.roi_side, 1, n_scans, st);
 }
 
+// Two walks of the same scans agree when their final ROIs intersect.
+__global__ void k_roi_overlap(const uwb_segment_result *ra, const uwb_segment_result *rb, int32_t *agree, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool ov = true;
+    for (int d = 0; d < 3; ++d)
+        ov = ov && max(ra[i].roi[2 * d], rb[i].roi[2 * d]) < min(ra[i].roi[2 * d + 1], rb[i].roi[2 * d + 1]);
+    agree[i] = ov ? 1 : 0;
+}
+
+int launch_roi_overlap(const uwb_segment_result *ra, const uwb_segment_result *rb, int32_t *agree, int n,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_roi_overlap, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ra, rb, agree, n);
+    return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
+}
+
 int launch_composite(const WalkArgs &a, int n_scans, float *img, hipStream_t st) {
     const int64_t nv = (int64_t)a.g.dims[0] * a.g.dims[1] * a.g.dims[2];
     const int64_t nb = (nv + kBlock - 1) / kBlock;

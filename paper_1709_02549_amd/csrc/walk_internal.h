@@ -66,6 +66,9 @@ int launch_grid64(Grid64Args a, const int *max_cnt, int max_step, int n_scans, h
 void assign_walk_ws(WalkArgs *a, void *ws, int n_scans);
 
 int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st);
+// agree[i] = 1 when the final ROIs of ra[i] and rb[i] intersect.
+int launch_roi_overlap(const uwb_segment_result *ra, const uwb_segment_result *rb, int32_t *agree, int n,
+                       hipStream_t st);
 // Mixed-resolution image [n_scans][nz][ny][nx] from a finished walk's results and workspace.
 int launch_composite(const WalkArgs &a, int n_scans, float *img, hipStream_t st);
 int launch_learned(const WalkArgs &a, int n_scans, uwb_cnn *cnn, float threshold, uint16_t *xin, float *probs,

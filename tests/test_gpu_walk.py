@@ -145,3 +145,37 @@ def test_composite_c3_octree():
     o = oracle.walk(s, op)
     assert res[0].child == o.child
     np.testing.assert_allclose(img.cpu().numpy()[0], composite(s, op, o), rtol=1e-6, atol=1e-30)
+
+
+# ----------------------------------------------------------------------------------
+# the two-decimation check (no-tumour test)
+# ----------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("bf", [0, 1])
+def test_tumour_check_matches_oracle(bf):
+    """Scans with a tumour (C1) and without (white noise only): same verdict and walks as the oracle."""
+    from oracle.walk import tumour_check
+    grid = synth.square_grid(128)
+    scans = [synth.c1_scan(k) for k in range(4)] + [synth.random_scan(k, 16, 1024, grid) for k in range(4)]
+    u = uwb()
+    op, gp = _params(beamformer=bf, walk="paper", metric="max", frame_final=0.25)
+    agree, ra, rb = u.tumour_check_batch(u.DeviceBatch.from_host(scans), grid, gp, 9, 5)
+    verdicts = []
+    for i, s in enumerate(scans):
+        ok, o1, o2 = tumour_check(s, op, 9, 5)
+        assert ra[i].child == o1.child and rb[i].child == o2.child
+        assert tuple(ra[i].roi) == tuple(o1.roi) and tuple(rb[i].roi) == tuple(o2.roi)
+        assert ra[i].argmax == o1.argmax and rb[i].argmax == o2.argmax
+        assert bool(agree[i]) == ok
+        verdicts.append(ok)
+    assert all(verdicts[:4])          # a tumour: confirmed
+
+
+def test_tumour_check_argument_errors():
+    u = uwb()
+    scans = [synth.c1_scan(0)]
+    b = u.DeviceBatch.from_host(scans)
+    with pytest.raises(u.UwbError):
+        u.tumour_check_batch(b, scans[0].grid, u.SegmentTree(walk="paper"), 5, 5)
+    with pytest.raises(u.UwbError):
+        u.tumour_check_batch(b, scans[0].grid, u.SegmentTree(walk="per_level"), 5, 7)
