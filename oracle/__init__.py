@@ -29,7 +29,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             build()
         _lib = ctypes.CDLL(LIB_PATH)
-        for name in ("oracle_image_indices", "oracle_image_points"):
+        for name in ("oracle_image_indices", "oracle_image_points", "oracle_image_indices_ms"):
             getattr(_lib, name).restype = ctypes.c_int
     return _lib
 
@@ -43,14 +43,19 @@ DAS, DMAS = 0, 1
 
 def image_indices(scan, beamformer: int, idx, window: int = 11, n_threads: int = 0,
                   return_threads: bool = False):
-    """Energies at voxel indices idx [n, 3] (ix, iy, iz) of scan.grid, fp64."""
+    """Energies at voxel indices idx [n, 3] (ix, iy, iz) of scan.grid, fp64.  A multistatic scan
+    (``scan.multistatic``: M antennas, M^2 traces, channel i*M + j) uses Eq. (2) / Eq. (4)."""
     idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int32).reshape(-1, 3))
     ant = np.ascontiguousarray(scan.ant_pos, dtype=np.float32)
     tr = np.ascontiguousarray(scan.traces, dtype=np.float32)
     origin = np.ascontiguousarray(scan.grid.origin, dtype=np.float64)
     pitch = np.ascontiguousarray(scan.grid.pitch, dtype=np.float64)
     out = np.zeros(idx.shape[0], dtype=np.float64)
-    used = lib().oracle_image_indices(
+    ms = bool(getattr(scan, "multistatic", False))
+    if ms and tr.shape[0] != ant.shape[0] ** 2:
+        raise ValueError("a multistatic scan holds M^2 traces")
+    fn = lib().oracle_image_indices_ms if ms else lib().oracle_image_indices
+    used = fn(
         ctypes.c_int(beamformer), ctypes.c_int(ant.shape[0]), ctypes.c_int(tr.shape[1]), _ptr(ant),
         _ptr(tr), ctypes.c_double(scan.dt), ctypes.c_double(scan.t0), ctypes.c_double(scan.v),
         ctypes.c_int(window), _ptr(origin), _ptr(pitch), ctypes.c_long(idx.shape[0]), _ptr(idx),

@@ -151,3 +151,87 @@ int oracle_image_points(int beamformer, int n_ant, int n_samp, const float *ant_
     }
     return used;
 }
+
+/*
+ * Multistatic imaging (Eq. (2) and Eq. (4)): every antenna transmits and every
+ * antenna receives, giving M^2 channels Y_ij, traces[(i*M + j)*n_samp ...].
+ *   delay      Eq. (2): the transmitter-to-point plus point-to-receiver path,
+ *              n_ij(r) = ((|r - a_i| + |r - a_j|) / v - t0) / dt
+ *              (with i = j this is the monostatic delay above).
+ *   DAS        Eq. (4): I(r) = sum_k ( sum_i sum_j s_ij(r,k) )^2, all M^2 channels.
+ *   DMAS       Section II-B applied to the M^2 channel signals: the sum over every
+ *              pair of distinct channels of the product of their aligned samples,
+ *              then the windowed energy (literal double loop over channel pairs).
+ */
+static double path_delay(const double r[3], const float *a_tx, const float *a_rx, double v, double dt,
+                         double t0)
+{
+    double d_tx = 0.0, d_rx = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double u = r[d] - (double)a_tx[d];
+        double w = r[d] - (double)a_rx[d];
+        d_tx += u * u;
+        d_rx += w * w;
+    }
+    return ((sqrt(d_tx) + sqrt(d_rx)) / v - t0) / dt;
+}
+
+static double focal_point_energy_ms(int beamformer, int n_ant, int n_samp, const float *ant_pos,
+                                    const float *traces, double dt, double t0, double v, int window,
+                                    const double r[3], double *tau, double *s)
+{
+    int h = (window - 1) / 2;
+    int n_ch = n_ant * n_ant;
+    for (int i = 0; i < n_ant; ++i)
+        for (int j = 0; j < n_ant; ++j)
+            tau[i * n_ant + j] = path_delay(r, ant_pos + 3 * i, ant_pos + 3 * j, v, dt, t0);
+    double energy = 0.0;
+    for (int k = -h; k <= h; ++k) {
+        for (int c = 0; c < n_ch; ++c)
+            s[c] = aligned_sample(traces + (size_t)c * n_samp, n_samp, tau[c], k);
+        double sum = 0.0;
+        if (beamformer == 0) {
+            for (int c = 0; c < n_ch; ++c)
+                sum += s[c];
+        } else {
+            for (int c = 0; c < n_ch - 1; ++c)
+                for (int e = c + 1; e < n_ch; ++e)
+                    sum += s[c] * s[e];
+        }
+        energy += sum * sum;
+    }
+    return energy;
+}
+
+/* Multistatic counterpart of oracle_image_indices: n_ant = M antennas, M^2 traces. */
+int oracle_image_indices_ms(int beamformer, int n_ant, int n_samp, const float *ant_pos,
+                            const float *traces, double dt, double t0, double v, int window,
+                            const double *origin, const double *pitch, long n, const int32_t *idx,
+                            double *out, int n_threads)
+{
+    int used = 1;
+#ifdef _OPENMP
+    if (n_threads <= 0)
+        n_threads = omp_get_max_threads();
+    used = n_threads;
+#pragma omp parallel num_threads(n_threads)
+#endif
+    {
+        size_t n_ch = (size_t)n_ant * (size_t)n_ant;
+        double *tau = (double *)malloc(sizeof(double) * n_ch);
+        double *s = (double *)malloc(sizeof(double) * n_ch);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+        for (long p = 0; p < n; ++p) {
+            double r[3];
+            for (int d = 0; d < 3; ++d)
+                r[d] = origin[d] + (double)idx[3 * p + d] * pitch[d];
+            out[p] = focal_point_energy_ms(beamformer, n_ant, n_samp, ant_pos, traces, dt, t0, v,
+                                           window, r, tau, s);
+        }
+        free(tau);
+        free(s);
+    }
+    return used;
+}

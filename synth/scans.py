@@ -58,6 +58,7 @@ class Scan:
     tumour: np.ndarray | None = None      # [3] metres
     eps_r: float = 9.0
     sigma_n: float = 0.0
+    multistatic: bool = False             # traces [M*M, T]: channel i*M + j = transmitter i, receiver j
 
     @property
     def n_ant(self) -> int:
@@ -281,3 +282,64 @@ def random_scan(seed: int, n_ant: int, n_samp: int, grid: Grid, v: float = C0 / 
     rng = np.random.default_rng(seed)
     y = rng.standard_normal((n_ant, n_samp))
     return Scan(ring_antennas(n_ant, radius), np.ascontiguousarray(y, dtype=np.float32), dt, t0, v, grid, seed)
+
+
+# ----------------------------------------------------------------------------------
+# multistatic scans (every antenna transmits, every antenna receives)
+# ----------------------------------------------------------------------------------
+
+def synthesize_ms(ant_pos, points, refl, n_samp, v, dt=DT, t0=0.0, kind="sin_gauss"):
+    """Clean multistatic traces Y[i*M + j, n] = sum_s A_ijs p(t0 + n dt - (|x_s - a_i| + |x_s - a_j|) / v),
+    A_ijs = rho_s (1 cm / |x_s - a_i|) (1 cm / |x_s - a_j|) (the monostatic 1/r^2 law split over both legs)."""
+    a = np.asarray(ant_pos, dtype=np.float64)
+    x = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    rho = np.asarray(refl, dtype=np.float64).reshape(-1)
+    m = a.shape[0]
+    dist = np.linalg.norm(x[None, :, :] - a[:, None, :], axis=2)          # [M, S]
+    n = np.arange(n_samp)
+    out = np.zeros((m * m, n_samp), dtype=np.float64)
+    for i in range(m):
+        for j in range(m):
+            for s in range(x.shape[0]):
+                tau = (dist[i, s] + dist[j, s]) / v
+                amp = rho[s] * (REF_DIST / dist[i, s]) * (REF_DIST / dist[j, s])
+                out[i * m + j] += amp * pulse(t0 + n * dt - tau, kind)
+    return out
+
+
+def ms_scan(seed: int, dataset: int = 1, noiseless: bool = False, n_ant: int = 12, n_samp: int = 1024,
+            kind: str = "sin_gauss") -> Scan:
+    """Multistatic ring of 12 antennas standing in for the two datasets of Section IV: a point tumour at
+    (-2, -3, 0) cm inside a 10 cm phantom (ring radius 12 cm, 20 x 20 cm grid at 1 mm), or at (2, 0, 1) cm inside
+    a 5 cm phantom (ring radius 7 cm, 10 x 10 cm slice through z = 1 cm at 1 mm); eps_r = 9, SNR 30 dB."""
+    if dataset == 1:
+        ant, tumour = ring_antennas(n_ant, 0.12), np.array([-0.02, -0.03, 0.0])
+        grid = Grid((-0.1 + 0.0005, -0.1 + 0.0005, 0.0), (0.001, 0.001, 0.001), (200, 200, 1))
+    else:
+        ant, tumour = ring_antennas(n_ant, RING_R), np.array([0.02, 0.0, 0.01])
+        grid = Grid((-0.05 + 0.0005, -0.05 + 0.0005, 0.01), (0.001, 0.001, 0.001), (100, 100, 1))
+    v = C0 / 3.0
+    y = synthesize_ms(ant, tumour[None, :], [1.0], n_samp, v, DT, 0.0, kind)
+    sigma_n = 0.0
+    if not noiseless:
+        a = np.asarray(ant, dtype=np.float64)
+        d = np.linalg.norm(a - tumour[None, :], axis=1)
+        n = np.arange(n_samp)
+        p = []
+        for i in range(n_ant):
+            for j in range(n_ant):
+                sel = np.abs(n * DT - (d[i] + d[j]) / v) <= 3.0 * PULSE_SIGMA
+                p.append(np.mean(y[i * n_ant + j, sel] ** 2) if np.any(sel) else 0.0)
+        sigma_n = math.sqrt(float(np.mean(p)) / 10.0 ** (30.0 / 10.0))
+        y = y + sigma_n * gaussian_noise(seed, n_ant * n_ant, n_samp)
+    return Scan(np.ascontiguousarray(ant, dtype=np.float32), np.ascontiguousarray(y, dtype=np.float32), DT, 0.0, v,
+                grid, seed, tumour, 9.0, sigma_n, multistatic=True)
+
+
+def random_scan_ms(seed: int, n_ant: int, n_samp: int, grid: Grid, v: float = C0 / 3.0, dt: float = DT,
+                   t0: float = 0.0, radius: float = RING_R) -> Scan:
+    """Multistatic ring with white-noise traces [M*M, T]."""
+    rng = np.random.default_rng(seed)
+    y = rng.standard_normal((n_ant * n_ant, n_samp))
+    return Scan(ring_antennas(n_ant, radius), np.ascontiguousarray(y, dtype=np.float32), dt, t0, v, grid, seed,
+                multistatic=True)
