@@ -210,6 +210,39 @@ typedef struct {
     int32_t reserved;
 } uwb_segment_result;
 
+/*
+ * Multistatic imaging (Eq. (2) and Eq. (4)): every one of the M antennas
+ * transmits and every one receives.  scan->n_ant = M (<= 256), scan->ant_pos
+ * [M][3], scan->traces [M * M][n_samp] fp32 with channel i * M + j the signal
+ * sent by antenna i and received on antenna j.  The delay of channel (i, j) is
+ * the transmitter-to-point plus point-to-receiver path,
+ *   n_ij(r) = ((|r - a_i| + |r - a_j|) / v - t0) / dt
+ * (Eq. (1) when i = j).  DAS is Eq. (4), the sum over all M^2 channels; DMAS
+ * takes the pairwise products of Section II-B over all pairs of distinct
+ * channels.  Batch forms: n_ant = M, traces [n_scans][M * M][n_samp].
+ * Everything else (images, workspace sizes, argmax rule, walk semantics and
+ * errors) as the monostatic calls; the learned walk and batch plans are
+ * monostatic only.
+ */
+int uwb_das_multistatic(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img, void *stream);
+int uwb_dmas_multistatic(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img, void *stream);
+int uwb_das_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img,
+                              void *stream);
+int uwb_dmas_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img,
+                               void *stream);
+int uwb_argmax_multistatic(const uwb_scan *scan, const uwb_grid *grid, int32_t window, int32_t beamformer,
+                           const float *img, uwb_peak *out, void *workspace, size_t workspace_bytes, void *stream);
+int uwb_argmax_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window,
+                                 int32_t beamformer, const float *img, uwb_peak *out, void *workspace,
+                                 size_t workspace_bytes, void *stream);
+int uwb_segment_refine_multistatic(const uwb_scan *scan, const uwb_grid *finest, int32_t window,
+                                   const uwb_segment_tree *tree, uwb_segment_result *out, float *roi_img,
+                                   int64_t roi_capacity, void *workspace, size_t workspace_bytes, void *stream);
+int uwb_segment_refine_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *finest, int32_t window,
+                                         const uwb_segment_tree *tree, uwb_segment_result *out, float *roi_img,
+                                         int64_t roi_capacity, void *workspace, size_t workspace_bytes,
+                                         void *stream);
+
 /* Largest ROI (voxels) the walk can end with for this grid and tree: the
    minimum roi_capacity.  Negative status on invalid arguments. */
 int64_t uwb_segment_roi_capacity(const uwb_grid *finest, const uwb_segment_tree *tree);

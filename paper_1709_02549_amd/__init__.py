@@ -615,3 +615,108 @@ def generate_disc_scans(recipe: DiscRecipe, ant_pos: torch.Tensor, seeds, want_t
     par = torch.tensor([[recipe.dt, recipe.t0, recipe.v]] * n, dtype=torch.float64, device=dev)
     pos = ant_pos.unsqueeze(0).expand(n, m, 3).contiguous()
     return DeviceBatch(pos, tr, par), tum
+
+
+# ----------------------------------------------------------------------------------
+# multistatic scans: M antennas, M^2 traces (channel i*M + j: transmit on i, receive on j)
+# ----------------------------------------------------------------------------------
+
+def _ms_scan_c(scan: DeviceScan) -> UwbScan:
+    _need_cuda(scan.ant_pos, "ant_pos")
+    _need_cuda(scan.traces, "traces")
+    m = int(scan.ant_pos.shape[0])
+    if scan.traces.shape[0] != m * m:
+        raise ValueError("a multistatic scan holds M^2 traces")
+    return UwbScan(m, scan.traces.shape[1], scan.ant_pos.data_ptr(), scan.traces.data_ptr(), scan.dt, scan.t0,
+                   scan.v)
+
+
+def _ms_batch_c(batch: DeviceBatch) -> UwbScanBatch:
+    bc = batch.c()
+    m = int(batch.ant_pos.shape[1])
+    if batch.traces.shape[1] != m * m:
+        raise ValueError("multistatic scans hold M^2 traces")
+    bc.n_ant = m
+    return bc
+
+
+def image_multistatic(scan: DeviceScan, grid, beamformer: int, window: int = 11, out=None):
+    """Multistatic DAS (Eq. (4)) or DMAS image [nz, ny, nx] fp32."""
+    if out is None:
+        out = torch.empty(_img_shape(grid), dtype=torch.float32, device=scan.traces.device)
+    _need_cuda(out, "out")
+    fn = lib().uwb_dmas_multistatic if beamformer == UWB_DMAS else lib().uwb_das_multistatic
+    sc, gc = _ms_scan_c(scan), grid_c(grid)
+    check(fn(ctypes.byref(sc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)), "image_multistatic")
+    return out
+
+
+def image_multistatic_batch(batch: DeviceBatch, grid, beamformer: int, window: int = 11, out=None, bc=None):
+    if out is None:
+        out = torch.empty((batch.n_scans,) + _img_shape(grid), dtype=torch.float32, device=batch.traces.device)
+    _need_cuda(out, "out")
+    fn = lib().uwb_dmas_multistatic_batch if beamformer == UWB_DMAS else lib().uwb_das_multistatic_batch
+    bc = bc if bc is not None else _ms_batch_c(batch)
+    gc = grid_c(grid)
+    check(fn(ctypes.byref(bc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)),
+          "image_multistatic_batch")
+    return out
+
+
+def argmax_multistatic(scan: DeviceScan, grid, img, beamformer: int, window: int = 11) -> Peak:
+    gc, sc = grid_c(grid), _ms_scan_c(scan)
+    need = lib().uwb_argmax_workspace_bytes(ctypes.byref(gc), 1)
+    ws = _ws.get(need, img.device)
+    out = torch.empty(ctypes.sizeof(UwbPeak), dtype=torch.uint8, device=img.device)
+    _need_cuda(img, "img")
+    check(lib().uwb_argmax_multistatic(ctypes.byref(sc), ctypes.byref(gc), window, beamformer, img.data_ptr(),
+                                       out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(img.device)),
+          "uwb_argmax_multistatic")
+    return _peaks(out, 1)[0]
+
+
+def argmax_multistatic_batch_async(batch: DeviceBatch, grid, img, beamformer: int, window: int = 11, bc=None):
+    gc = grid_c(grid)
+    bc = bc if bc is not None else _ms_batch_c(batch)
+    need = lib().uwb_argmax_workspace_bytes(ctypes.byref(gc), batch.n_scans)
+    ws = _ws.get(need, img.device)
+    out = torch.empty(ctypes.sizeof(UwbPeak) * batch.n_scans, dtype=torch.uint8, device=img.device)
+    _need_cuda(img, "img")
+    check(lib().uwb_argmax_multistatic_batch(ctypes.byref(bc), ctypes.byref(gc), window, beamformer, img.data_ptr(),
+                                             out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(img.device)),
+          "uwb_argmax_multistatic_batch")
+    return out
+
+
+def segment_refine_multistatic(scan: DeviceScan, grid, tree: SegmentTree, window: int = 11, want_roi=False):
+    gc, tc, sc = grid_c(grid), tree.c(), _ms_scan_c(scan)
+    dev = scan.traces.device
+    cap = roi_capacity(grid, tree)
+    need = lib().uwb_segment_workspace_bytes(ctypes.byref(gc), ctypes.byref(tc), 1)
+    ws = _ws.get(need, dev)
+    out = torch.empty(ctypes.sizeof(UwbSegmentResult), dtype=torch.uint8, device=dev)
+    roi = torch.empty(cap, dtype=torch.float32, device=dev) if want_roi else None
+    check(lib().uwb_segment_refine_multistatic(ctypes.byref(sc), ctypes.byref(gc), window, ctypes.byref(tc),
+                                               out.data_ptr(), roi.data_ptr() if roi is not None else 0, cap,
+                                               ws.data_ptr(), ws.numel(), _stream(dev)),
+          "uwb_segment_refine_multistatic")
+    res = _results(out, 1, 4 if int(grid.dims[2]) == 1 else 8)[0]
+    if want_roi:
+        b = res.roi
+        shape = (b[5] - b[4], b[3] - b[2], b[1] - b[0])
+        res.roi_image = roi[:int(np.prod(shape))].cpu().numpy().reshape(shape)
+    return res
+
+
+def segment_refine_multistatic_batch_async(batch: DeviceBatch, grid, tree: SegmentTree, window: int = 11, bc=None):
+    gc, tc = grid_c(grid), tree.c()
+    bc = bc if bc is not None else _ms_batch_c(batch)
+    dev = batch.traces.device
+    cap = roi_capacity(grid, tree)
+    need = lib().uwb_segment_workspace_bytes(ctypes.byref(gc), ctypes.byref(tc), batch.n_scans)
+    ws = _ws.get(need, dev)
+    out = torch.empty(ctypes.sizeof(UwbSegmentResult) * batch.n_scans, dtype=torch.uint8, device=dev)
+    check(lib().uwb_segment_refine_multistatic_batch(ctypes.byref(bc), ctypes.byref(gc), window, ctypes.byref(tc),
+                                                     out.data_ptr(), 0, cap, ws.data_ptr(), ws.numel(), _stream(dev)),
+          "uwb_segment_refine_multistatic_batch")
+    return out

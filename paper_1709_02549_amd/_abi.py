@@ -77,6 +77,21 @@ PROTOTYPES = {
     "uwb_dmas": (c_i32, [ctypes.POINTER(UwbScan), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp]),
     "uwb_das_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp]),
     "uwb_dmas_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp]),
+    "uwb_das_multistatic": (c_i32, [ctypes.POINTER(UwbScan), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp]),
+    "uwb_dmas_multistatic": (c_i32, [ctypes.POINTER(UwbScan), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp]),
+    "uwb_das_multistatic_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp]),
+    "uwb_dmas_multistatic_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_vp,
+                                           c_vp]),
+    "uwb_argmax_multistatic": (c_i32, [ctypes.POINTER(UwbScan), ctypes.POINTER(UwbGrid), c_i32, c_i32, c_vp, c_vp,
+                                       c_vp, ctypes.c_size_t, c_vp]),
+    "uwb_argmax_multistatic_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_i32,
+                                             c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "uwb_segment_refine_multistatic": (c_i32, [ctypes.POINTER(UwbScan), ctypes.POINTER(UwbGrid), c_i32,
+                                               ctypes.POINTER(UwbSegmentTree), c_vp, c_vp, c_i64, c_vp,
+                                               ctypes.c_size_t, c_vp]),
+    "uwb_segment_refine_multistatic_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32,
+                                                     ctypes.POINTER(UwbSegmentTree), c_vp, c_vp, c_i64, c_vp,
+                                                     ctypes.c_size_t, c_vp]),
     "uwb_argmax_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(UwbGrid), c_i32]),
     "uwb_argmax": (c_i32, [ctypes.POINTER(UwbScan), ctypes.POINTER(UwbGrid), c_i32, c_i32, c_vp, c_vp, c_vp,
                            ctypes.c_size_t, c_vp]),

@@ -48,11 +48,23 @@ int scan_set(const uwb_scan *s, ScanSet *out) {
     out->tr_stride = 0;
     out->n_ant = s->n_ant;
     out->n_samp = s->n_samp;
+    out->ms = 0;
     out->dt = s->dt;
     out->t0 = s->t0;
     out->v = s->v;
     return UWB_OK;
 }
+
+// A multistatic scan: s->n_ant antennas, s->n_ant^2 traces (channel i*M + j).
+static int scan_set_ms(const uwb_scan *s, ScanSet *out) {
+    int st = scan_set(s, out);
+    if (st) return st;
+    if (s->n_ant > kMaxMultistaticAnt) return UWB_EUNSUPPORTED;
+    out->ms = s->n_ant;
+    out->n_ant = s->n_ant * s->n_ant;
+    return UWB_OK;
+}
+
 
 int batch_set(const uwb_scan_batch *b, ScanSet *out) {
     if (!b || !b->ant_pos || !b->traces || !b->params) return UWB_EINVAL;
@@ -68,9 +80,20 @@ int batch_set(const uwb_scan_batch *b, ScanSet *out) {
     out->tr_stride = (int64_t)b->n_ant * b->n_samp;
     out->n_ant = b->n_ant;
     out->n_samp = b->n_samp;
+    out->ms = 0;
     out->dt = b->dt_min;      // lower bounds: size the on-chip staging
     out->t0 = 0.0;
     out->v = b->v_min;
+    return UWB_OK;
+}
+
+static int batch_set_ms(const uwb_scan_batch *b, ScanSet *out) {
+    int st = batch_set(b, out);
+    if (st) return st;
+    if (b->n_ant > kMaxMultistaticAnt) return UWB_EUNSUPPORTED;
+    out->ms = b->n_ant;
+    out->n_ant = b->n_ant * b->n_ant;
+    out->tr_stride = (int64_t)out->n_ant * b->n_samp;
     return UWB_OK;
 }
 
@@ -165,6 +188,70 @@ int uwb_dmas_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t wi
     ScanSet ss;
     int st = batch_set(scans, &ss);
     return st ? st : image_common(UWB_DMAS, ss, scans->n_scans, grid, window, img, stream);
+}
+
+int uwb_das_multistatic(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img, void *stream) {
+    ScanSet ss;
+    int st = scan_set_ms(scan, &ss);
+    return st ? st : image_common(UWB_DAS, ss, 1, grid, window, img, stream);
+}
+
+int uwb_dmas_multistatic(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img, void *stream) {
+    ScanSet ss;
+    int st = scan_set_ms(scan, &ss);
+    return st ? st : image_common(UWB_DMAS, ss, 1, grid, window, img, stream);
+}
+
+int uwb_das_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img,
+                              void *stream) {
+    ScanSet ss;
+    int st = batch_set_ms(scans, &ss);
+    return st ? st : image_common(UWB_DAS, ss, scans->n_scans, grid, window, img, stream);
+}
+
+int uwb_dmas_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img,
+                               void *stream) {
+    ScanSet ss;
+    int st = batch_set_ms(scans, &ss);
+    return st ? st : image_common(UWB_DMAS, ss, scans->n_scans, grid, window, img, stream);
+}
+
+int uwb_argmax_multistatic(const uwb_scan *scan, const uwb_grid *grid, int32_t window, int32_t beamformer,
+                           const float *img, uwb_peak *out, void *workspace, size_t workspace_bytes, void *stream) {
+    ScanSet ss;
+    int st = scan_set_ms(scan, &ss);
+    return st ? st : argmax_common(ss, 1, grid, window, beamformer, img, out, workspace, workspace_bytes, stream);
+}
+
+int uwb_argmax_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window,
+                                 int32_t beamformer, const float *img, uwb_peak *out, void *workspace,
+                                 size_t workspace_bytes, void *stream) {
+    ScanSet ss;
+    int st = batch_set_ms(scans, &ss);
+    return st ? st
+              : argmax_common(ss, scans->n_scans, grid, window, beamformer, img, out, workspace, workspace_bytes,
+                              stream);
+}
+
+int uwb_segment_refine_multistatic(const uwb_scan *scan, const uwb_grid *finest, int32_t window,
+                                   const uwb_segment_tree *tree, uwb_segment_result *out, float *roi_img,
+                                   int64_t roi_capacity, void *workspace, size_t workspace_bytes, void *stream) {
+    ScanSet ss;
+    int st = scan_set_ms(scan, &ss);
+    return st ? st
+              : walk_common(ss, 1, finest, window, tree, out, roi_img, roi_capacity, workspace, workspace_bytes,
+                            stream);
+}
+
+int uwb_segment_refine_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *finest, int32_t window,
+                                         const uwb_segment_tree *tree, uwb_segment_result *out, float *roi_img,
+                                         int64_t roi_capacity, void *workspace, size_t workspace_bytes,
+                                         void *stream) {
+    ScanSet ss;
+    int st = batch_set_ms(scans, &ss);
+    return st ? st
+              : walk_common(ss, scans->n_scans, finest, window, tree, out, roi_img, roi_capacity, workspace,
+                            workspace_bytes, stream);
 }
 
 size_t uwb_argmax_workspace_bytes(const uwb_grid *grid, int32_t n_scans) {

@@ -96,6 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_batch32(const BatchArgs a) {
         j.tz0 = (tile / (d.tiles_x * d.tiles_y)) * tz;
         j.rs = d.rs;
         j.chunk = d.chunk;
+        j.ms = 0;
         image_tile<BF, W, D3, VPL>(j, smem);
         __syncthreads();   // every lane's image stores are issued before the scan counter moves
         if (threadIdx.x == 0) {

@@ -24,8 +24,9 @@ struct TileJob {
     double s, t0s;        // samples per metre of path (2 / (v dt)) and t0 / dt
     GridView g;
     int tx0, ty0, tz0;    // first voxel of the tile
-    int rs;               // staged samples per antenna (LDS stride)
-    int chunk;            // antennas staged per pass
+    int rs;               // staged samples per channel (LDS stride)
+    int chunk;            // channels staged per pass
+    int ms;               // multistatic: antennas per side (channel i*ms + j), 0: monostatic
 };
 
 // Tile geometry.  2D: 16 (x) by 16*VPL (y); lane (tx, ty) owns y = ty + 16 v.
@@ -37,22 +38,27 @@ template <bool D3, int VPL> struct TileShape {
     __device__ static void get(int &x, int &y, int &z) { x = X; y = Y; z = Z; }
 };
 
-template <int BF, int W, bool D3, int VPL>
+// Monostatic (MS = false): channel i is antenna i, delay s |r - a_i| - t0s (Eq. (1)).
+// Multistatic (MS = true): channel i*M + j, delay (s/2)(|r - a_i| + |r - a_j|) - t0s
+// (Eq. (2)); the table then holds the transmitter's and the receiver's offsets.
+template <int BF, int W, bool D3, int VPL, bool MS = false>
 __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
     using TS = TileShape<D3, VPL>;
     constexpr int H = (W - 1) / 2;
     constexpr int TX = TS::X, TY = TS::Y, TZ = TS::Z;
+    constexpr int TE = MS ? 2 : 1;                            // table entries per channel
     const int chunk = j.chunk, rs = j.rs;
-    float4 *tab = reinterpret_cast<float4 *>(smem);          // [chunk]
-    float *stage = smem + 4 * chunk;                          // [chunk][rs]
+    float4 *tab = reinterpret_cast<float4 *>(smem);          // [chunk][TE]
+    float *stage = smem + 4 * TE * chunk;                     // [chunk][rs]
+    const double sc = MS ? 0.5 * j.s : j.s;                   // samples per metre of each leg
     const int tid = threadIdx.x;
     const int nx = j.g.dims[0], ny = j.g.dims[1], nz = j.g.dims[2];
     const int T = j.T, M = j.M;
     const int tx0 = j.tx0, ty0 = j.ty0, tz0 = j.tz0;
 
-    const float qx = (float)(j.s * j.g.pitch[0]);
-    const float qy = (float)(j.s * j.g.pitch[1]);
-    const float qz = (float)(j.s * j.g.pitch[2]);
+    const float qx = (float)(sc * j.g.pitch[0]);
+    const float qy = (float)(sc * j.g.pitch[1]);
+    const float qz = (float)(sc * j.g.pitch[2]);
     const float t0s = (float)j.t0s;
     // this scan's own staging need must fit the launch's (a batch is sized for its bound)
     const double ex = (TX - 1) * j.g.pitch[0], ey = (TY - 1) * j.g.pitch[1], ez = (TZ - 1) * j.g.pitch[2];
@@ -96,37 +102,44 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
         __syncthreads();   // previous chunk (or previous tile) fully consumed
         if (tid < nch) {
             const int i = a0 + tid;
-            const double ax = (double)j.pos[3 * i + 0];
-            const double ay = (double)j.pos[3 * i + 1];
-            const double az = (double)j.pos[3 * i + 2];
-            // antenna-relative offsets in sample units: c + idx * q
-            const double cx = j.s * (j.g.origin[0] - ax);
-            const double cy = j.s * (j.g.origin[1] - ay);
-            const double cz = j.s * (j.g.origin[2] - az);
-            const double dqx = j.s * j.g.pitch[0], dqy = j.s * j.g.pitch[1], dqz = j.s * j.g.pitch[2];
-            const double lx = cx + tx0 * dqx, hx = cx + bx1 * dqx;
-            const double ly = cy + ty0 * dqy, hy = cy + by1 * dqy;
-            const double lz = cz + tz0 * dqz, hz = cz + bz1 * dqz;
-            // nearest point of the tile's box to the antenna (the antenna is at 0 here)
-            const double mx = fmin(fmax(0.0, lx), hx), my = fmin(fmax(0.0, ly), hy), mz = fmin(fmax(0.0, lz), hz);
-            const double tmin = sqrt(mx * mx + my * my + mz * mz) - j.t0s;
+            const double dqx = sc * j.g.pitch[0], dqy = sc * j.g.pitch[1], dqz = sc * j.g.pitch[2];
+            double tmin = -j.t0s;
+            float4 e[TE];
+#pragma unroll
+            for (int leg = 0; leg < TE; ++leg) {
+                const int ant = MS ? (leg == 0 ? i / j.ms : i % j.ms) : i;
+                const double ax = (double)j.pos[3 * ant + 0];
+                const double ay = (double)j.pos[3 * ant + 1];
+                const double az = (double)j.pos[3 * ant + 2];
+                // antenna-relative offsets in sample units: c + idx * q
+                const double cx = sc * (j.g.origin[0] - ax);
+                const double cy = sc * (j.g.origin[1] - ay);
+                const double cz = sc * (j.g.origin[2] - az);
+                const double lx = cx + tx0 * dqx, hx = cx + bx1 * dqx;
+                const double ly = cy + ty0 * dqy, hy = cy + by1 * dqy;
+                const double lz = cz + tz0 * dqz, hz = cz + bz1 * dqz;
+                // nearest point of the tile's box to the antenna (the antenna is at 0 here)
+                const double mx = fmin(fmax(0.0, lx), hx), my = fmin(fmax(0.0, ly), hy), mz = fmin(fmax(0.0, lz), hz);
+                tmin += sqrt(mx * mx + my * my + mz * mz);
+                e[leg].x = (float)cx;
+                e[leg].y = (float)cy;
+                e[leg].z = D3 ? (float)cz : (float)(cz * cz);
+                e[leg].w = 0.f;
+            }
             // first staged sample: one below the lowest window start; clamped so that
             // a window outside the trace still reads a run of zeros
             double lo = floor(tmin) - (H + 1);
             lo = fmin(fmax(lo, -(double)(W + 1)), (double)(T + W + 1 - rs));
             const int ilo = (int)lo;
-            float4 e;
-            e.x = (float)cx;
-            e.y = (float)cy;
-            e.z = D3 ? (float)cz : (float)(cz * cz);
-            e.w = __int_as_float(tid * rs - ilo - H);   // window start = floor(tau) + this
-            tab[tid] = e;
+            e[0].w = __int_as_float(tid * rs - ilo - H);   // window start = floor(tau) + this
+#pragma unroll
+            for (int leg = 0; leg < TE; ++leg) tab[TE * tid + leg] = e[leg];
         }
         __syncthreads();
         // stage [lo, lo + rs) of every antenna of the chunk
         const int wave = tid >> 6, lane = tid & 63;
         for (int jj = wave; jj < nch; jj += kBlock / 64) {
-            const int ilo = jj * rs - H - __float_as_int(tab[jj].w);
+            const int ilo = jj * rs - H - __float_as_int(tab[TE * jj].w);
             const float *tr = j.tr + (int64_t)(a0 + jj) * T;
             float *dst = stage + jj * rs;
             for (int m = lane; m < rs; m += 64) {
@@ -137,16 +150,26 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
         __syncthreads();
 
         for (int jj = 0; jj < nch; ++jj) {
-            const float4 e = tab[jj];
+            const float4 e = tab[TE * jj];
+            const float4 er = tab[TE * jj + (MS ? 1 : 0)];
             const int base = __float_as_int(e.w);
             const int lob = jj * rs, hib = jj * rs + rs - (W + 1);
             const float dx = fmaf(fx, qx, e.x);
-            float part;
+            float part, partr = 0.f;
             if (!D3) {
                 part = fmaf(dx, dx, e.z);
             } else {
                 const float dy = fmaf(fy[0], qy, e.y);
                 part = fmaf(dy, dy, dx * dx);
+            }
+            if (MS) {
+                const float rx_ = fmaf(fx, qx, er.x);
+                if (!D3) {
+                    partr = fmaf(rx_, rx_, er.z);
+                } else {
+                    const float ry_ = fmaf(fy[0], qy, er.y);
+                    partr = fmaf(ry_, ry_, rx_ * rx_);
+                }
             }
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
@@ -158,7 +181,18 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
                     const float dz = fmaf(fz[v], qz, e.z);
                     d2 = fmaf(dz, dz, part);
                 }
-                const float tau = __builtin_amdgcn_sqrtf(d2) - t0s;
+                float tau = __builtin_amdgcn_sqrtf(d2) - t0s;
+                if (MS) {
+                    float d2r;
+                    if (!D3) {
+                        const float dy = fmaf(fy[v], qy, er.y);
+                        d2r = fmaf(dy, dy, partr);
+                    } else {
+                        const float dz = fmaf(fz[v], qz, er.z);
+                        d2r = fmaf(dz, dz, partr);
+                    }
+                    tau += __builtin_amdgcn_sqrtf(d2r);
+                }
                 const float fl = floorf(tau);
                 const float f = tau - fl;
                 const float g = 1.f - f;

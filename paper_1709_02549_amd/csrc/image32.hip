@@ -52,7 +52,7 @@ struct Args {
     int chunk;              // antennas staged per pass
 };
 
-template <int BF, int W, bool D3>
+template <int BF, int W, bool D3, bool MS>
 __global__ __launch_bounds__(kBlock) void k_image32(const Args a) {
     constexpr int VPL = 2;
     extern __shared__ float smem[];
@@ -75,13 +75,19 @@ __global__ __launch_bounds__(kBlock) void k_image32(const Args a) {
     j.tz0 = (tile / (a.tiles_x * a.tiles_y)) * tz;
     j.rs = a.rs;
     j.chunk = a.chunk;
-    image_tile<BF, W, D3, VPL>(j, smem);
+    j.ms = a.ss.ms;
+    image_tile<BF, W, D3, VPL, MS>(j, smem);
 }
 
 template <int BF, int W>
 hipError_t launch_w(bool d3, dim3 grid, size_t lds, hipStream_t st, const Args &a) {
-    if (d3) hipLaunchKernelGGL((k_image32<BF, W, true>), grid, dim3(kBlock), lds, st, a);
-    else hipLaunchKernelGGL((k_image32<BF, W, false>), grid, dim3(kBlock), lds, st, a);
+    if (a.ss.ms) {
+        if (d3) hipLaunchKernelGGL((k_image32<BF, W, true, true>), grid, dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((k_image32<BF, W, false, true>), grid, dim3(kBlock), lds, st, a);
+    } else {
+        if (d3) hipLaunchKernelGGL((k_image32<BF, W, true, false>), grid, dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((k_image32<BF, W, false, false>), grid, dim3(kBlock), lds, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -115,7 +121,7 @@ int launch_image32(int bf, const ScanSet &ss, int n_scans, const GridView &g, in
     const double s_max = 2.0 / (ss.v * ss.dt);
     a.rs = staged_samples(s_max, (tx - 1) * g.pitch[0], (ty - 1) * g.pitch[1], (tz - 1) * g.pitch[2], window,
                           ss.n_samp);
-    const int per_ant = a.rs * 4 + 16;
+    const int per_ant = a.rs * 4 + (ss.ms ? 32 : 16);   // staged samples + table entries
     if (per_ant > kLdsBudget) return UWB_EUNSUPPORTED;
     a.chunk = kLdsBudget / per_ant;
     if (a.chunk > kBlock) a.chunk = kBlock;

@@ -13,16 +13,21 @@ constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kMaxWindow = UWB_MAX_WINDOW;
 constexpr double kTieRel = 1e-12;    // relative band of the maximum-selection rule
 constexpr double kCandRel = 1e-3;    // FP32 candidates for the FP64 argmax re-evaluation
+constexpr int kMaxMultistaticAnt = 256;   // antennas of a multistatic scan (M^2 channels)
 
 // A set of same-shaped scans in device memory.  Scan s uses
 //   ant_pos + s*pos_stride, traces + s*tr_stride, and (dt, t0, v) either from
 //   params[3*s..] (device) or, when params == nullptr, from the inline values.
+// n_ant counts channels.  Monostatic (ms == 0): channel i is antenna i.
+// Multistatic (ms == M > 0): M antennas, n_ant = M^2 channels, channel i*M + j
+// transmits from antenna i and receives on antenna j (Eq. (2)).
 struct ScanSet {
     const float *ant_pos;
     const float *traces;
     const double *params;
     int64_t pos_stride, tr_stride;
     int32_t n_ant, n_samp;
+    int32_t ms;
     double dt, t0, v;
 };
 
@@ -38,6 +43,7 @@ struct ScanConst {
     const float *tr;
     double s;     // 2 / (v dt)
     double t0s;   // t0 / dt
+    int ms;       // multistatic: antennas per side (0: monostatic)
 };
 
 __device__ __forceinline__ ScanConst scan_const(const ScanSet &ss, int scan) {
@@ -52,6 +58,7 @@ __device__ __forceinline__ ScanConst scan_const(const ScanSet &ss, int scan) {
     }
     c.s = 2.0 / (v * dt);
     c.t0s = t0 / dt;
+    c.ms = ss.ms;
     return c;
 }
 
@@ -125,7 +132,7 @@ __device__ __forceinline__ int block_exclusive_scan(int x, int *out, int *tmp /*
 // touch.  Returns false (uniformly) when they do not fit; the caller then reads HBM.
 __device__ bool stage_box(const Stage &st, int *tmp, const ScanConst &sc, int M, int T, int window,
                           const GridView &g, const int *blo, const int *bhi) {
-    if (M > kStageMaxAnt) return false;
+    if (M > kStageMaxAnt || sc.ms) return false;   // monostatic spans only
     const int h = (window - 1) / 2;
     const int tid = threadIdx.x;
     for (int i = tid; i < M; i += kBlock) {
@@ -184,6 +191,20 @@ __device__ bool stage_box(const Stage &st, int *tmp, const ScanConst &sc, int M,
 // ------------------------------------------------------------------------------
 constexpr int kChunk = 8;
 
+// FP64 delay in samples of channel i at r: Eq. (1) (monostatic) or Eq. (2) (multistatic).
+__device__ __forceinline__ double delay64(const ScanConst &sc, int i, double rx, double ry, double rz) {
+    if (sc.ms) {
+        const float *at = sc.pos + 3 * (i / sc.ms), *ar = sc.pos + 3 * (i % sc.ms);
+        const double tx = rx - (double)at[0], ty = ry - (double)at[1], tz = rz - (double)at[2];
+        const double ux = rx - (double)ar[0], uy = ry - (double)ar[1], uz = rz - (double)ar[2];
+        return 0.5 * sc.s * (sqrt(tx * tx + ty * ty + tz * tz) + sqrt(ux * ux + uy * uy + uz * uz)) - sc.t0s;
+    }
+    const double dx = rx - (double)sc.pos[3 * i + 0];
+    const double dy = ry - (double)sc.pos[3 * i + 1];
+    const double dz = rz - (double)sc.pos[3 * i + 2];
+    return sc.s * sqrt(dx * dx + dy * dy + dz * dz) - sc.t0s;
+}
+
 __device__ __forceinline__ double trace64(const float *tr, int T, long long m) {
     return (m >= 0 && m < T) ? (double)tr[m] : 0.0;
 }
@@ -198,11 +219,7 @@ __device__ double energy64_group(const ScanConst &sc, int M, int T, int window, 
 #pragma unroll
         for (int j = 0; j < kChunk; ++j) { S[j] = 0.0; P[j] = 0.0; }
         for (int i = gl; i < M; i += G) {
-            const double ax = (double)sc.pos[3 * i + 0];
-            const double ay = (double)sc.pos[3 * i + 1];
-            const double az = (double)sc.pos[3 * i + 2];
-            const double dx = rx - ax, dy = ry - ay, dz = rz - az;
-            const double tau = sc.s * sqrt(dx * dx + dy * dy + dz * dz) - sc.t0s;
+            const double tau = delay64(sc, i, rx, ry, rz);
             const double fl = floor(tau);
             const double f = tau - fl;
             if (st) {

@@ -21,7 +21,7 @@
 namespace uwb {
 namespace {
 
-constexpr int kTabBytes = 32;   // per staged antenna: position (3 doubles) and first staged sample
+constexpr int kTabBytes = 64;   // per staged channel: transmitter and receiver positions, first staged sample
 
 template <bool D3> struct Tile64 {
     static constexpr int X = D3 ? 8 : 16, Y = D3 ? 8 : 16, Z = D3 ? 4 : 1;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_grid64(const Grid64Args a) {
     const ScanConst sc = scan_const(a.ss, scan);
     const int M = a.ss.n_ant, T = a.ss.n_samp;
     const int rs = a.rs, chunk = a.chunk;
-    double *tab = reinterpret_cast<double *>(dsm);                        // [chunk][4]
+    double *tab = reinterpret_cast<double *>(dsm);                        // [chunk][8]
     float *stage = reinterpret_cast<float *>(dsm + (size_t)kTabBytes * chunk);   // [chunk][rs]
 
     // lane -> lattice point -> finest indices -> position
@@ -112,27 +112,32 @@ __global__ __launch_bounds__(kBlock) void k_grid64(const Grid64Args a) {
         __syncthreads();   // previous chunk consumed
         if (tid < nch) {
             const int i = a0 + tid;
-            const double ax = (double)sc.pos[3 * i + 0];
-            const double ay = (double)sc.pos[3 * i + 1];
-            const double az = (double)sc.pos[3 * i + 2];
-            // nearest point of the tile's box to the antenna: earliest delay of the tile
-            const double nx = fmin(fmax(ax, blo[0]), bhi[0]) - ax;
-            const double ny = fmin(fmax(ay, blo[1]), bhi[1]) - ay;
-            const double nz = fmin(fmax(az, blo[2]), bhi[2]) - az;
-            const double tmin = sc.s * sqrt(nx * nx + ny * ny + nz * nz) - sc.t0s;
+            // transmitter and receiver of the channel (the same antenna when monostatic)
+            const float *at = sc.pos + 3 * (sc.ms ? i / sc.ms : i), *ar = sc.pos + 3 * (sc.ms ? i % sc.ms : i);
+            double dmin = 0.0;
+            for (int leg = 0; leg < 2; ++leg) {
+                const float *ap = leg == 0 ? at : ar;
+                const double ax = (double)ap[0], ay = (double)ap[1], az = (double)ap[2];
+                // nearest point of the tile's box to the antenna: earliest delay of the tile
+                const double nx = fmin(fmax(ax, blo[0]), bhi[0]) - ax;
+                const double ny = fmin(fmax(ay, blo[1]), bhi[1]) - ay;
+                const double nz = fmin(fmax(az, blo[2]), bhi[2]) - az;
+                dmin += sqrt(nx * nx + ny * ny + nz * nz);
+                tab[8 * tid + 3 * leg + 0] = ax;
+                tab[8 * tid + 3 * leg + 1] = ay;
+                tab[8 * tid + 3 * leg + 2] = az;
+            }
+            const double tmin = 0.5 * sc.s * dmin - sc.t0s;
             // first staged sample: one below the lowest window start, clamped so that a
             // window wholly outside the trace still reads a run of zeros
             double lo = floor(tmin) - (H + 1);
             lo = fmin(fmax(lo, -(double)(W + 1)), (double)(T + W + 1 - rs));
-            tab[4 * tid + 0] = ax;
-            tab[4 * tid + 1] = ay;
-            tab[4 * tid + 2] = az;
-            tab[4 * tid + 3] = lo;
+            tab[8 * tid + 6] = lo;
         }
         __syncthreads();
         const int wave = tid >> 6, lane = tid & 63;
         for (int jj = wave; jj < nch; jj += kBlock / 64) {
-            const int ilo = (int)tab[4 * jj + 3];
+            const int ilo = (int)tab[8 * jj + 6];
             const float *tr = sc.tr + (int64_t)(a0 + jj) * T;
             float *dst = stage + jj * rs;
             for (int m = lane; m < rs; m += 64) {
@@ -142,15 +147,23 @@ __global__ __launch_bounds__(kBlock) void k_grid64(const Grid64Args a) {
         }
         __syncthreads();
         for (int jj = 0; jj < nch; ++jj) {
-            const double dx = rx - tab[4 * jj + 0];
-            const double dy = ry - tab[4 * jj + 1];
-            const double dz = rz - tab[4 * jj + 2];
-            const double tau = sc.s * sqrt(dx * dx + dy * dy + dz * dz) - sc.t0s;
+            const double dx = rx - tab[8 * jj + 0];
+            const double dy = ry - tab[8 * jj + 1];
+            const double dz = rz - tab[8 * jj + 2];
+            double tau;
+            if (sc.ms) {   // Eq. (2): both legs
+                const double ux = rx - tab[8 * jj + 3];
+                const double uy = ry - tab[8 * jj + 4];
+                const double uz = rz - tab[8 * jj + 5];
+                tau = 0.5 * sc.s * (sqrt(dx * dx + dy * dy + dz * dz) + sqrt(ux * ux + uy * uy + uz * uz)) - sc.t0s;
+            } else {
+                tau = sc.s * sqrt(dx * dx + dy * dy + dz * dz) - sc.t0s;
+            }
             const double fl = floor(tau);
             const double f = tau - fl;
             // window samples n-H .. n+H+1 sit at stage offsets n-H-lo .. ; the clamp only
             // guards non-finite inputs (every span fits by construction)
-            const double off = fmin(fmax(fl - H - tab[4 * jj + 3], 0.0), (double)(rs - (W + 1)));
+            const double off = fmin(fmax(fl - H - tab[8 * jj + 6], 0.0), (double)(rs - (W + 1)));
             const float *p = stage + jj * rs + (int)off;
             float y[W + 1];
 #pragma unroll
