@@ -45,7 +45,7 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2      # wave64 FP32 instructions per second
 # HBM bytes per launch of the DMAS kernel at the default batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a 256 MiB copy); valid only for the kernel
 # sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
-TRAFFIC = {"source_hash": "12642dd4847ae4f1", "batch": 256, "bytes": 310766066}
+TRAFFIC = {"source_hash": "ee12d55101657519", "batch": 256, "bytes": 310781591}
 
 
 def _kernel_source_hash() -> str:
@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--c5-eval", type=int, default=10_000, help="held-out scans for its localisation error")
     ap.add_argument("--c5-epochs", type=float, default=1.0)
     ap.add_argument("--no-c5", action="store_true", help="skip training / evaluating the learned proposer")
+    ap.add_argument("--ms-batch", type=int, default=64, help="multistatic scans (12-antenna ring, 200x200 grid)")
+    ap.add_argument("--no-ms", action="store_true", help="skip the multistatic and no-tumour-check measurements")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (HBM counter reference)")
     args = ap.parse_args()
@@ -215,6 +217,9 @@ def main():
 
     if not args.no_c5:
         out["learned"] = learned_block(args, uwb, synth, dev)
+    if not args.no_ms:
+        out["multistatic"] = multistatic_block(args, uwb, synth, dev)
+        out["tumour_check"] = tumour_check_block(uwb, synth, dev)
 
     if not args.no_cpu:
         import oracle
@@ -235,6 +240,71 @@ def main():
                                "sample": f"{n_done} full 512x512 scans, DAS + direct-pairwise DMAS, FP64, "
                                          f"{el:.1f} s"}
     print(json.dumps(out), flush=True)
+
+
+def _timed(fn, reps=5):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def multistatic_block(args, uwb, synth, dev):
+    """Eq. (2)/(4) on the 12-antenna ring standing in for the paper's first dataset (144 channels, 200 x 200 grid at
+    1 mm): full-resolution DAS/DMAS throughput, the paper walk with automatic D (1 cm tumour -> D = 7), and its
+    localisation against full-resolution DMAS."""
+    import numpy as np
+    B = args.ms_batch
+    scans = [synth.ms_scan(k, 1) for k in range(min(B, 16))]
+    scans = [scans[k % len(scans)] for k in range(B)]
+    grid = scans[0].grid
+    b = uwb.DeviceBatch.from_host(scans, dev)
+    bc = uwb._ms_batch_c(b)
+    nx, ny, nz = grid.dims
+    img = {bf: torch_empty(B, grid, dev) for bf in (0, 1)}
+    ms = {bf: _timed(lambda bf=bf: uwb.image_multistatic_batch(b, grid, bf, out=img[bf], bc=bc)) for bf in (0, 1)}
+    vc = B * nx * ny * nz * 144
+    tree = uwb.SegmentTree(beamformer=1, walk="paper", min_tumour=0.01, metric="max", frame_final=0.25)
+    walk_ms = _timed(lambda: uwb.segment_refine_multistatic_batch_async(b, grid, tree, bc=bc))
+    out = uwb.segment_refine_multistatic_batch_async(b, grid, tree, bc=bc)
+    res = uwb._results(out, B, 4)
+    pk = uwb._peaks(uwb.argmax_multistatic_batch_async(b, grid, img[1], 1, bc=bc), B)
+    arg_ms = _timed(lambda: uwb.argmax_multistatic_batch_async(b, grid, img[1], 1, bc=bc))
+    within = float(np.mean([abs(r.argmax % nx - p.index % nx) <= 1 and abs(r.argmax // nx - p.index // nx) <= 1
+                            for r, p in zip(res, pk)]))
+    return {"workload": "12-antenna multistatic ring (radius 12 cm), 144 channels x 1024 samples, 200x200 grid at 1 mm, "
+                        "window 11", "batch_scans": B,
+            "das_gvcs": round(vc / (ms[0] * 1e-3) / 1e9, 2), "dmas_gvcs": round(vc / (ms[1] * 1e-3) / 1e9, 2),
+            "unit": "Gvoxel·channel/s", "das_ms": round(ms[0], 4), "dmas_ms": round(ms[1], 4),
+            "full_dmas_scans_per_s": round(B / ((ms[1] + arg_ms) * 1e-3), 1),
+            "paper_walk_scans_per_s": round(B / (walk_ms * 1e-3), 1), "paper_walk_decimation": res[0].decimation,
+            "paper_walk_within_1_voxel_of_full_dmas": within,
+            "voxel_ratio_full_over_walk": round(nx * ny / float(np.mean([r.voxels_evaluated for r in res])), 1)}
+
+
+def torch_empty(B, grid, dev):
+    import torch
+    nx, ny, nz = grid.dims
+    return torch.empty((B, nz, ny, nx), dtype=torch.float32, device=dev)
+
+
+def tumour_check_block(uwb, synth, dev):
+    """The two-decimation check of Section IV on 64 C1 scans with a tumour and 64 noise-only scans."""
+    import numpy as np
+    grid = synth.square_grid(128)
+    yes = [synth.c1_scan(k) for k in range(64)]
+    no = [synth.random_scan(k, 16, 1024, grid) for k in range(64)]
+    tree = uwb.SegmentTree(beamformer=1, walk="paper", metric="max", frame_final=0.25)
+    ay, _, _ = uwb.tumour_check_batch(uwb.DeviceBatch.from_host(yes, dev), grid, tree, 9, 5)
+    an, _, _ = uwb.tumour_check_batch(uwb.DeviceBatch.from_host(no, dev), grid, tree, 9, 5)
+    return {"decimations": [9, 5], "confirmed_with_tumour": float(np.mean(ay)),
+            "confirmed_noise_only": float(np.mean(an)), "scans": 64}
 
 
 def learned_block(args, uwb, synth, dev):
