@@ -4,9 +4,11 @@
 // count, trace length, grid and output) and a work list of (scan, tile) items,
 // scan-major, scans ordered by decreasing cost (longest-processing-time first)
 // or as given.  The persistent kernel keeps a fixed number of workgroups per CU
-// resident; each pulls the next item with one atomic, images that tile with the
-// same tile body as the single-scan kernel, and the workgroup that finishes a
-// scan's last tile stamps the scan's completion time (s_memrealtime, 100 MHz).
+// resident; each pulls the next kItemsPerFetch items with one atomic, images those
+// tiles with the same tile body as the single-scan kernel, and after every tile
+// raises the scan's completion stamp to the current time (s_memrealtime, 100 MHz)
+// with a non-returning atomic max, so no round trip is waited for per tile: a
+// scan's stamp ends as the time its last tile finished.
 // A reset kernel and the persistent kernel are captured once into a hipGraph;
 // uwb_batch_run replays it.  The tile shape (voxels per lane), the resident
 // workgroups per CU, the LDS staging budget (hence the antenna chunk) and the
@@ -42,10 +44,11 @@ struct BatchArgs {
     const int *item_scan;
     int n_items, n_scans;
     int *counter;
-    int *remaining;
     unsigned long long *t_done;
     unsigned long long *t_start;
 };
+
+constexpr int kItemsPerFetch = 4;
 
 namespace {
 
@@ -53,7 +56,6 @@ __global__ void k_batch_reset(BatchArgs a) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) { *a.counter = 0; *a.t_start = 0ull; }
     for (int s = i; s < a.n_scans; s += gridDim.x * blockDim.x) {
-        a.remaining[s] = a.descs[s].n_tiles;
         a.t_done[s] = 0ull;
     }
 }
@@ -62,53 +64,50 @@ template <int BF, int W, bool D3, int VPL>
 __global__ __launch_bounds__(kBlock) void k_batch32(const BatchArgs a) {
     extern __shared__ __align__(16) float smem[];
     __shared__ int s_item;
-    // Lane 0 is the only lane that touches the work counter.  Each iteration has a
-    // single lane-0 region (completion of the previous item, fetch of the next)
-    // between two barriers, and the exit test reads the item as a scalar: if the
-    // loop were entered through a lane-0-only block, or its exit were a per-lane
-    // value, the compiler may restructure it so that lanes 1..63 keep iterating on
-    // a stale item while lane 0, which would fetch the next one, waits at the exit.
+    // Lane 0 is the only lane that touches the work counter.  Each fetch is a single
+    // lane-0 region between two barriers, and every loop bound is read as a scalar:
+    // if the loop were entered through a lane-0-only block, or its exit were a
+    // per-lane value, the compiler may restructure it so that lanes 1..63 keep
+    // iterating on a stale item while lane 0, which would fetch the next one, waits
+    // at the exit.
     if (threadIdx.x == 0) {
         const unsigned long long t = __builtin_amdgcn_s_memrealtime();
-        const int it = atomicAdd(a.counter, 1);
+        const int it = atomicAdd(a.counter, kItemsPerFetch);
         if (it == 0) *a.t_start = t;
         s_item = it;
     }
     __syncthreads();
-    int item = __builtin_amdgcn_readfirstlane(s_item);
-    while (item < a.n_items) {
-        const int scan = a.item_scan[item];
-        const BatchDesc &d = a.descs[scan];
-        int tx, ty, tz;
-        TileShape<D3, VPL>::get(tx, ty, tz);
-        const int tile = item - d.first_item;
-        TileJob j;
-        j.pos = d.pos;
-        j.tr = d.tr;
-        j.img = d.img;
-        j.M = d.M;
-        j.T = d.T;
-        j.s = d.s;
-        j.t0s = d.t0s;
-        j.g = d.g;
-        j.tx0 = (tile % d.tiles_x) * tx;
-        j.ty0 = ((tile / d.tiles_x) % d.tiles_y) * ty;
-        j.tz0 = (tile / (d.tiles_x * d.tiles_y)) * tz;
-        j.rs = d.rs;
-        j.chunk = d.chunk;
-        j.ms = 0;
-        image_tile<BF, W, D3, VPL>(j, smem);
-        __syncthreads();   // every lane's image stores are issued before the scan counter moves
-        if (threadIdx.x == 0) {
-            __threadfence();
-            if (atomicSub(&a.remaining[scan], 1) == 1) {
-                __threadfence();
-                a.t_done[scan] = __builtin_amdgcn_s_memrealtime();
-            }
-            s_item = atomicAdd(a.counter, 1);
+    int first = __builtin_amdgcn_readfirstlane(s_item);
+    while (first < a.n_items) {
+        const int last = min(first + kItemsPerFetch, a.n_items);
+        for (int item = first; item < last; ++item) {
+            const int scan = a.item_scan[item];
+            const BatchDesc &d = a.descs[scan];
+            int tx, ty, tz;
+            TileShape<D3, VPL>::get(tx, ty, tz);
+            const int tile = item - d.first_item;
+            TileJob j;
+            j.pos = d.pos;
+            j.tr = d.tr;
+            j.img = d.img;
+            j.M = d.M;
+            j.T = d.T;
+            j.s = d.s;
+            j.t0s = d.t0s;
+            j.g = d.g;
+            j.tx0 = (tile % d.tiles_x) * tx;
+            j.ty0 = ((tile / d.tiles_x) % d.tiles_y) * ty;
+            j.tz0 = (tile / (d.tiles_x * d.tiles_y)) * tz;
+            j.rs = d.rs;
+            j.chunk = d.chunk;
+            j.ms = 0;
+            image_tile<BF, W, D3, VPL>(j, smem);
+            __syncthreads();   // every lane's image stores are issued before the stamp
+            if (threadIdx.x == 0) atomicMax(&a.t_done[scan], __builtin_amdgcn_s_memrealtime());
         }
+        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, kItemsPerFetch);
         __syncthreads();
-        item = __builtin_amdgcn_readfirstlane(s_item);
+        first = __builtin_amdgcn_readfirstlane(s_item);
     }
 }
 
@@ -156,7 +155,7 @@ struct uwb_batch_plan {
     // device
     BatchDesc *descs = nullptr;
     int *item_scan = nullptr;
-    int *counters = nullptr;            // [0] work counter, [1..n] remaining tiles
+    int *counters = nullptr;            // [0] work counter
     unsigned long long *stamps = nullptr;   // [0] start, [1..n] done
     int n_items = 0;
     size_t lds = 0;
@@ -189,7 +188,6 @@ BatchArgs args_of(const uwb_batch_plan *p) {
     a.n_items = p->n_items;
     a.n_scans = p->n;
     a.counter = p->counters;
-    a.remaining = p->counters + 1;
     a.t_done = p->stamps + 1;
     a.t_start = p->stamps;
     return a;
@@ -404,13 +402,13 @@ int uwb_batch_plan_create(uwb_batch_plan **plan, const uwb_batch_item *items, in
         return UWB_EHIP;
     }
     if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) { delete p; return UWB_EHIP; }
-    if (hipMalloc(&p->counters, sizeof(int) * (n_scans + 1)) != hipSuccess ||
+    if (hipMalloc(&p->counters, sizeof(int)) != hipSuccess ||
         hipMalloc(&p->stamps, sizeof(unsigned long long) * (n_scans + 1)) != hipSuccess) {
         uwb_batch_plan_destroy(p);
         return UWB_ENOMEM;
     }
     p->key = plan_key(p);
-    uwb_batch_config c = {2, 8, 40, 0};
+    uwb_batch_config c = {4, 8, 40, 0};
     if (cfg) c = *cfg;
     else {
         uwb_batch_config cached;

@@ -13,9 +13,8 @@
 //     deviates from Philox4x32-10 (Salmon et al. 2011), counter (sample pair,
 //     antenna, tag, 0), key (seed low, seed high), Box-Muller (cosine for the even
 //     sample, sine for the odd one).
-// One workgroup per scan; each lane owns 8 consecutive samples of the antenna
-// being synthesised and adds every scatterer's contribution in scatterer order,
-// so the result is deterministic.
+// One workgroup per (scan, antenna); each lane owns 8 consecutive samples and adds
+// every scatterer's contribution in scatterer order, so the result is deterministic.
 #include <cmath>
 
 #include "uwb_internal.h"
@@ -65,13 +64,15 @@ __device__ __forceinline__ float pulse32(float t, float f0, float sigma, float i
     return sinf(6.283185307179586f * f0 * t) * expf(-(t * t) / (2.f * sigma * sigma)) * inv_peak;
 }
 
+// One workgroup per (scan, antenna): every workgroup of a scan redraws the (cheap)
+// scene and the tumour power, then synthesises its antenna's trace.
 __global__ __launch_bounds__(256) void k_gen_disc(const GenArgs a) {
     __shared__ double sx[kMaxScat + 1], sy[kMaxScat + 1], srho[kMaxScat + 1];
     __shared__ double s_tau[kMaxScat + 1];
     __shared__ float s_amp[kMaxScat + 1];
     __shared__ int s_n0[kMaxScat + 1];
     __shared__ double red[256];
-    const int scan = blockIdx.x, tid = threadIdx.x;
+    const int scan = blockIdx.x, i = blockIdx.y, tid = threadIdx.x;
     const unsigned long long seed = a.seeds[scan];
     const int ns = a.n_clutter + 1;
     if (tid == 0) {
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(256) void k_gen_disc(const GenArgs a) {
         }
         srho[0] = 1.0;
         for (int s = 1; s < ns; ++s) srho[s] = 0.1 * r.uniform();
-        if (a.tumours) {
+        if (a.tumours && i == 0) {
             a.tumours[3 * scan + 0] = sx[0];
             a.tumours[3 * scan + 1] = sy[0];
             a.tumours[3 * scan + 2] = 0.0;
@@ -95,8 +96,8 @@ __global__ __launch_bounds__(256) void k_gen_disc(const GenArgs a) {
     const double half = 6.0 * a.sigma;
     // tumour echo power: mean over antennas of its mean square within 3 sigma of arrival
     double pw = 0.0;
-    for (int i = tid; i < a.M; i += 256) {
-        const double ax = a.ant_pos[3 * i], ay = a.ant_pos[3 * i + 1], az = a.ant_pos[3 * i + 2];
+    for (int k = tid; k < a.M; k += 256) {
+        const double ax = a.ant_pos[3 * k], ay = a.ant_pos[3 * k + 1], az = a.ant_pos[3 * k + 2];
         const double dx = sx[0] - ax, dy = sy[0] - ay, dz = -az;
         const double dist = sqrt(dx * dx + dy * dy + dz * dz);
         const double tau = 2.0 * dist / a.v;
@@ -125,47 +126,44 @@ __global__ __launch_bounds__(256) void k_gen_disc(const GenArgs a) {
     }
     const double ps = red[0] / a.M;
     const double sigma_n = sqrt(ps / pow(10.0, a.snr_db / 10.0));
+    // this workgroup's antenna
+    const double ax = a.ant_pos[3 * i], ay = a.ant_pos[3 * i + 1], az = a.ant_pos[3 * i + 2];
+    for (int s = tid; s < ns; s += 256) {
+        const double dx = sx[s] - ax, dy = sy[s] - ay, dz = -az;
+        const double dist = sqrt(dx * dx + dy * dy + dz * dz);
+        const double tau = 2.0 * dist / a.v;
+        s_tau[s] = tau - a.t0;
+        s_amp[s] = (float)(srho[s] * (0.01 / dist) * (0.01 / dist));
+        s_n0[s] = (int)floor((tau - half - a.t0) / a.dt);
+    }
     __syncthreads();
-    for (int i = 0; i < a.M; ++i) {
-        const double ax = a.ant_pos[3 * i], ay = a.ant_pos[3 * i + 1], az = a.ant_pos[3 * i + 2];
-        for (int s = tid; s < ns; s += 256) {
-            const double dx = sx[s] - ax, dy = sy[s] - ay, dz = -az;
-            const double dist = sqrt(dx * dx + dy * dy + dz * dz);
-            const double tau = 2.0 * dist / a.v;
-            s_tau[s] = tau - a.t0;
-            s_amp[s] = (float)(srho[s] * (0.01 / dist) * (0.01 / dist));
-            s_n0[s] = (int)floor((tau - half - a.t0) / a.dt);
-        }
-        __syncthreads();
-        float acc[8];
-        const int m0 = tid * 8;
-        for (int q = 0; q < 8; ++q) acc[q] = 0.f;
-        if (m0 < a.T) {
-            for (int s = 0; s < ns; ++s) {
-                const int n0 = s_n0[s];
-                if (n0 + 40 < m0 || n0 > m0 + 7) continue;
-                const double tau = s_tau[s];
-                const float amp = s_amp[s];
-                for (int q = 0; q < 8; ++q) {
-                    const float t = (float)((double)(m0 + q) * a.dt - tau);   // difference in FP64, pulse in FP32
-                    acc[q] += amp * pulse32(t, f0, sigma, inv_peak);
-                }
+    float acc[8];
+    const int m0 = tid * 8;
+    for (int q = 0; q < 8; ++q) acc[q] = 0.f;
+    if (m0 < a.T) {
+        for (int s = 0; s < ns; ++s) {
+            const int n0 = s_n0[s];
+            if (n0 + 40 < m0 || n0 > m0 + 7) continue;
+            const double tau = s_tau[s];
+            const float amp = s_amp[s];
+            for (int q = 0; q < 8; ++q) {
+                const float t = (float)((double)(m0 + q) * a.dt - tau);   // difference in FP64, pulse in FP32
+                acc[q] += amp * pulse32(t, f0, sigma, inv_peak);
             }
-            // noise: pairs (m0/2 .. m0/2 + 3) of this antenna
-            for (int pq = 0; pq < 4; ++pq) {
-                uint32_t c[4] = {(uint32_t)(m0 / 2 + pq), (uint32_t)i, kNoiseTag, 0u};
-                philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
-                const double u1 = ((double)c[0] + 0.5) * (1.0 / 4294967296.0);
-                const double u2 = ((double)c[1] + 0.5) * (1.0 / 4294967296.0);
-                const double rr = sqrt(-2.0 * log(u1));
-                acc[2 * pq] = (float)((double)acc[2 * pq] + sigma_n * rr * cos(2.0 * M_PI * u2));
-                acc[2 * pq + 1] = (float)((double)acc[2 * pq + 1] + sigma_n * rr * sin(2.0 * M_PI * u2));
-            }
-            float *out = a.traces + ((size_t)scan * a.M + i) * a.T;
-            for (int q = 0; q < 8; ++q)
-                if (m0 + q < a.T) out[m0 + q] = acc[q];
         }
-        __syncthreads();
+        // noise: pairs (m0/2 .. m0/2 + 3) of this antenna
+        for (int pq = 0; pq < 4; ++pq) {
+            uint32_t c[4] = {(uint32_t)(m0 / 2 + pq), (uint32_t)i, kNoiseTag, 0u};
+            philox4x32_10(c, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+            const double u1 = ((double)c[0] + 0.5) * (1.0 / 4294967296.0);
+            const double u2 = ((double)c[1] + 0.5) * (1.0 / 4294967296.0);
+            const double rr = sqrt(-2.0 * log(u1));
+            acc[2 * pq] = (float)((double)acc[2 * pq] + sigma_n * rr * cos(2.0 * M_PI * u2));
+            acc[2 * pq + 1] = (float)((double)acc[2 * pq + 1] + sigma_n * rr * sin(2.0 * M_PI * u2));
+        }
+        float *out = a.traces + ((size_t)scan * a.M + i) * a.T;
+        for (int q = 0; q < 8; ++q)
+            if (m0 + q < a.T) out[m0 + q] = acc[q];
     }
 }
 
@@ -203,6 +201,7 @@ extern "C" int uwb_generate_disc_scans(const uwb_gen_recipe *r, const float *ant
     a.peak = r->pulse_peak;
     a.salt = r->salt;
     if (a.T > 256 * 8) return UWB_EUNSUPPORTED;   // one pass of 8 samples per lane
-    hipLaunchKernelGGL(k_gen_disc, dim3(n), dim3(256), 0, (hipStream_t)stream, a);
+    if (a.M > 65535) return UWB_EUNSUPPORTED;
+    hipLaunchKernelGGL(k_gen_disc, dim3(n, a.M), dim3(256), 0, (hipStream_t)stream, a);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }
