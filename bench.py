@@ -71,7 +71,9 @@ def main():
     ap.add_argument("--c5-eval", type=int, default=10_000, help="held-out scans for its localisation error")
     ap.add_argument("--c5-epochs", type=float, default=1.0)
     ap.add_argument("--no-c5", action="store_true", help="skip training / evaluating the learned proposer")
-    ap.add_argument("--ms-batch", type=int, default=64, help="multistatic scans (12-antenna ring, 200x200 grid)")
+    ap.add_argument("--c4-scans", type=int, default=1024, help="uneven scans of the batched-serving plan")
+    ap.add_argument("--no-c4", action="store_true", help="skip the batched-serving measurement")
+    ap.add_argument("--ms-batch", type=int, default=512, help="multistatic scans (12-antenna ring, 200x200 grid)")
     ap.add_argument("--no-ms", action="store_true", help="skip the multistatic and no-tumour-check measurements")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (HBM counter reference)")
@@ -217,6 +219,8 @@ def main():
 
     if not args.no_c5:
         out["learned"] = learned_block(args, uwb, synth, dev)
+    if not args.no_c4:
+        out["batched_serving"] = c4_block(args, uwb, synth, dev)
     if not args.no_ms:
         out["multistatic"] = multistatic_block(args, uwb, synth, dev)
         out["tumour_check"] = tumour_check_block(uwb, synth, dev)
@@ -253,6 +257,32 @@ def _timed(fn, reps=5):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def c4_block(args, uwb, synth, dev):
+    """Batched serving of uneven scans: one persistent graph-captured launch over C4's mixed batch (M in
+    {16..64}, T in {1024..4096}, side in {64..512}, seeds 1000 + i), autotuned on the batch itself; scans/s and the
+    per-scan completion-time percentiles within a launch."""
+    import numpy as np
+    import torch
+    n = args.c4_scans
+    scans = [synth.c4_scan(1000 + k) for k in range(n)]
+    devs = [uwb.DeviceScan.from_host(s, dev) for s in scans]
+    outs = [torch.empty((1, s.grid.dims[1], s.grid.dims[0]), dtype=torch.float32, device=dev) for s in scans]
+    va = sum(s.n_ant * s.grid.dims[0] * s.grid.dims[1] for s in scans)
+    res = {"workload": "C4: uneven monostatic scans, antennas 16-64, samples 1024-4096, grid side 64-512, window 11",
+           "scans": n, "voxel_antenna_per_launch": int(va)}
+    for bf, name in ((0, "das"), (1, "dmas")):
+        plan = uwb.BatchPlan([(d, s.grid, o) for d, s, o in zip(devs, scans, outs)], bf)
+        cfg = plan.autotune(3)
+        ms = _timed(plan.run, reps=10)
+        plan.run()
+        ts = plan.timestamps_ns() / 1e6
+        res[name] = {"scans_per_s": round(n / (ms * 1e-3), 1), "ms_per_launch": round(ms, 4),
+                     "gvas": round(va / (ms * 1e-3) / 1e9, 2), "latency_ms_p50": round(float(np.percentile(ts, 50)), 4),
+                     "latency_ms_p99": round(float(np.percentile(ts, 99)), 4), "config": cfg}
+        plan.close()
+    return res
 
 
 def multistatic_block(args, uwb, synth, dev):
