@@ -42,6 +42,10 @@ void tile_shape(bool d3, int vpl, int *tx, int *ty, int *tz) {
 
 namespace {
 
+// Voxels per lane of the grid-mapped kernel: 4 (tiles of 16 x 64 in 2D, 8 x 8 x 16 in 3D)
+// measured a few per cent faster than 2 for DAS and DMAS on the 512 x 512 batch.
+constexpr int kImageVpl = 4;
+
 struct Args {
     ScanSet ss;
     GridView g;
@@ -54,7 +58,7 @@ struct Args {
 
 template <int BF, int W, bool D3, bool MS>
 __global__ __launch_bounds__(kBlock) void k_image32(const Args a) {
-    constexpr int VPL = 2;
+    constexpr int VPL = kImageVpl;
     extern __shared__ float smem[];
     const int scan = blockIdx.y;
     const ScanConst sc = scan_const(a.ss, scan);
@@ -107,7 +111,7 @@ int launch_image32(int bf, const ScanSet &ss, int n_scans, const GridView &g, in
                    hipStream_t stream) {
     const bool d3 = g.dims[2] > 1;
     int tx, ty, tz;
-    tile_shape(d3, 2, &tx, &ty, &tz);
+    tile_shape(d3, kImageVpl, &tx, &ty, &tz);
     Args a;
     a.ss = ss;
     a.g = g;
