@@ -12,7 +12,17 @@ constexpr int kLdsBudget = 40 * 1024;   // bytes of staged samples per workgroup
 // Every odd window 1..31 is compiled.
 #define UWB_WINDOWS(X) X(1) X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) X(27) X(29) X(31)
 
-int staged_samples(double s, double ex, double ey, double ez, int window, int T);
+// Staged samples per channel for a tile spanning (ex, ey, ez) metres: the delay
+// range over any box is at most s * |box diagonal| (triangle inequality; for a
+// bistatic channel each leg contributes s/2 of it); add the window and margins;
+// never more than the whole zero-padded trace.
+__host__ __device__ inline int staged_samples(double s, double ex, double ey, double ez, int window, int T) {
+    const double span = s * sqrt(ex * ex + ey * ey + ez * ez);
+    double rs = ceil(span) + window + 6;
+    const double cap = (double)T + 2.0 * window + 2.0;
+    if (!(rs <= cap)) rs = cap;
+    return (int)rs;
+}
 void tile_shape(bool d3, int vpl, int *tx, int *ty, int *tz);
 
 // One tile of one scan.
@@ -97,6 +107,10 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
             for (int k = 0; k < (BF == UWB_DMAS ? W : 1); ++k) pre[v][k] = 0.f;
     }
 
+    float dtx[MS ? VPL : 1];   // bistatic: current transmitter's leg (sample units) minus t0s, per voxel
+#pragma unroll
+    for (int v = 0; v < (MS ? VPL : 1); ++v) dtx[v] = 0.f;
+
     for (int a0 = 0; a0 < M; a0 += chunk) {
         const int nch = min(chunk, M - a0);
         __syncthreads();   // previous chunk (or previous tile) fully consumed
@@ -149,50 +163,43 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
         }
         __syncthreads();
 
+        // bistatic: receiver of the chunk's first channel (channels run in order, so a
+        // transmitter's distances carry over a chunk boundary)
+        int rxi = MS ? a0 % j.ms : 0;
         for (int jj = 0; jj < nch; ++jj) {
             const float4 e = tab[TE * jj];
             const float4 er = tab[TE * jj + (MS ? 1 : 0)];
             const int base = __float_as_int(e.w);
             const int lob = jj * rs, hib = jj * rs + rs - (W + 1);
-            const float dx = fmaf(fx, qx, e.x);
+            // squared distance from the lane's voxels to one leg's antenna: leg_d2 forms the part
+            // shared by the lane's voxels, leg_v adds voxel v's own coordinate
+            auto leg_d2 = [&](const float4 &t, float &part) {
+                const float dx = fmaf(fx, qx, t.x);
+                if (!D3) part = fmaf(dx, dx, t.z);
+                else { const float dy = fmaf(fy[0], qy, t.y); part = fmaf(dy, dy, dx * dx); }
+            };
+            auto leg_v = [&](const float4 &t, float part, int v) {
+                if (!D3) { const float dy = fmaf(fy[v], qy, t.y); return fmaf(dy, dy, part); }
+                const float dz = fmaf(fz[v], qz, t.z);
+                return fmaf(dz, dz, part);
+            };
             float part, partr = 0.f;
-            if (!D3) {
-                part = fmaf(dx, dx, e.z);
-            } else {
-                const float dy = fmaf(fy[0], qy, e.y);
-                part = fmaf(dy, dy, dx * dx);
-            }
             if (MS) {
-                const float rx_ = fmaf(fx, qx, er.x);
-                if (!D3) {
-                    partr = fmaf(rx_, rx_, er.z);
-                } else {
-                    const float ry_ = fmaf(fy[0], qy, er.y);
-                    partr = fmaf(ry_, ry_, rx_ * rx_);
+                if (rxi == 0) {   // a new transmitter (uniform over the workgroup): its leg per voxel
+                    leg_d2(e, part);
+#pragma unroll
+                    for (int v = 0; v < VPL; ++v) dtx[v] = __builtin_amdgcn_sqrtf(leg_v(e, part, v)) - t0s;
                 }
+                rxi = rxi + 1 == j.ms ? 0 : rxi + 1;
+                leg_d2(er, partr);
+            } else {
+                leg_d2(e, part);
             }
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
-                float d2;
-                if (!D3) {
-                    const float dy = fmaf(fy[v], qy, e.y);
-                    d2 = fmaf(dy, dy, part);
-                } else {
-                    const float dz = fmaf(fz[v], qz, e.z);
-                    d2 = fmaf(dz, dz, part);
-                }
-                float tau = __builtin_amdgcn_sqrtf(d2) - t0s;
-                if (MS) {
-                    float d2r;
-                    if (!D3) {
-                        const float dy = fmaf(fy[v], qy, er.y);
-                        d2r = fmaf(dy, dy, partr);
-                    } else {
-                        const float dz = fmaf(fz[v], qz, er.z);
-                        d2r = fmaf(dz, dz, partr);
-                    }
-                    tau += __builtin_amdgcn_sqrtf(d2r);
-                }
+                float tau;
+                if (MS) tau = dtx[v] + __builtin_amdgcn_sqrtf(leg_v(er, partr, v));
+                else tau = __builtin_amdgcn_sqrtf(leg_v(e, part, v)) - t0s;
                 const float fl = floorf(tau);
                 const float f = tau - fl;
                 const float g = 1.f - f;

@@ -24,17 +24,6 @@
 
 namespace uwb {
 
-// Staged samples per antenna for a tile spanning (ex, ey, ez) metres: the delay
-// range over any box is at most s * |box diagonal| (triangle inequality); add
-// the window and margins; never more than the whole zero-padded trace.
-int staged_samples(double s, double ex, double ey, double ez, int window, int T) {
-    const double span = s * sqrt(ex * ex + ey * ey + ez * ez);
-    double rs = ceil(span) + window + 6;
-    const double cap = (double)T + 2.0 * window + 2.0;
-    if (!(rs <= cap)) rs = cap;
-    return (int)rs;
-}
-
 void tile_shape(bool d3, int vpl, int *tx, int *ty, int *tz) {
     if (d3) { *tx = 8; *ty = 8; *tz = 4 * vpl; }
     else { *tx = 16; *ty = 16 * vpl; *tz = 1; }

@@ -3,16 +3,24 @@
 // lattice of the whole grid (paper walk) and the full-resolution ROI.
 //
 // The kernel mirrors the FP32 imaging kernel's structure in double precision.
-// A workgroup owns a tile of 16 x 16 (2D) or 8 x 8 x 4 (3D) lattice points, one
-// point per lane.  For a chunk of antennas it derives (in FP64) the interval of
-// samples any point of the tile can reach, stages those intervals from HBM into
-// LDS, and then every lane computes its delay for each antenna once (Eq. (1)),
-// reads the W+1 staged samples around it and accumulates the linearly
-// interpolated window into W FP64 accumulators (Eq. (3) DAS, or the prefix form
-// P_k += s_k S_k, S_k += s_k of the Section II-B pairwise DMAS sum).  Positions
-// are formed exactly as the rest of the walk forms them (origin + index * pitch
-// on the finest grid), antennas are taken in order, and every point's energy is
-// written once: the values do not depend on the tile shape.
+// A workgroup evaluates 256 lattice points of one scan at a time, one point per
+// lane: a tile of 16 x 16 (2D) or 8 x 8 x 4 (3D) points when the scan's lattice
+// is a whole number of such tiles, else a band of 256 consecutive points in
+// lattice order, so that a ragged lattice (a ROI) idles at most part of its last
+// band instead of the edges of every tile row.  For a chunk of channels it
+// derives (in FP64) the interval of samples any of its points can reach, stages
+// those intervals from HBM into LDS, and then every lane computes its delay for
+// each channel once (Eq. (1), or Eq. (2) for a bistatic channel, whose
+// transmitter distance is kept while consecutive channels share the
+// transmitter), reads the W+1 staged samples around it and accumulates the
+// linearly interpolated window into W FP64 accumulators (Eq. (3) DAS, or the
+// prefix form P_k += s_k S_k, S_k += s_k of the Section II-B pairwise DMAS sum).
+// Positions are formed exactly as the rest of the walk forms them (origin +
+// index * pitch on the finest grid), channels are taken in order, and every
+// point's energy is written once: the values depend neither on the tiling nor on
+// the staging.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 
 #include "image32.h"
@@ -21,7 +29,9 @@
 namespace uwb {
 namespace {
 
-constexpr int kTabBytes = 64;   // per staged channel: transmitter and receiver positions, first staged sample
+constexpr int kTabBytes = 64;          // per staged channel: transmitter and receiver positions, first staged sample
+constexpr int kLdsPerCu = 160 * 1024;  // LDS of one CU
+constexpr int kGridLdsMax = 64 * 1024; // staging budget of one workgroup, at most
 
 template <bool D3> struct Tile64 {
     static constexpr int X = D3 ? 8 : 16, Y = D3 ? 8 : 16, Z = D3 ? 4 : 1;
@@ -31,10 +41,25 @@ struct Lat {
     int x0[3], step, cnt[3];
 };
 
-template <int BF, int W, bool D3>
-__global__ __launch_bounds__(kBlock) void k_grid64(const Grid64Args a) {
+// One group of up to 256 points of the lattice L: lane point k (lattice indices,
+// valid or not), the group's bounding box lo..hi (lattice indices) and the
+// output offset of the lane's point.
+struct Group {
+    int k[3], lo[3], hi[3];
+    int64_t p;
+    bool valid;
+};
+
+template <int BF, int W, bool MS>
+__device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const Group &G, unsigned char *dsm);
+
+// MS: the scans' channels are the transmitter-receiver pairs of a multistatic array.
+// DAS with windows up to 13 samples fits five waves per SIMD without spilling: asked of
+// the register allocator, which otherwise settles one wave lower.
+template <int BF, int W, bool D3, bool MS>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BF == UWB_DAS && W <= 13 ? 5 : 1)))
+void k_grid64(const Grid64Args a) {
     using TS = Tile64<D3>;
-    constexpr int H = (W - 1) / 2;
     extern __shared__ __align__(16) unsigned char dsm[];
     const int scan = blockIdx.y;
     const int tid = threadIdx.x;
@@ -61,45 +86,68 @@ __global__ __launch_bounds__(kBlock) void k_grid64(const Grid64Args a) {
         for (int d = 0; d < 3; ++d) { L.x0[d] = a.x0[d]; L.cnt[d] = a.cnt[d]; }
         L.step = a.step;
     }
+    const int c0 = L.cnt[0], c1 = L.cnt[1], c2 = L.cnt[2];
+    const int64_t n = (int64_t)c0 * c1 * c2;
     // a lattice larger than its output slot (never, for a planned walk) is not written
-    if ((int64_t)L.cnt[0] * L.cnt[1] * L.cnt[2] + a.out_offset > a.out_stride) return;
-    const int t = blockIdx.x;
-    const int tx0 = (t % a.tiles[0]) * TS::X;
-    const int ty0 = ((t / a.tiles[0]) % a.tiles[1]) * TS::Y;
-    const int tz0 = (t / (a.tiles[0] * a.tiles[1])) * TS::Z;
-    if (tx0 >= L.cnt[0] || ty0 >= L.cnt[1] || tz0 >= L.cnt[2]) return;   // uniform per workgroup
+    if (n < 1 || n + a.out_offset > a.out_stride) return;
+    const bool tiled = c0 % TS::X == 0 && c1 % TS::Y == 0 && c2 % TS::Z == 0;
+    const int64_t ngroups = (n + kBlock - 1) / kBlock;   // tiles or bands: the same count when tiled
+    const int64_t t = blockIdx.x;   // the launch holds enough workgroups for the largest lattice
+    if (t >= ngroups) return;       // uniform per workgroup
+    Group G;
+    if (tiled) {
+        const int ntx = c0 / TS::X, nty = c1 / TS::Y;
+        G.lo[0] = (int)(t % ntx) * TS::X;
+        G.lo[1] = (int)((t / ntx) % nty) * TS::Y;
+        G.lo[2] = (int)(t / ((int64_t)ntx * nty)) * TS::Z;
+        G.hi[0] = G.lo[0] + TS::X - 1;
+        G.hi[1] = G.lo[1] + TS::Y - 1;
+        G.hi[2] = G.lo[2] + TS::Z - 1;
+        if (!D3) { G.k[0] = G.lo[0] + (tid & 15); G.k[1] = G.lo[1] + (tid >> 4); G.k[2] = 0; }
+        else { G.k[0] = G.lo[0] + (tid & 7); G.k[1] = G.lo[1] + ((tid >> 3) & 7); G.k[2] = G.lo[2] + (tid >> 6); }
+        G.valid = true;
+        G.p = ((int64_t)G.k[2] * c1 + G.k[1]) * c0 + G.k[0];
+    } else {
+        const int64_t p0 = t * kBlock, p1 = min(p0 + kBlock, n) - 1;
+        G.valid = p0 + tid <= p1;
+        G.p = min(p0 + tid, p1);
+        const int64_t s01 = (int64_t)c0 * c1;
+        G.k[0] = (int)(G.p % c0); G.k[1] = (int)((G.p / c0) % c1); G.k[2] = (int)(G.p / s01);
+        const int ax = (int)(p0 % c0), ay = (int)((p0 / c0) % c1), az = (int)(p0 / s01);
+        const int bx = (int)(p1 % c0), by = (int)((p1 / c0) % c1), bz = (int)(p1 / s01);
+        // a band within one row spans its own columns; across rows, whole rows; across slabs, whole slabs
+        G.lo[2] = az; G.hi[2] = bz;
+        G.lo[1] = az == bz ? ay : 0; G.hi[1] = az == bz ? by : c1 - 1;
+        G.lo[0] = (az == bz && ay == by) ? ax : 0; G.hi[0] = (az == bz && ay == by) ? bx : c0 - 1;
+    }
+    grid64_group<BF, W, MS>(a, L, scan, G, dsm);
+}
 
+template <int BF, int W, bool MS>
+__device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const Group &G, unsigned char *dsm) {
+    constexpr int H = (W - 1) / 2;
+    const int tid = threadIdx.x;
     const ScanConst sc = scan_const(a.ss, scan);
     const int M = a.ss.n_ant, T = a.ss.n_samp;
-    const int rs = a.rs, chunk = a.chunk;
-    double *tab = reinterpret_cast<double *>(dsm);                        // [chunk][8]
-    float *stage = reinterpret_cast<float *>(dsm + (size_t)kTabBytes * chunk);   // [chunk][rs]
+    double *tab = reinterpret_cast<double *>(dsm);   // [chunk][8]
 
-    // lane -> lattice point -> finest indices -> position
-    int kx, ky, kz;
-    if (!D3) { kx = tx0 + (tid & 15); ky = ty0 + (tid >> 4); kz = 0; }
-    else { kx = tx0 + (tid & 7); ky = ty0 + ((tid >> 3) & 7); kz = tz0 + (tid >> 6); }
-    const bool valid = kx < L.cnt[0] && ky < L.cnt[1] && kz < L.cnt[2];
-    const int ix = L.x0[0] + L.step * min(kx, L.cnt[0] - 1);
-    const int iy = L.x0[1] + L.step * min(ky, L.cnt[1] - 1);
-    const int iz = L.x0[2] + L.step * min(kz, L.cnt[2] - 1);
-    const double rx = a.g.origin[0] + ix * a.g.pitch[0];
-    const double ry = a.g.origin[1] + iy * a.g.pitch[1];
-    const double rz = a.g.origin[2] + iz * a.g.pitch[2];
+    // lane point -> finest indices -> position
+    const double rx = a.g.origin[0] + (L.x0[0] + L.step * G.k[0]) * a.g.pitch[0];
+    const double ry = a.g.origin[1] + (L.x0[1] + L.step * G.k[1]) * a.g.pitch[1];
+    const double rz = a.g.origin[2] + (L.x0[2] + L.step * G.k[2]) * a.g.pitch[2];
 
-    // the tile's bounding box (metres) and whether this scan's spans fit the staging stride
+    // the group's bounding box (metres); its staging stride and the channels per chunk follow from it
     double blo[3], bhi[3];
-    {
-        const int k0[3] = {tx0, ty0, tz0};
-        const int ext[3] = {TS::X, TS::Y, TS::Z};
-        for (int d = 0; d < 3; ++d) {
-            const int k1 = min(k0[d] + ext[d], L.cnt[d]) - 1;
-            blo[d] = a.g.origin[d] + (L.x0[d] + L.step * k0[d]) * a.g.pitch[d];
-            bhi[d] = a.g.origin[d] + (L.x0[d] + L.step * k1) * a.g.pitch[d];
-        }
+    for (int d = 0; d < 3; ++d) {
+        blo[d] = a.g.origin[d] + (L.x0[d] + L.step * G.lo[d]) * a.g.pitch[d];
+        bhi[d] = a.g.origin[d] + (L.x0[d] + L.step * G.hi[d]) * a.g.pitch[d];
     }
-    const double ex = bhi[0] - blo[0], ey = bhi[1] - blo[1], ez = bhi[2] - blo[2];
-    const bool fits = ceil(sc.s * sqrt(ex * ex + ey * ey + ez * ez)) + W + 6 <= (double)rs || rs >= T + 2 * W + 2;
+    // (uniform, but computed on the vector unit: kept in scalar registers, so that the
+    // channel loop's counters stay scalar)
+    const int rs = __builtin_amdgcn_readfirstlane(
+        staged_samples(sc.s, bhi[0] - blo[0], bhi[1] - blo[1], bhi[2] - blo[2], W, T));
+    const int chunk = __builtin_amdgcn_readfirstlane(min(a.lds_bytes / (kTabBytes + 4 * rs), min(M, kBlock)));
+    float *stage = reinterpret_cast<float *>(dsm + (size_t)kTabBytes * chunk);   // [chunk][rs]
 
     double S[W], P[BF == UWB_DMAS ? W : 1];
 #pragma unroll
@@ -107,18 +155,19 @@ __global__ __launch_bounds__(kBlock) void k_grid64(const Grid64Args a) {
 #pragma unroll
     for (int k = 0; k < (BF == UWB_DMAS ? W : 1); ++k) P[k] = 0.0;
 
-    for (int a0 = 0; a0 < M; a0 += chunk) {
+    double dtx = 0.0;   // bistatic: the current transmitter's distance
+    for (int a0 = 0; chunk > 0 && a0 < M; a0 += chunk) {
         const int nch = min(chunk, M - a0);
-        __syncthreads();   // previous chunk consumed
+        __syncthreads();   // previous chunk (or group) consumed
         if (tid < nch) {
             const int i = a0 + tid;
             // transmitter and receiver of the channel (the same antenna when monostatic)
-            const float *at = sc.pos + 3 * (sc.ms ? i / sc.ms : i), *ar = sc.pos + 3 * (sc.ms ? i % sc.ms : i);
+            const float *at = sc.pos + 3 * (MS ? i / sc.ms : i), *ar = sc.pos + 3 * (MS ? i % sc.ms : i);
             double dmin = 0.0;
             for (int leg = 0; leg < 2; ++leg) {
                 const float *ap = leg == 0 ? at : ar;
                 const double ax = (double)ap[0], ay = (double)ap[1], az = (double)ap[2];
-                // nearest point of the tile's box to the antenna: earliest delay of the tile
+                // nearest point of the group's box to the antenna: earliest delay of the group
                 const double nx = fmin(fmax(ax, blo[0]), bhi[0]) - ax;
                 const double ny = fmin(fmax(ay, blo[1]), bhi[1]) - ay;
                 const double nz = fmin(fmax(az, blo[2]), bhi[2]) - az;
@@ -146,17 +195,27 @@ __global__ __launch_bounds__(kBlock) void k_grid64(const Grid64Args a) {
             }
         }
         __syncthreads();
+        // bistatic: receiver of the chunk's first channel (channels run in order, so a
+        // transmitter's distance carries over a chunk boundary)
+        int rxi = MS ? a0 % sc.ms : 0;
         for (int jj = 0; jj < nch; ++jj) {
-            const double dx = rx - tab[8 * jj + 0];
-            const double dy = ry - tab[8 * jj + 1];
-            const double dz = rz - tab[8 * jj + 2];
             double tau;
-            if (sc.ms) {   // Eq. (2): both legs
+            if (MS) {   // Eq. (2): both legs; the transmitter's leg is shared by its receivers
+                if (rxi == 0) {   // a new transmitter (uniform over the workgroup)
+                    const double dx = rx - tab[8 * jj + 0];
+                    const double dy = ry - tab[8 * jj + 1];
+                    const double dz = rz - tab[8 * jj + 2];
+                    dtx = sqrt(dx * dx + dy * dy + dz * dz);
+                }
+                rxi = rxi + 1 == sc.ms ? 0 : rxi + 1;
                 const double ux = rx - tab[8 * jj + 3];
                 const double uy = ry - tab[8 * jj + 4];
                 const double uz = rz - tab[8 * jj + 5];
-                tau = 0.5 * sc.s * (sqrt(dx * dx + dy * dy + dz * dz) + sqrt(ux * ux + uy * uy + uz * uz)) - sc.t0s;
-            } else {
+                tau = 0.5 * sc.s * (dtx + sqrt(ux * ux + uy * uy + uz * uz)) - sc.t0s;
+            } else {    // Eq. (1)
+                const double dx = rx - tab[8 * jj + 0];
+                const double dy = ry - tab[8 * jj + 1];
+                const double dz = rz - tab[8 * jj + 2];
                 tau = sc.s * sqrt(dx * dx + dy * dy + dz * dz) - sc.t0s;
             }
             const double fl = floor(tau);
@@ -182,29 +241,70 @@ __global__ __launch_bounds__(kBlock) void k_grid64(const Grid64Args a) {
         const double q = BF == UWB_DMAS ? P[k] : S[k];
         e += q * q;
     }
-    if (!fits) e = __builtin_nan("");
-    if (valid) {
-        const int64_t p = ((int64_t)kz * L.cnt[1] + ky) * L.cnt[0] + kx;
-        a.out64[(int64_t)scan * a.out_stride + a.out_offset + p] = e;
-        if (a.out32) a.out32[(int64_t)scan * a.out32_stride + p] = (float)e;
+    if (chunk < 1) e = __builtin_nan("");   // a span longer than the staging space (rejected on the host)
+    if (G.valid) {
+        a.out64[(int64_t)scan * a.out_stride + a.out_offset + G.p] = e;
+        if (a.out32) a.out32[(int64_t)scan * a.out32_stride + G.p] = (float)e;
     }
 }
 
+// Staging budget per workgroup: the CU's LDS shared by as many workgroups as the
+// kernel's registers let run at once (queried once per instantiation), at most kGridLdsMax.
+int lds_budget(const void *kern, std::atomic<int> &cache) {
+    int b = cache.load(std::memory_order_relaxed);
+    if (b > 0) return b;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kBlock, 0) != hipSuccess || nb < 1) nb = 5;
+    b = std::min(kGridLdsMax, (kLdsPerCu / nb) & ~255);
+    cache.store(b, std::memory_order_relaxed);
+    return b;
+}
+
+template <int BF, int W, bool D3, bool MS>
+int launch_k(dim3 grid, Grid64Args a, int rs_max, hipStream_t st) {
+    static std::atomic<int> budget;
+    const int lim = lds_budget(reinterpret_cast<const void *>(&k_grid64<BF, W, D3, MS>), budget);
+    if (kTabBytes + 4 * rs_max > lim) return UWB_EUNSUPPORTED;   // not even one channel's span fits
+    a.lds_bytes = (int)std::min<int64_t>((int64_t)(kTabBytes + 4 * rs_max) * std::min(a.ss.n_ant, kBlock), lim);
+    hipLaunchKernelGGL((k_grid64<BF, W, D3, MS>), grid, dim3(kBlock), a.lds_bytes, st, a);
+    return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
+}
+
+// rs_max: staged samples per channel of the widest group of the launch.
 template <int BF, int W>
-hipError_t launch_w(bool d3, dim3 grid, size_t lds, hipStream_t st, const Grid64Args &a) {
-    if (d3) hipLaunchKernelGGL((k_grid64<BF, W, true>), grid, dim3(kBlock), lds, st, a);
-    else hipLaunchKernelGGL((k_grid64<BF, W, false>), grid, dim3(kBlock), lds, st, a);
-    return hipGetLastError();
+int launch_w(bool d3, dim3 grid, const Grid64Args &a, int rs_max, hipStream_t st) {
+    if (a.ss.ms) return d3 ? launch_k<BF, W, true, true>(grid, a, rs_max, st) : launch_k<BF, W, false, true>(grid, a, rs_max, st);
+    return d3 ? launch_k<BF, W, true, false>(grid, a, rs_max, st) : launch_k<BF, W, false, false>(grid, a, rs_max, st);
 }
 
 template <int BF>
-hipError_t launch_bf(int window, bool d3, dim3 grid, size_t lds, hipStream_t st, const Grid64Args &a) {
+int launch_bf(int window, bool d3, dim3 grid, const Grid64Args &a, int rs_max, hipStream_t st) {
     switch (window) {
-#define UWB_W(w) case w: return launch_w<BF, w>(d3, grid, lds, st, a);
+#define UWB_W(w) case w: return launch_w<BF, w>(d3, grid, a, rs_max, st);
         UWB_WINDOWS(UWB_W)
 #undef UWB_W
     }
-    return hipErrorInvalidValue;
+    return UWB_EINVAL;
+}
+
+// Largest bounding box (lattice steps per axis) of the groups the kernel forms on a
+// cnt[0] x cnt[1] x cnt[2] lattice: a tile, or the bands of 256 consecutive points.
+void group_extent(const int *cnt, bool d3, int64_t ext[3]) {
+    const int tx = d3 ? 8 : 16, ty = d3 ? 8 : 16, tz = d3 ? 4 : 1;
+    if (cnt[0] % tx == 0 && cnt[1] % ty == 0 && cnt[2] % tz == 0) {
+        ext[0] = tx - 1; ext[1] = ty - 1; ext[2] = tz - 1;
+        return;
+    }
+    const int64_t c0 = cnt[0], c1 = cnt[1], n = c0 * c1 * cnt[2];
+    ext[0] = ext[1] = ext[2] = 0;
+    for (int64_t p0 = 0; p0 < n; p0 += kBlock) {
+        const int64_t p1 = std::min<int64_t>(p0 + kBlock, n) - 1;
+        const int64_t az = p0 / (c0 * c1), bz = p1 / (c0 * c1);
+        const int64_t ay = (p0 / c0) % c1, by = (p1 / c0) % c1;
+        ext[2] = std::max(ext[2], bz - az);
+        ext[1] = std::max(ext[1], az == bz ? by - ay : c1 - 1);
+        ext[0] = std::max(ext[0], (az == bz && ay == by) ? p1 % c0 - p0 % c0 : c0 - 1);
+    }
 }
 
 }  // namespace
@@ -213,27 +313,22 @@ hipError_t launch_bf(int window, bool d3, dim3 grid, size_t lds, hipStream_t st,
 // max_step: finest voxels between neighbouring points.
 int launch_grid64(Grid64Args a, const int *max_cnt, int max_step, int n_scans, hipStream_t st) {
     const bool d3 = a.g.dims[2] > 1;
-    const int tx = d3 ? 8 : 16, ty = d3 ? 8 : 16, tz = d3 ? 4 : 1;
-    a.tiles[0] = (max_cnt[0] + tx - 1) / tx;
-    a.tiles[1] = (max_cnt[1] + ty - 1) / ty;
-    a.tiles[2] = (max_cnt[2] + tz - 1) / tz;
-    const int64_t tiles = (int64_t)a.tiles[0] * a.tiles[1] * a.tiles[2];
-    if (tiles < 1 || n_scans < 1) return UWB_OK;
-    if (tiles > 0x7fffffff || n_scans > 65535) return UWB_EUNSUPPORTED;
-    // staging stride from the largest samples-per-metre of the batch and the largest tile extent
+    const int64_t points = (int64_t)max_cnt[0] * max_cnt[1] * max_cnt[2];
+    if (points < 1 || n_scans < 1) return UWB_OK;
+    const int64_t wgs = (points + kBlock - 1) / kBlock;
+    if (wgs > 0x7fffffff || n_scans > 65535) return UWB_EUNSUPPORTED;
+    // LDS: every channel of the widest group's span, within the kernel's budget (the kernel
+    // sizes each group's own chunk of channels to it). A ROI's own size is known only on the
+    // device: its groups lie within the bounding lattice.
+    int64_t ext[3] = {max_cnt[0] - 1, max_cnt[1] - 1, max_cnt[2] - 1};
+    if (a.mode != kGridRoi && points <= (int64_t)kBlock * 4096) group_extent(max_cnt, d3, ext);
     const double s_max = 2.0 / (a.ss.v * a.ss.dt);
-    a.rs = staged_samples(s_max, (double)(tx - 1) * max_step * a.g.pitch[0], (double)(ty - 1) * max_step * a.g.pitch[1],
-                          (double)(tz - 1) * max_step * a.g.pitch[2], a.window, a.ss.n_samp);
-    const int per_ant = a.rs * 4 + kTabBytes;
-    if (per_ant > kLdsBudget) return UWB_EUNSUPPORTED;
-    a.chunk = kLdsBudget / per_ant;
-    if (a.chunk > kBlock) a.chunk = kBlock;
-    if (a.chunk > a.ss.n_ant) a.chunk = a.ss.n_ant;
-    const size_t lds = (size_t)a.chunk * per_ant;
-    const dim3 grid((unsigned)tiles, (unsigned)n_scans);
-    const hipError_t e = a.bf == UWB_DMAS ? launch_bf<UWB_DMAS>(a.window, d3, grid, lds, st, a)
-                                          : launch_bf<UWB_DAS>(a.window, d3, grid, lds, st, a);
-    return e == hipSuccess ? UWB_OK : UWB_EHIP;
+    const int rs_max = staged_samples(s_max, (double)ext[0] * max_step * a.g.pitch[0],
+                                      (double)ext[1] * max_step * a.g.pitch[1],
+                                      (double)ext[2] * max_step * a.g.pitch[2], a.window, a.ss.n_samp);
+    const dim3 grid((unsigned)wgs, (unsigned)n_scans);
+    return a.bf == UWB_DMAS ? launch_bf<UWB_DMAS>(a.window, d3, grid, a, rs_max, st)
+                            : launch_bf<UWB_DAS>(a.window, d3, grid, a, rs_max, st);
 }
 
 }  // namespace uwb

@@ -58,7 +58,7 @@ struct Grid64Args {
     int64_t out_stride, out_offset;
     float *out32;                      // optional FP32 copy
     int64_t out32_stride;
-    int tiles[3], rs, chunk;           // filled by launch_grid64
+    int lds_bytes;                     // filled by launch_grid64
 };
 int launch_grid64(Grid64Args a, const int *max_cnt, int max_step, int n_scans, hipStream_t st);
 
