@@ -96,6 +96,18 @@ def test_c3_octree(bf):
         _compare(g, o)
 
 
+@pytest.mark.parametrize("coarse,n", [(6, 48), (10, 40)])
+@pytest.mark.parametrize("bf", [0, 1])
+def test_c3_octree_ragged_lattices(coarse, n, bf):
+    """Lattices that are no whole number of 8 x 8 x 4 tiles (6^3 and 10^3 points per level, a 14^3 ROI) are
+    evaluated in bands of 256 consecutive points that cross z-slabs; values and decisions stay the oracle's."""
+    s = synth.c3_scan(2, n_grid=n)
+    op, gp = _params(beamformer=bf, coarse=coarse, metric="max", frame_final=0.25)
+    o = oracle.walk(s, op)
+    g = uwb().segment_refine(uwb().DeviceScan.from_host(s), s.grid, gp, want_roi=True)
+    _compare(g, o)
+
+
 def test_frame_level_and_depth_limits():
     s = synth.c1_scan(9)
     for kw in [dict(max_depth=2), dict(max_depth=1, term="wb"), dict(coarse=4, frame_level=0.5),
