@@ -45,7 +45,7 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2      # wave64 FP32 instructions per second
 # HBM bytes per launch of the DMAS kernel at the default batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a 256 MiB copy); valid only for the kernel
 # sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
-TRAFFIC = {"source_hash": "d9e3e1a14b0ffeee", "batch": 256, "bytes": 311048444}
+TRAFFIC = {"source_hash": "b5be7710d1a3cc59", "batch": 256, "bytes": 311048631}
 
 
 def _kernel_source_hash() -> str:
