@@ -10,10 +10,12 @@
 //   paper walk:
 //     k_grid64      decimated image of the whole grid                  -> ws
 //     k_walk_paper  one workgroup per scan runs every level on those samples
-//   k_grid64        ROI at full resolution, box read from the result   -> ws, roi_img
-//   k_roi_argmax    maximal-energy voxel of the ROI                    -> result
-// Every energy here is evaluated in FP64, so each decision is taken in the same
-// precision as a double-precision reference and does not hinge on FP32 rounding.
+//   k_roi32         ROI at full resolution in FP32, box read from the result -> ws
+//   k_roi_pick      its maximal-energy voxel, decided in FP64 over the FP32
+//                   near-maximal candidates (walk_roi.hip)         -> result, roi_img
+// Every energy a decision rests on is evaluated in FP64, so each decision is taken
+// in the same precision as a double-precision reference and does not hinge on FP32
+// rounding.
 #include <climits>
 #include <cmath>
 
@@ -567,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void k_composite(const WalkArgs a, float *i
     double val;
     if (in_box(R.roi, x, y, z)) {
         const int rnx = R.roi[1] - R.roi[0], rny = R.roi[3] - R.roi[2];
-        val = a.roi64[(int64_t)scan * a.roi_cap + ((int64_t)(z - R.roi[4]) * rny + (y - R.roi[2])) * rnx + (x - R.roi[0])];
+        val = a.roi32[(int64_t)scan * a.roi_cap + ((int64_t)(z - R.roi[4]) * rny + (y - R.roi[2])) * rnx + (x - R.roi[0])];
     } else if (a.walk == UWB_WALK_PAPER) {
         const int D = a.decimation;
         const int kx = min(x / D, a.dec_cnt[0] - 1), ky = min(y / D, a.dec_cnt[1] - 1);
@@ -586,51 +588,6 @@ __global__ __launch_bounds__(kBlock) void k_composite(const WalkArgs a, float *i
     }
     img[(int64_t)scan * nv + v] = (float)val;
 }
-
-// Maximal-energy voxel of the ROI (rule: lowest finest-grid index within the 1e-12 band).
-__global__ __launch_bounds__(kBlock) void k_roi_argmax(const WalkArgs a) {
-    __shared__ double red[kWaves];
-    __shared__ long long redi[kWaves];
-    const int scan = blockIdx.x;
-    uwb_segment_result &R = a.out[scan];
-    const int rx0 = R.roi[0], ry0 = R.roi[2], rz0 = R.roi[4];
-    const int rnx = R.roi[1] - R.roi[0], rny = R.roi[3] - R.roi[2], rnz = R.roi[5] - R.roi[4];
-    const int64_t n = min((int64_t)rnx * rny * rnz, a.roi_cap);
-    const double *v = a.roi64 + (int64_t)scan * a.roi_cap;
-    double m = -INFINITY;
-    for (int64_t p = threadIdx.x; p < n; p += kBlock) m = fmax(m, v[p]);
-    m = wave_max(m);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    double mm = red[0];
-    for (int i = 1; i < kWaves; ++i) mm = fmax(mm, red[i]);
-    const double thr = mm - kTieRel * fabs(mm);
-    long long best = LLONG_MAX;
-    for (int64_t p = threadIdx.x; p < n; p += kBlock) {
-        if (v[p] >= thr) {
-            const int64_t kx = p % rnx, ky = (p / rnx) % rny, kz = p / ((int64_t)rnx * rny);
-            const long long lin = (rx0 + kx) + (int64_t)a.g.dims[0] * ((ry0 + ky) + (int64_t)a.g.dims[1] * (rz0 + kz));
-            best = lin < best ? lin : best;
-        }
-    }
-    best = wave_min_ll(best);
-    if ((threadIdx.x & 63) == 0) redi[threadIdx.x >> 6] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        long long b = redi[0];
-        for (int i = 1; i < kWaves; ++i) b = redi[i] < b ? redi[i] : b;
-        R.argmax = b == LLONG_MAX ? -1 : b;
-        // value at the winner
-        double pv = __builtin_nan("");
-        if (b != LLONG_MAX) {
-            const int64_t nx = a.g.dims[0], ny = a.g.dims[1];
-            const int64_t ix = b % nx - rx0, iy = (b / nx) % ny - ry0, iz = b / (nx * ny) - rz0;
-            pv = v[(iz * rny + iy) * rnx + ix];
-        }
-        R.peak = pv;
-    }
-}
-
 
 // ----------------------------------------------------------------------------
 // Learned walk (per-level quadtree, g = 32, planar): each level images the box's
@@ -894,7 +851,7 @@ int plan_walk(const GridView &g, const uwb_segment_tree *t, int n_scans, WalkArg
     *roi_bound = bound;
     a->roi_cap = bound;
     const size_t lat = (size_t)lattice_slot(a);
-    *ws_bytes = 4 * 256 + (size_t)n_scans * (8 * ((size_t)bound + (size_t)a->dec_count + lat) + sizeof(PLState));
+    *ws_bytes = 4 * 256 + (size_t)n_scans * (4 * (size_t)bound + 8 * ((size_t)a->dec_count + lat) + sizeof(PLState));
     return UWB_OK;
 }
 
@@ -902,8 +859,8 @@ static uintptr_t align256(uintptr_t p) { return (p + 255) & ~(uintptr_t)255; }
 
 void assign_walk_ws(WalkArgs *a, void *ws, int n_scans) {
     uintptr_t p = align256((uintptr_t)ws);
-    a->roi64 = reinterpret_cast<double *>(p);
-    p = align256(p + (size_t)n_scans * a->roi_cap * 8);
+    a->roi32 = reinterpret_cast<float *>(p);
+    p = align256(p + (size_t)n_scans * a->roi_cap * 4);
     a->dec64 = reinterpret_cast<double *>(p);
     p = align256(p + (size_t)n_scans * a->dec_count * 8);
     a->lat64 = reinterpret_cast<double *>(p);
@@ -945,17 +902,6 @@ static Grid64Args grid_args(const WalkArgs &a, int mode) {
     g.out32 = nullptr;
     g.out32_stride = 0;
     return g;
-}
-
-// Full-resolution ROI of every scan (box read from its result) into roi64 (and roi_img).
-static int launch_roi(const WalkArgs &a, int bf, int n_scans, hipStream_t st) {
-    Grid64Args g = grid_args(a, kGridRoi);
-    g.bf = bf;
-    g.out64 = a.roi64;
-    g.out_stride = a.roi_cap;
-    g.out32 = a.roi_img;
-    g.out32_stride = a.roi_img_stride;
-    return launch_grid64(g, a.roi_side, 1, n_scans, st);
 }
 
 // Two walks of the same scans agree when their final ROIs intersect.
@@ -1014,7 +960,6 @@ int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st) {
         hipLaunchKernelGGL(k_pl_finish, dim3(nb), dim3(256), 0, st, a, n_scans);
     }
     if ((rc = launch_roi(a, a.bf, n_scans, st))) return rc;
-    hipLaunchKernelGGL(k_roi_argmax, dim3(n_scans), dim3(kBlock), 0, st, a);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }
 
@@ -1049,7 +994,6 @@ int launch_learned(const WalkArgs &a, int n_scans, uwb_cnn *cnn, float threshold
     }
     hipLaunchKernelGGL(k_learn_finish, dim3((n_scans + 255) / 256), dim3(256), 0, st, levels, a.depth, n_scans);
     if ((rc = launch_roi(a, roi_bf, n_scans, st))) return rc;
-    hipLaunchKernelGGL(k_roi_argmax, dim3(n_scans), dim3(kBlock), 0, st, a);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }
 

@@ -27,9 +27,9 @@ struct WalkArgs {
     int64_t dec_count;
     double *dec64;             // [n_scans][dec_count]
     // ROI
-    int64_t roi_cap;           // ROI bound: stride of roi64
+    int64_t roi_cap;           // ROI bound: stride of roi32
     int roi_side[3];           // largest ROI side per axis
-    double *roi64;             // [n_scans][roi_cap]
+    float *roi32;              // [n_scans][roi_cap]: FP32 ROI images
     float *roi_img;            // optional, scan s at s * roi_img_stride
     int64_t roi_img_stride;
     uwb_segment_result *out;   // [n_scans]
@@ -66,6 +66,9 @@ int launch_grid64(Grid64Args a, const int *max_cnt, int max_step, int n_scans, h
 void assign_walk_ws(WalkArgs *a, void *ws, int n_scans);
 
 int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st);
+// Final imaging of every scan's ROI (box from its result) with beamformer bf, in FP32 into
+// roi32 (and roi_img), and its detection decided in FP64 into the result (walk_roi.hip).
+int launch_roi(const WalkArgs &a, int bf, int n_scans, hipStream_t st);
 // agree[i] = 1 when the final ROIs of ra[i] and rb[i] intersect.
 int launch_roi_overlap(const uwb_segment_result *ra, const uwb_segment_result *rb, int32_t *agree, int n,
                        hipStream_t st);

@@ -1,0 +1,252 @@
+// Final-imaging phase of the walks (Section III): the full-resolution image of
+// every scan's region of interest and its maximal-energy voxel (the detection).
+//
+// k_roi32   images the ROI (box read from the scan's result) with the tile body of
+//           the full-resolution FP32 kernel (one voxel per lane, tiles of 16 x 16 or
+//           8 x 8 x 4), the ROI taken as a grid of its own   -> roi32
+// k_roi_pick one workgroup per scan: decides the detection in FP64, as for the
+//           full image -- every ROI voxel whose FP32 energy is within kCandRel of
+//           the ROI's FP32 maximum is re-evaluated in FP64 (a whole wave per voxel,
+//           channels over the lanes), and the winner is the lowest finest-grid index
+//           within the FP64 tie band kTieRel of the largest of those values; it also
+//           copies the ROI image to the caller's buffer      -> result, roi_img
+// FP32 rounding moves an energy by about 1e-5 of the peak, far inside kCandRel, so
+// the FP64 maximum is always among the candidates: the decision is the one a
+// double-precision evaluation of the whole ROI would take.
+#include <climits>
+#include <cmath>
+
+#include "image32.h"
+#include "walk_internal.h"
+
+namespace uwb {
+namespace {
+
+constexpr int kRoiWaves = kBlock / 64;
+constexpr int kRoiList = 256;   // FP64-evaluated candidates remembered per scan
+
+struct RoiArgs {
+    ScanSet ss;
+    GridView g;                  // finest grid
+    uwb_segment_result *res;     // [n_scans]: ROI box in, detection out
+    float *roi32;                // [n_scans][roi_cap]
+    int64_t roi_cap;
+    float *roi_img;              // optional copy, scan s at s * roi_img_stride
+    int64_t roi_img_stride;
+    int rs, chunk;               // staging stride and channels per pass
+    int bf, window;
+};
+
+// Grid: x = scan, y = tile of the scan's own ROI (row-major over its tiles), so that
+// the workgroups with work -- every scan's first tiles -- are dispatched before the
+// ones past a scan's ROI, which only the largest possible ROI needs.
+template <int BF, int W, bool D3, bool MS>
+__global__ __launch_bounds__(kBlock) void k_roi32(const RoiArgs a) {
+    extern __shared__ float smem[];
+    const int scan = blockIdx.x;
+    const int *roi = a.res[scan].roi;
+    TileJob j;
+    for (int d = 0; d < 3; ++d) {   // the ROI as a grid of its own
+        j.g.dims[d] = roi[2 * d + 1] - roi[2 * d];
+        j.g.pitch[d] = a.g.pitch[d];
+        j.g.origin[d] = a.g.origin[d] + roi[2 * d] * a.g.pitch[d];
+    }
+    // a ROI larger than its slot (never, for a planned walk) is not imaged
+    if ((int64_t)j.g.dims[0] * j.g.dims[1] * j.g.dims[2] > a.roi_cap) return;
+    int tx, ty, tz;
+    TileShape<D3, 1>::get(tx, ty, tz);
+    const int ntx = (j.g.dims[0] + tx - 1) / tx, nty = (j.g.dims[1] + ty - 1) / ty;
+    const int ntz = (j.g.dims[2] + tz - 1) / tz;
+    const int ntiles = ntx * nty * ntz;
+    if ((int)blockIdx.y >= ntiles) return;   // uniform per workgroup
+    const ScanConst sc = scan_const(a.ss, scan);
+    j.pos = sc.pos;
+    j.tr = sc.tr;
+    j.img = a.roi32 + (int64_t)scan * a.roi_cap;
+    j.M = a.ss.n_ant;
+    j.T = a.ss.n_samp;
+    j.s = sc.s;
+    j.t0s = sc.t0s;
+    j.rs = a.rs;
+    j.chunk = a.chunk;
+    j.ms = a.ss.ms;
+    // (more tiles than the grid's 65535 rows: the rows stride over them)
+    for (int t = blockIdx.y; t < ntiles; t += gridDim.y) {
+        j.tx0 = (t % ntx) * tx;
+        j.ty0 = ((t / ntx) % nty) * ty;
+        j.tz0 = (t / (ntx * nty)) * tz;
+        image_tile<BF, W, D3, 1, MS>(j, smem);
+    }
+}
+
+__device__ __forceinline__ void roi_pos(const RoiArgs &a, const int *roi, int rnx, int rny, int64_t p, double &rx,
+                                        double &ry, double &rz) {
+    const int64_t kx = p % rnx, ky = (p / rnx) % rny, kz = p / ((int64_t)rnx * rny);
+    rx = a.g.origin[0] + (double)(roi[0] + kx) * a.g.pitch[0];
+    ry = a.g.origin[1] + (double)(roi[2] + ky) * a.g.pitch[1];
+    rz = a.g.origin[2] + (double)(roi[4] + kz) * a.g.pitch[2];
+}
+
+__global__ __launch_bounds__(kBlock) void k_roi_pick(const RoiArgs a) {
+    __shared__ float redf[kRoiWaves];
+    __shared__ double redd[kRoiWaves];
+    __shared__ long long sb[kBlock];
+    __shared__ double sv[kBlock];
+    __shared__ int lcount;
+    __shared__ int64_t lidx[kRoiList];
+    __shared__ double lval[kRoiList];
+    const int scan = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uwb_segment_result &R = a.res[scan];
+    const int *roi = R.roi;
+    const int rnx = roi[1] - roi[0], rny = roi[3] - roi[2], rnz = roi[5] - roi[4];
+    const int64_t n = min((int64_t)rnx * rny * rnz, a.roi_cap);
+    const float *v = a.roi32 + (int64_t)scan * a.roi_cap;
+    float *copy = a.roi_img ? a.roi_img + (int64_t)scan * a.roi_img_stride : nullptr;
+
+    // FP32 maximum (and the caller's copy of the image)
+    float m = -INFINITY;
+    for (int64_t p = threadIdx.x; p < n; p += kBlock) {
+        const float x = v[p];
+        m = fmaxf(m, x);
+        if (copy) copy[p] = x;
+    }
+    m = wave_maxf(m);
+    if (lane == 0) redf[wave] = m;
+    if (threadIdx.x == 0) lcount = 0;
+    __syncthreads();
+    m = redf[0];
+    for (int i = 1; i < kRoiWaves; ++i) m = fmaxf(m, redf[i]);
+    const float thr32 = m - (float)kCandRel * fabsf(m);
+
+    // FP64 energies of the candidates: one wave per candidate, channels over its lanes
+    const ScanConst sc = scan_const(a.ss, scan);
+    const int M = a.ss.n_ant, T = a.ss.n_samp;
+    double best = -INFINITY;
+    for (int64_t p0 = 0; p0 < n; p0 += kBlock) {
+        const int64_t p = p0 + threadIdx.x;
+        unsigned long long mask = __ballot(p < n && v[p] >= thr32);
+        while (mask) {
+            const int l = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const int64_t pp = p0 + 64 * wave + l;
+            double rx, ry, rz;
+            roi_pos(a, roi, rnx, rny, pp, rx, ry, rz);
+            const double e = energy64_dispatch(a.bf, sc, M, T, a.window, rx, ry, rz, lane, 64);
+            best = fmax(best, e);
+            if (lane == 0) {
+                const int slot = atomicAdd(&lcount, 1);
+                if (slot < kRoiList) { lidx[slot] = pp; lval[slot] = e; }
+            }
+        }
+    }
+    best = wave_max(best);
+    if (lane == 0) redd[wave] = best;
+    __syncthreads();
+    double mx = redd[0];
+    for (int i = 1; i < kRoiWaves; ++i) mx = fmax(mx, redd[i]);
+    const double thr64 = mx - kTieRel * fabs(mx);
+    const int count = lcount;
+
+    // lowest ROI index (= lowest finest-grid index) within the FP64 tie band, with its value
+    long long bi = LLONG_MAX;
+    double bv = 0.0;
+    if (count <= kRoiList) {
+        for (int i = threadIdx.x; i < count; i += kBlock)
+            if (lval[i] >= thr64 && lidx[i] < bi) { bi = lidx[i]; bv = lval[i]; }
+    } else {   // more candidates than the list holds: evaluate them again
+        for (int64_t p0 = 0; p0 < n; p0 += kBlock) {
+            const int64_t p = p0 + threadIdx.x;
+            unsigned long long mask = __ballot(p < n && v[p] >= thr32);
+            while (mask) {
+                const int l = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                const int64_t pp = p0 + 64 * wave + l;
+                if (pp >= bi) break;   // wave-uniform: this wave's later candidates are larger
+                double rx, ry, rz;
+                roi_pos(a, roi, rnx, rny, pp, rx, ry, rz);
+                const double e = energy64_dispatch(a.bf, sc, M, T, a.window, rx, ry, rz, lane, 64);
+                if (e >= thr64) { bi = pp; bv = e; }
+            }
+        }
+    }
+    __syncthreads();   // every thread is done with the candidate list
+    sb[threadIdx.x] = bi;
+    sv[threadIdx.x] = bv;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    long long b = LLONG_MAX;
+    double pv = __builtin_nan("");
+    for (int i = 0; i < kBlock; ++i)
+        if (sb[i] < b) { b = sb[i]; pv = sv[i]; }
+    if (b == LLONG_MAX) {   // no finite candidate (e.g. a NaN image)
+        R.argmax = -1;
+        R.peak = __builtin_nan("");
+        return;
+    }
+    const int64_t kx = b % rnx, ky = (b / rnx) % rny, kz = b / ((int64_t)rnx * rny);
+    R.argmax = (roi[0] + kx) + (int64_t)a.g.dims[0] * ((roi[2] + ky) + (int64_t)a.g.dims[1] * (roi[4] + kz));
+    R.peak = pv;
+}
+
+template <int BF, int W>
+void launch_w(bool d3, dim3 grid, size_t lds, hipStream_t st, const RoiArgs &a) {
+    if (a.ss.ms) {
+        if (d3) hipLaunchKernelGGL((k_roi32<BF, W, true, true>), grid, dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((k_roi32<BF, W, false, true>), grid, dim3(kBlock), lds, st, a);
+    } else {
+        if (d3) hipLaunchKernelGGL((k_roi32<BF, W, true, false>), grid, dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((k_roi32<BF, W, false, false>), grid, dim3(kBlock), lds, st, a);
+    }
+}
+
+template <int BF>
+bool launch_bf(int window, bool d3, dim3 grid, size_t lds, hipStream_t st, const RoiArgs &a) {
+    switch (window) {
+#define UWB_W(w) case w: launch_w<BF, w>(d3, grid, lds, st, a); return true;
+        UWB_WINDOWS(UWB_W)
+#undef UWB_W
+    }
+    return false;
+}
+
+}  // namespace
+
+int launch_roi(const WalkArgs &w, int bf, int n_scans, hipStream_t st) {
+    if (n_scans < 1) return UWB_OK;
+    const bool d3 = w.g.dims[2] > 1;
+    int tx, ty, tz;
+    tile_shape(d3, 1, &tx, &ty, &tz);
+    RoiArgs a;
+    a.ss = w.ss;
+    a.g = w.g;
+    a.res = w.out;
+    a.roi32 = w.roi32;
+    a.roi_cap = w.roi_cap;
+    a.roi_img = w.roi_img;
+    a.roi_img_stride = w.roi_img_stride;
+    a.bf = bf;
+    a.window = w.window;
+    const int64_t tiles = (int64_t)((w.roi_side[0] + tx - 1) / tx) * ((w.roi_side[1] + ty - 1) / ty) *
+                          ((w.roi_side[2] + tz - 1) / tz);   // of the largest ROI
+    if (tiles < 1) return UWB_EUNSUPPORTED;
+    // staging sized for the largest samples-per-metre of the batch (lower bounds of v and dt)
+    const double s_max = 2.0 / (w.ss.v * w.ss.dt);
+    a.rs = staged_samples(s_max, (tx - 1) * w.g.pitch[0], (ty - 1) * w.g.pitch[1], (tz - 1) * w.g.pitch[2], w.window,
+                          w.ss.n_samp);
+    const int per_ch = a.rs * 4 + (w.ss.ms ? 32 : 16);   // staged samples + table entries
+    if (per_ch > kLdsBudget) return UWB_EUNSUPPORTED;
+    a.chunk = kLdsBudget / per_ch;
+    if (a.chunk > kBlock) a.chunk = kBlock;
+    if (a.chunk > w.ss.n_ant) a.chunk = w.ss.n_ant;
+    const size_t lds = (size_t)a.chunk * per_ch;
+    const dim3 grid((unsigned)n_scans, (unsigned)(tiles < 65535 ? tiles : 65535));
+    const bool ok = bf == UWB_DMAS ? launch_bf<UWB_DMAS>(w.window, d3, grid, lds, st, a)
+                                   : launch_bf<UWB_DAS>(w.window, d3, grid, lds, st, a);
+    if (!ok) return UWB_EINVAL;
+    if (hipGetLastError() != hipSuccess) return UWB_EHIP;
+    hipLaunchKernelGGL(k_roi_pick, dim3((unsigned)n_scans), dim3(kBlock), 0, st, a);
+    return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
+}
+
+}  // namespace uwb

@@ -112,7 +112,7 @@ def test_walks_match_oracle(walk, kw, bf):
         assert g.peak == pytest.approx(o.peak, rel=1e-9)
         for a, b in zip(g.scores, o.scores):
             np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-300)
-        np.testing.assert_allclose(g.roi_image, o.roi_image, rtol=1e-6, atol=1e-6 * o.roi_image.max())
+        _check_image(g.roi_image, o.roi_image)   # the ROI is imaged in FP32; its detection is FP64 (above)
 
 
 def test_paper_decimation_finds_the_tumour():

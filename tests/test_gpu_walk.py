@@ -35,7 +35,25 @@ def _compare(g, o, exact_scores=1e-9):
     for a, b in zip(g.wb, o.wb):
         np.testing.assert_allclose(a, b, rtol=1e-9)
     if o.roi_image is not None and g.roi_image is not None:
-        np.testing.assert_allclose(g.roi_image, o.roi_image, rtol=1e-6, atol=1e-6 * o.roi_image.max())
+        roi_close(g.roi_image, o.roi_image)
+
+
+def roi_close(got, want, window=11):
+    """The ROI is imaged in FP32 (its detection is decided in FP64, checked above): the full-image bar,
+    |error| <= 1e-4 x peak everywhere and <= 1e-4 relative above 1 % of the peak (5e-4 for windows under 5)."""
+    peak = np.abs(want).max()
+    assert np.max(np.abs(got - want)) <= 1e-4 * peak
+    big = np.abs(want) > 1e-2 * peak
+    assert np.max(np.abs(got[big] - want[big]) / np.abs(want[big])) <= (5e-4 if window < 5 else 1e-4)
+
+
+def composite_close(got, want, roi):
+    """Composite: FP32 ROI voxels at the image bar, every other voxel the FP64 coarse value rounded to FP32."""
+    inside = np.zeros(want.shape, bool)
+    x0, x1, y0, y1, z0, z1 = roi
+    inside[z0:z1, y0:y1, x0:x1] = True   # [nz][ny][nx]
+    np.testing.assert_allclose(got[~inside], want[~inside], rtol=1e-6, atol=1e-30)
+    roi_close(got[inside], want[inside])
 
 
 @pytest.mark.parametrize("metric", METRICS)
@@ -145,7 +163,7 @@ def test_composite_matches_oracle(walk, kw, bf):
         o = oracle.walk(s, op)
         assert res[i].child == o.child and tuple(res[i].roi) == tuple(o.roi)
         want = composite(s, op, o)
-        np.testing.assert_allclose(img[i], want, rtol=1e-6, atol=1e-30)
+        composite_close(img[i], want, o.roi)
 
 
 def test_composite_c3_octree():
@@ -156,7 +174,7 @@ def test_composite_c3_octree():
     res, img = u.segment_composite_batch(u.DeviceBatch.from_host([s]), s.grid, gp)
     o = oracle.walk(s, op)
     assert res[0].child == o.child
-    np.testing.assert_allclose(img.cpu().numpy()[0], composite(s, op, o), rtol=1e-6, atol=1e-30)
+    composite_close(img.cpu().numpy()[0], composite(s, op, o), o.roi)
 
 
 # ----------------------------------------------------------------------------------
