@@ -9,7 +9,7 @@
 //                   block reductions, W/B test, selection             -> result, state
 //   paper walk:
 //     k_grid64      decimated image of the whole grid                  -> ws
-//     k_walk_paper  one workgroup per scan runs every level on those samples
+//     k_walk_paper  one wavefront per scan runs every level on those samples
 //   k_roi32         ROI at full resolution in FP32, box read from the result -> ws
 //   k_roi_pick      its maximal-energy voxel, decided in FP64 over the FP32
 //                   near-maximal candidates (walk_roi.hip)         -> result, roi_img
@@ -28,27 +28,8 @@ namespace {
 constexpr int kWaves = kBlock / 64;
 
 // ----------------------------------------------------------------------------
-// block reductions of small vectors (all threads get the result)
+// block reduction of small vectors (all threads get the result)
 // ----------------------------------------------------------------------------
-template <int N>
-__device__ void block_sum(double (&v)[N], double *red /* [kWaves][N] */) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = wave_sum(v[i]);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int i = 0; i < N; ++i) red[w * N + i] = v[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        double s = red[i];
-        for (int k = 1; k < kWaves; ++k) s += red[k * N + i];
-        v[i] = s;
-    }
-}
-
 template <int N>
 __device__ void block_max(double (&v)[N], double *red) {
 #pragma unroll
@@ -161,111 +142,22 @@ struct LevelStats {
     double count[8];
 };
 
-// Parent (current box) and child statistics of one level and the children's metric (Section III).
-// cbox receives the children boxes, sc8 their scores under a.metric.
-__device__ LevelStats level_stats(const WalkArgs &a, const Lattice &L, const double *src, const int *box, int nact,
-                              int side, bool paper, double *red, int cbox[8][6], double sc8[8]) {
-    const int tid = threadIdx.x;
-    const int nchild = 1 << nact;
-    const int P = L.count();
-    // children boxes and their scoring boxes
-    int sbx[8][6];
-    const int half = side / 2;
-    const int efr = paper ? 0 : (int)floor(a.frame_level * (double)half);
-    for (int c = 0; c < nchild; ++c) {
-        split_box(box, c, nact, cbox[c]);
-        for (int i = 0; i < 6; ++i) sbx[c][i] = cbox[c][i];
-        if (!paper) {
-            for (int d = 0; d < nact; ++d) {
-                sbx[c][2 * d] = max(box[2 * d], cbox[c][2 * d] - efr);
-                sbx[c][2 * d + 1] = min(box[2 * d + 1], cbox[c][2 * d + 1] + efr);
-            }
-        }
-    }
-
-    // pass 1: counts, sums, maxima of the parent (current box) and children
-    double s1[18], mx[9];
-    for (int i = 0; i < 18; ++i) s1[i] = 0.0;
-    for (int i = 0; i < 9; ++i) mx[i] = -INFINITY;
-    for (int p = tid; p < P; p += kBlock) {
-        int x, y, z;
-        L.coord(p, x, y, z);
-        if (!in_box(box, x, y, z)) continue;
-        const double v = src[p];
-        s1[0] += 1.0; s1[1] += v; mx[0] = fmax(mx[0], v);
-        for (int c = 0; c < nchild; ++c)
-            if (in_box(sbx[c], x, y, z)) { s1[2 + 2 * c] += 1.0; s1[3 + 2 * c] += v; mx[1 + c] = fmax(mx[1 + c], v); }
-    }
-    block_sum(s1, red);
-    block_max(mx, red);
-    const double pn = s1[0], pmean = s1[1] / pn, pmax = mx[0];
-    const double scale = pmax > 0.0 ? pmax : 1.0;    // Eq. (5) normalisation
-    double cmean[8];
-    for (int c = 0; c < nchild; ++c) cmean[c] = s1[3 + 2 * c] / s1[2 + 2 * c];
-    // pass 2: normalised sums (Eq. 5) and raw squared deviations
-    double s2[18];
-    for (int i = 0; i < 18; ++i) s2[i] = 0.0;
-    for (int p = tid; p < P; p += kBlock) {
-        int x, y, z;
-        L.coord(p, x, y, z);
-        if (!in_box(box, x, y, z)) continue;
-        const double v = src[p];
-        const double vn = pmax > 0.0 ? v / scale : v;
-        s2[0] += (v - pmean) * (v - pmean); s2[1] += vn;
-        for (int c = 0; c < nchild; ++c)
-            if (in_box(sbx[c], x, y, z)) {
-                s2[2 + 2 * c] += (v - cmean[c]) * (v - cmean[c]);
-                s2[3 + 2 * c] += vn;
-            }
-    }
-    block_sum(s2, red);
-    const double pm2 = s2[0];
-    const double pnmean = s2[1] / pn;
-    double cnmean[8];
-    for (int c = 0; c < nchild; ++c) cnmean[c] = s2[3 + 2 * c] / s1[2 + 2 * c];
-    // pass 3: normalised squared deviations (Eq. 5 variances)
-    double s3[9];
-    for (int i = 0; i < 9; ++i) s3[i] = 0.0;
-    if (a.metric == UWB_EQ5 || a.metric == UWB_EQ5_CLAMPED) {
-        for (int p = tid; p < P; p += kBlock) {
-            int x, y, z;
-            L.coord(p, x, y, z);
-            if (!in_box(box, x, y, z)) continue;
-            const double v = src[p];
-            const double vn = pmax > 0.0 ? v / scale : v;
-            s3[0] += (vn - pnmean) * (vn - pnmean);
-            for (int c = 0; c < nchild; ++c)
-                if (in_box(sbx[c], x, y, z)) s3[1 + c] += (vn - cnmean[c]) * (vn - cnmean[c]);
-        }
-        block_sum(s3, red);
-    }
-
-    LevelStats out;
-    out.pn = pn;
-    out.pmean = pmean;
-    out.pm2 = pm2;
-    for (int c = 0; c < nchild; ++c) {
-        out.count[c] = s1[2 + 2 * c];
-        const double n = s1[2 + 2 * c];
-        const double nvar = s3[1 + c] / n;
-        sc8[c] = metric_value(a.metric, n, cmean[c], s2[2 + 2 * c], mx[1 + c], cnmean[c], nvar, s3[0] / pn);
-    }
-    return out;
-}
-
-// The same statistics for one scan on one wavefront (no workgroup barriers), for
-// the per-level walk where every level's lattice lies inside its box.  Passes 2
-// and 3 run only when the metric or the W/B stop needs them.  Every lane returns
-// the result.
+// The same statistics for one scan on one wavefront (no workgroup barriers): for
+// the per-level walk, whose every level's lattice lies inside its box, and for the
+// paper walk (paper = true), whose samples are the decimated lattice points inside
+// the current box.  Passes 2 and 3 run only when the metric or the W/B stop needs
+// them.  Every lane returns the result.
 template <int NACT>
 __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, const double *src, const int *box,
-                                       int side, int cbox[8][6], double sc8[8]) {
+                                       int side, bool paper, int cbox[8][6], double sc8[8]) {
     constexpr int NCH = 1 << NACT;
     const int lane = threadIdx.x & 63;
     const int P = L.count();
     int sbx[NCH][6];
     const int half = side / 2;
-    const int efr = (int)floor(a.frame_level * (double)half);
+    // the per-level walk scores each child on its box widened by the level frame; the
+    // paper walk on the child's own samples
+    const int efr = paper ? 0 : (int)floor(a.frame_level * (double)half);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         split_box(box, c, NACT, cbox[c]);
@@ -361,15 +253,16 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
 }
 
 // ----------------------------------------------------------------------------
-// k_walk_paper: the ROI-selection loop of the three-phase walk, one workgroup
+// k_walk_paper: the ROI-selection loop of the three-phase walk, one wavefront
 // per scan, over the samples of the decimated image (computed once).
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_walk_paper(const WalkArgs a) {
-    __shared__ double red[kWaves * 32];
-    const int scan = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int nact = a.g.dims[2] > 1 ? 3 : 2;
-    const int nchild = 1 << nact;
+template <int NACT>
+__global__ __launch_bounds__(kBlock) void k_walk_paper(const WalkArgs a, int n_scans) {
+    const int scan = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (scan >= n_scans) return;   // uniform per wavefront
+    const int tid = threadIdx.x & 63;
+    constexpr int nact = NACT;
+    constexpr int nchild = 1 << NACT;
     const int dims[3] = {a.g.dims[0], a.g.dims[1], a.g.dims[2]};
     uwb_segment_result &R = a.out[scan];
 
@@ -389,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_paper(const WalkArgs a) {
         if (lev == a.depth && a.term != UWB_TERM_WB) { n_kept = a.depth; break; }
         int cbox[8][6];
         double sc8[8];
-        const LevelStats ls = level_stats(a, L, src, box, nact, 0, true, red, cbox, sc8);
+        const LevelStats ls = wave_level_stats<NACT>(a, L, src, box, 0, true, cbox, sc8);
         const double pn = ls.pn, pmean = ls.pmean, pm2 = ls.pm2;
         double cmin = INFINITY;
         for (int c = 0; c < nchild; ++c) cmin = fmin(cmin, ls.count[c]);
@@ -488,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_pl_level(const WalkArgs a, int lev, 
     const double *src = a.lat64 + (int64_t)scan * a.lat_stride + (int64_t)lev * P;
     int cbox[8][6];
     double sc8[8];
-    const LevelStats ls = wave_level_stats<NACT>(a, L, src, box, side, cbox, sc8);
+    const LevelStats ls = wave_level_stats<NACT>(a, L, src, box, side, false, cbox, sc8);
     if ((threadIdx.x & 63) != 0) return;       // the rest is one lane's bookkeeping
     PLState st = S;
     st.nvox += P;
@@ -632,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void k_learn_level(const WalkArgs a, int le
     const double *lv = a.lat64 + (int64_t)scan * a.lat_stride + (int64_t)lev * kLearnG * kLearnG;
     int cbox[8][6];
     double sc8[8];
-    wave_level_stats<2>(a, L, lv, box, side, cbox, sc8);
+    wave_level_stats<2>(a, L, lv, box, side, false, cbox, sc8);
     double best = -INFINITY;
     for (int c = 0; c < 4; ++c) best = fmax(best, sc8[c]);
     const double thr = best - kTieRel * fabs(best);
@@ -937,7 +830,9 @@ int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st) {
         g.out64 = a.dec64;
         g.out_stride = a.dec_count;
         if ((rc = launch_grid64(g, a.dec_cnt, a.decimation, n_scans, st))) return rc;
-        hipLaunchKernelGGL(k_walk_paper, dim3(n_scans), dim3(kBlock), 0, st, a);
+        const dim3 gw((unsigned)((n_scans + kWaves - 1) / kWaves));
+        if (a.g.dims[2] > 1) hipLaunchKernelGGL(k_walk_paper<3>, gw, dim3(kBlock), 0, st, a, n_scans);
+        else hipLaunchKernelGGL(k_walk_paper<2>, gw, dim3(kBlock), 0, st, a, n_scans);
     } else {
         const unsigned nb = (unsigned)((n_scans + 255) / 256);
         hipLaunchKernelGGL(k_pl_init, dim3(nb), dim3(256), 0, st, a, n_scans);
