@@ -4,7 +4,7 @@
 // k_roi32   images the ROI (box read from the scan's result) with the tile body of
 //           the full-resolution FP32 kernel (one voxel per lane, tiles of 16 x 16 or
 //           8 x 8 x 4), the ROI taken as a grid of its own   -> roi32
-// k_roi_pick one workgroup per scan: decides the detection in FP64, as for the
+// k_roi_pick one wavefront per scan: decides the detection in FP64, as for the
 //           full image -- every ROI voxel whose FP32 energy is within kCandRel of
 //           the ROI's FP32 maximum is re-evaluated in FP64 (a whole wave per voxel,
 //           channels over the lanes), and the winner is the lowest finest-grid index
@@ -23,7 +23,6 @@ namespace uwb {
 namespace {
 
 constexpr int kRoiWaves = kBlock / 64;
-constexpr int kRoiList = 256;   // FP64-evaluated candidates remembered per scan
 
 struct RoiArgs {
     ScanSet ss;
@@ -87,16 +86,13 @@ __device__ __forceinline__ void roi_pos(const RoiArgs &a, const int *roi, int rn
     rz = a.g.origin[2] + (double)(roi[4] + kz) * a.g.pitch[2];
 }
 
-__global__ __launch_bounds__(kBlock) void k_roi_pick(const RoiArgs a) {
-    __shared__ float redf[kRoiWaves];
-    __shared__ double redd[kRoiWaves];
-    __shared__ long long sb[kBlock];
-    __shared__ double sv[kBlock];
-    __shared__ int lcount;
-    __shared__ int64_t lidx[kRoiList];
-    __shared__ double lval[kRoiList];
-    const int scan = blockIdx.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// One wavefront per scan.  Lane l remembers the l-th FP64-evaluated candidate (in
+// index order), so the tie band needs no second evaluation unless a scan has more
+// than 64 candidates.
+__global__ __launch_bounds__(kBlock) void k_roi_pick(const RoiArgs a, int n_scans) {
+    const int scan = blockIdx.x * kRoiWaves + (threadIdx.x >> 6);
+    if (scan >= n_scans) return;   // uniform per wavefront
+    const int lane = threadIdx.x & 63;
     uwb_segment_result &R = a.res[scan];
     const int *roi = R.roi;
     const int rnx = roi[1] - roi[0], rny = roi[3] - roi[2], rnz = roi[5] - roi[4];
@@ -106,79 +102,62 @@ __global__ __launch_bounds__(kBlock) void k_roi_pick(const RoiArgs a) {
 
     // FP32 maximum (and the caller's copy of the image)
     float m = -INFINITY;
-    for (int64_t p = threadIdx.x; p < n; p += kBlock) {
+    for (int64_t p = lane; p < n; p += 64) {
         const float x = v[p];
         m = fmaxf(m, x);
         if (copy) copy[p] = x;
     }
     m = wave_maxf(m);
-    if (lane == 0) redf[wave] = m;
-    if (threadIdx.x == 0) lcount = 0;
-    __syncthreads();
-    m = redf[0];
-    for (int i = 1; i < kRoiWaves; ++i) m = fmaxf(m, redf[i]);
     const float thr32 = m - (float)kCandRel * fabsf(m);
 
-    // FP64 energies of the candidates: one wave per candidate, channels over its lanes
+    // FP64 energies of the candidates in index order, channels over the lanes
     const ScanConst sc = scan_const(a.ss, scan);
     const int M = a.ss.n_ant, T = a.ss.n_samp;
     double best = -INFINITY;
-    for (int64_t p0 = 0; p0 < n; p0 += kBlock) {
-        const int64_t p = p0 + threadIdx.x;
+    int count = 0;
+    int64_t my_idx = 0;
+    double my_val = 0.0;
+    for (int64_t p0 = 0; p0 < n; p0 += 64) {
+        const int64_t p = p0 + lane;
         unsigned long long mask = __ballot(p < n && v[p] >= thr32);
         while (mask) {
             const int l = __builtin_ctzll(mask);
             mask &= mask - 1;
-            const int64_t pp = p0 + 64 * wave + l;
+            const int64_t pp = p0 + l;
             double rx, ry, rz;
             roi_pos(a, roi, rnx, rny, pp, rx, ry, rz);
-            const double e = energy64_dispatch(a.bf, sc, M, T, a.window, rx, ry, rz, lane, 64);
+            const double e = energy64_dispatch(a.bf, sc, M, T, a.window, rx, ry, rz, lane, 64);   // on every lane
             best = fmax(best, e);
-            if (lane == 0) {
-                const int slot = atomicAdd(&lcount, 1);
-                if (slot < kRoiList) { lidx[slot] = pp; lval[slot] = e; }
-            }
+            if (lane == count) { my_idx = pp; my_val = e; }
+            ++count;
         }
     }
-    best = wave_max(best);
-    if (lane == 0) redd[wave] = best;
-    __syncthreads();
-    double mx = redd[0];
-    for (int i = 1; i < kRoiWaves; ++i) mx = fmax(mx, redd[i]);
-    const double thr64 = mx - kTieRel * fabs(mx);
-    const int count = lcount;
+    const double thr64 = best - kTieRel * fabs(best);
 
     // lowest ROI index (= lowest finest-grid index) within the FP64 tie band, with its value
-    long long bi = LLONG_MAX;
-    double bv = 0.0;
-    if (count <= kRoiList) {
-        for (int i = threadIdx.x; i < count; i += kBlock)
-            if (lval[i] >= thr64 && lidx[i] < bi) { bi = lidx[i]; bv = lval[i]; }
-    } else {   // more candidates than the list holds: evaluate them again
-        for (int64_t p0 = 0; p0 < n; p0 += kBlock) {
-            const int64_t p = p0 + threadIdx.x;
+    long long b = LLONG_MAX;
+    double pv = __builtin_nan("");
+    if (count <= 64) {
+        long long mine = lane < count && my_val >= thr64 ? my_idx : LLONG_MAX;
+        b = wave_min_ll(mine);
+        const unsigned long long owner = __ballot(mine == b && b != LLONG_MAX);
+        if (owner) pv = __shfl(my_val, __builtin_ctzll(owner), 64);
+    } else {   // more candidates than lanes: evaluate them again, the first in the band wins
+        for (int64_t p0 = 0; p0 < n && b == LLONG_MAX; p0 += 64) {
+            const int64_t p = p0 + lane;
             unsigned long long mask = __ballot(p < n && v[p] >= thr32);
             while (mask) {
                 const int l = __builtin_ctzll(mask);
                 mask &= mask - 1;
-                const int64_t pp = p0 + 64 * wave + l;
-                if (pp >= bi) break;   // wave-uniform: this wave's later candidates are larger
+                const int64_t pp = p0 + l;
                 double rx, ry, rz;
                 roi_pos(a, roi, rnx, rny, pp, rx, ry, rz);
                 const double e = energy64_dispatch(a.bf, sc, M, T, a.window, rx, ry, rz, lane, 64);
-                if (e >= thr64) { bi = pp; bv = e; }
+                if (e >= thr64) { b = pp; pv = e; break; }
             }
         }
     }
-    __syncthreads();   // every thread is done with the candidate list
-    sb[threadIdx.x] = bi;
-    sv[threadIdx.x] = bv;
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    long long b = LLONG_MAX;
-    double pv = __builtin_nan("");
-    for (int i = 0; i < kBlock; ++i)
-        if (sb[i] < b) { b = sb[i]; pv = sv[i]; }
+    if (lane != 0) return;
     if (b == LLONG_MAX) {   // no finite candidate (e.g. a NaN image)
         R.argmax = -1;
         R.peak = __builtin_nan("");
@@ -245,7 +224,8 @@ int launch_roi(const WalkArgs &w, int bf, int n_scans, hipStream_t st) {
                                    : launch_bf<UWB_DAS>(w.window, d3, grid, lds, st, a);
     if (!ok) return UWB_EINVAL;
     if (hipGetLastError() != hipSuccess) return UWB_EHIP;
-    hipLaunchKernelGGL(k_roi_pick, dim3((unsigned)n_scans), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_roi_pick, dim3((unsigned)((n_scans + kRoiWaves - 1) / kRoiWaves)), dim3(kBlock), 0, st, a,
+                       n_scans);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }
 
