@@ -252,8 +252,9 @@ size_t uwb_segment_workspace_bytes(const uwb_grid *finest, const uwb_segment_tre
 /*
  * out:       device uwb_segment_result (one per scan for the batch form)
  * roi_img:   device fp32 [roi_capacity] per scan (batch: scan s at
- *            s * roi_capacity), the final ROI image [z][y][x] of the ROI box;
- *            may be NULL
+ *            s * roi_capacity), the final ROI image [z][y][x] of the ROI box,
+ *            imaged in FP32 (the detection in out is decided in FP64 over the
+ *            voxels within 1e-3 of its maximum, as for a full image); may be NULL
  * roi_capacity: >= uwb_segment_roi_capacity(...), else UWB_ERANGE
  */
 int uwb_segment_refine(const uwb_scan *scan, const uwb_grid *finest, int32_t window,
