@@ -4,7 +4,8 @@
 // and follows the host generator's definition draw for draw:
 //   * scene: SplitMix64 (Steele, Lea, Flood 2014) seeded with seed ^ (salt << 56):
 //     tumour (r = R sqrt(u), theta = 2 pi u'), then every clutter point the same
-//     way, then the clutter reflectivities rho = 0.1 u;
+//     way, then the clutter reflectivities rho = 0.1 u (each draw taken directly
+//     from its index, one scatterer per lane);
 //   * echoes: Y_i[n] = sum_s A_is p(t0 + n dt - 2 |x_s - a_i| / v),
 //     A_is = rho_s (1 cm / |x_s - a_i|)^2,
 //     p(t) = sin(2 pi f0 t) exp(-t^2 / 2 sigma^2) / peak for |t| <= 6 sigma;
@@ -22,20 +23,19 @@
 namespace uwb {
 namespace {
 
-constexpr int kMaxScat = 1024;
+constexpr int kMaxScat = 1024;   // scatterers per scene (LDS: 40 B each)
 constexpr uint32_t kNoiseTag = 0x4E4F4953u;
 
-struct SplitMix64 {
-    unsigned long long s;
-    __device__ unsigned long long next() {
-        s += 0x9E3779B97F4A7C15ull;
-        unsigned long long z = s;
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        return z ^ (z >> 31);
-    }
-    __device__ double uniform() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); }
-};
+// SplitMix64 adds a constant to its state before every output, so draw d (0-based)
+// of a stream seeded with s0 is the output mix of s0 + (d + 1) * gamma: any draw can
+// be taken directly, and the scatterers of a scene are drawn in parallel.
+__device__ __forceinline__ double splitmix_uniform(unsigned long long s0, unsigned long long d) {
+    unsigned long long z = s0 + (d + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
 
 __device__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
     for (int r = 0; r < 10; ++r) {
@@ -66,64 +66,84 @@ __device__ __forceinline__ float pulse32(float t, float f0, float sigma, float i
 
 // One workgroup per (scan, antenna): every workgroup of a scan redraws the (cheap)
 // scene and the tumour power, then synthesises its antenna's trace.
+// Dynamic LDS: scene and per-scatterer terms for ns scatterers, then the reduction space.
+__host__ __device__ inline size_t gen_lds_bytes(int ns) { return (size_t)ns * (4 * sizeof(double) + 8) + 256 * 16; }
+
 __global__ __launch_bounds__(256) void k_gen_disc(const GenArgs a) {
-    __shared__ double sx[kMaxScat + 1], sy[kMaxScat + 1], srho[kMaxScat + 1];
-    __shared__ double s_tau[kMaxScat + 1];
-    __shared__ float s_amp[kMaxScat + 1];
-    __shared__ int s_n0[kMaxScat + 1];
-    __shared__ double red[256];
+    extern __shared__ __align__(16) unsigned char gsm[];
+    const int ns = a.n_clutter + 1;
+    double *sx = reinterpret_cast<double *>(gsm), *sy = sx + ns, *srho = sy + ns, *s_tau = srho + ns;
+    float *s_amp = reinterpret_cast<float *>(s_tau + ns);
+    int *s_n0 = reinterpret_cast<int *>(s_amp + ns);
+    double *red = reinterpret_cast<double *>(gsm + (((size_t)ns * (4 * sizeof(double) + 8) + 15) & ~(size_t)15));
+    int *redn = reinterpret_cast<int *>(red + 256);
     const int scan = blockIdx.x, i = blockIdx.y, tid = threadIdx.x;
     const unsigned long long seed = a.seeds[scan];
-    const int ns = a.n_clutter + 1;
-    if (tid == 0) {
-        SplitMix64 r{seed ^ (a.salt << 56)};
-        for (int s = 0; s < ns; ++s) {
-            const double rr = a.radius * sqrt(r.uniform());
-            const double th = 2.0 * M_PI * r.uniform();
-            sx[s] = rr * cos(th);
-            sy[s] = rr * sin(th);
-        }
-        srho[0] = 1.0;
-        for (int s = 1; s < ns; ++s) srho[s] = 0.1 * r.uniform();
-        if (a.tumours && i == 0) {
-            a.tumours[3 * scan + 0] = sx[0];
-            a.tumours[3 * scan + 1] = sy[0];
-            a.tumours[3 * scan + 2] = 0.0;
-        }
+    // scene: scatterer s takes draws 2 s (radius) and 2 s + 1 (angle); clutter point
+    // s >= 1 its reflectivity from draw 2 ns + s - 1, after every position
+    const unsigned long long s0 = seed ^ (a.salt << 56);
+    for (int s = tid; s < ns; s += 256) {
+        const double rr = a.radius * sqrt(splitmix_uniform(s0, 2ull * s));
+        const double th = 2.0 * M_PI * splitmix_uniform(s0, 2ull * s + 1);
+        sx[s] = rr * cos(th);
+        sy[s] = rr * sin(th);
+        srho[s] = s == 0 ? 1.0 : 0.1 * splitmix_uniform(s0, 2ull * ns + s - 1);
     }
     __syncthreads();
+    if (a.tumours && i == 0 && tid == 0) {
+        a.tumours[3 * scan + 0] = sx[0];
+        a.tumours[3 * scan + 1] = sy[0];
+        a.tumours[3 * scan + 2] = 0.0;
+    }
     const float sigma = (float)a.sigma, f0 = (float)a.f0, inv_peak = (float)(1.0 / a.peak);
     const double half = 6.0 * a.sigma;
-    // tumour echo power: mean over antennas of its mean square within 3 sigma of arrival
+    // tumour echo power: mean over antennas of its mean square within 3 sigma of arrival.
+    // G threads per antenna (G = 256 / M rounded down to a power of two, at least 1) take
+    // every G-th sample of its window; the parts are added in thread order.
+    int G = 1;
+    while (2 * G * a.M <= 256) G *= 2;
+    const int per = 256 / G;   // antennas per pass
     double pw = 0.0;
-    for (int k = tid; k < a.M; k += 256) {
-        const double ax = a.ant_pos[3 * k], ay = a.ant_pos[3 * k + 1], az = a.ant_pos[3 * k + 2];
-        const double dx = sx[0] - ax, dy = sy[0] - ay, dz = -az;
-        const double dist = sqrt(dx * dx + dy * dy + dz * dz);
-        const double tau = 2.0 * dist / a.v;
-        const double amp = (0.01 / dist) * (0.01 / dist);
+    for (int k0 = 0; k0 < a.M; k0 += per) {
+        const int k = k0 + tid / G, g = tid % G;
         double sq = 0.0;
         int cnt = 0;
-        const long long lo = (long long)ceil((tau - 3.0 * a.sigma - a.t0) / a.dt);
-        const long long hi = (long long)floor((tau + 3.0 * a.sigma - a.t0) / a.dt);
-        for (long long m = lo - 1; m <= hi + 1; ++m) {
-            if (m < 0 || m >= a.T) continue;
-            const double t = a.t0 + m * a.dt - tau;
-            if (fabs(t) > 3.0 * a.sigma) continue;
-            const double p = fabs(t) <= half
-                                 ? amp * sin(2.0 * M_PI * a.f0 * t) * exp(-(t * t) / (2.0 * a.sigma * a.sigma)) / a.peak
-                                 : 0.0;
-            sq += p * p;
-            ++cnt;
+        if (k < a.M) {
+            const double ax = a.ant_pos[3 * k], ay = a.ant_pos[3 * k + 1], az = a.ant_pos[3 * k + 2];
+            const double dx = sx[0] - ax, dy = sy[0] - ay, dz = -az;
+            const double dist = sqrt(dx * dx + dy * dy + dz * dz);
+            const double tau = 2.0 * dist / a.v;
+            const double amp = (0.01 / dist) * (0.01 / dist);
+            const long long lo = (long long)ceil((tau - 3.0 * a.sigma - a.t0) / a.dt);
+            const long long hi = (long long)floor((tau + 3.0 * a.sigma - a.t0) / a.dt);
+            for (long long m = lo - 1 + g; m <= hi + 1; m += G) {
+                if (m < 0 || m >= a.T) continue;
+                const double t = a.t0 + m * a.dt - tau;
+                if (fabs(t) > 3.0 * a.sigma) continue;
+                const double p = fabs(t) <= half
+                                     ? amp * sin(2.0 * M_PI * a.f0 * t) * exp(-(t * t) / (2.0 * a.sigma * a.sigma)) / a.peak
+                                     : 0.0;
+                sq += p * p;
+                ++cnt;
+            }
         }
-        pw += cnt ? sq / cnt : 0.0;
-    }
-    red[tid] = pw;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) red[tid] += red[tid + o];
+        __syncthreads();   // the previous pass's parts are consumed
+        red[tid] = sq;
+        redn[tid] = cnt;
         __syncthreads();
+        if (g == 0 && k < a.M) {
+            double sk = 0.0;
+            int ck = 0;
+            for (int j = 0; j < G; ++j) { sk += red[tid + j]; ck += redn[tid + j]; }
+            red[tid] = ck ? sk / ck : 0.0;   // this antenna's mean square
+        }
+        __syncthreads();
+        if (tid == 0)
+            for (int kk = k0; kk < a.M && kk < k0 + per; ++kk) pw += red[(kk - k0) * G];
     }
+    __syncthreads();
+    if (tid == 0) red[0] = pw;
+    __syncthreads();
     const double ps = red[0] / a.M;
     const double sigma_n = sqrt(ps / pow(10.0, a.snr_db / 10.0));
     // this workgroup's antenna
@@ -202,6 +222,6 @@ extern "C" int uwb_generate_disc_scans(const uwb_gen_recipe *r, const float *ant
     a.salt = r->salt;
     if (a.T > 256 * 8) return UWB_EUNSUPPORTED;   // one pass of 8 samples per lane
     if (a.M > 65535) return UWB_EUNSUPPORTED;
-    hipLaunchKernelGGL(k_gen_disc, dim3(n, a.M), dim3(256), 0, (hipStream_t)stream, a);
+    hipLaunchKernelGGL(k_gen_disc, dim3(n, a.M), dim3(256), gen_lds_bytes(a.n_clutter + 1), (hipStream_t)stream, a);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }
