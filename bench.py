@@ -126,10 +126,10 @@ def main():
             if record:
                 ev[k][i].record()
         mark("das", 0)
-        uwb.image_batch(batch, grid, 0, W, img_das)
+        uwb.image_batch(batch, grid, 0, W, img_das, bc=bc)
         mark("das", 1)
         mark("dmas", 0)
-        uwb.image_batch(batch, grid, 1, W, img_dmas)
+        uwb.image_batch(batch, grid, 1, W, img_dmas, bc=bc)
         mark("dmas", 1)
         mark("arg", 0)
         uwb.argmax_batch_async(batch, grid, img_das, 0, W, pk_das, ws_argmax, bc=bc)
@@ -164,6 +164,23 @@ def main():
     med = {k: float(np.median(v)) for k, v in times.items()}
     das_gvas = va / (med["das"] * 1e-3) / 1e9
     dmas_gvas = va / (med["dmas"] * 1e-3) / 1e9
+
+    # the two walks of a step are launch-bound at this batch (about a dozen small kernels each): the
+    # same calls replayed as one HIP graph (kernels only: no memsets, no host synchronisation)
+    wg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(wg):
+        for bf in (0, 1):
+            out, ws = walk_bufs[bf]
+            uwb.segment_refine_batch_async(batch, grid, trees[bf], W, out=out, workspace=ws, bc=bc)
+    wg.replay()
+    torch.cuda.synchronize()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record()
+    for _ in range(20):
+        wg.replay()
+    g1.record()
+    torch.cuda.synchronize()
+    walk_graph_ms = g0.elapsed_time(g1) / 20
 
     # accuracy of the walks against the full-resolution DMAS detection (outside the timed region)
     full = uwb._peaks(pk_dmas, B)
@@ -209,6 +226,7 @@ def main():
         "dmas_gvas": round(dmas_gvas, 2),
         "hierarchical": {
             "walk_scans_per_s": round(2 * B / (med["walk"] * 1e-3), 1),
+            "walk_scans_per_s_hip_graph": round(2 * B / (walk_graph_ms * 1e-3), 1),
             "full_dmas_scans_per_s": round(B / ((med["dmas"] + med["arg"] / 2) * 1e-3), 1),
             "dmas_walk_within_1_voxel_of_full_dmas": loc[1],
             "das_walk_within_1_voxel_of_full_dmas": loc[0],

@@ -115,12 +115,14 @@ def dmas(scan, grid, window=11, out=None):
     return image(scan, grid, UWB_DMAS, window, out)
 
 
-def image_batch(batch: DeviceBatch, grid, beamformer: int, window: int = 11, out=None):
+def image_batch(batch: DeviceBatch, grid, beamformer: int, window: int = 11, out=None, bc=None):
+    """bc: the batch's descriptor (batch.c()), built once by callers that launch repeatedly or capture the call
+    in a graph (building it reads the per-scan parameters back to the host)."""
     if out is None:
         out = torch.empty((batch.n_scans,) + _img_shape(grid), dtype=torch.float32, device=batch.traces.device)
     _need_cuda(out, "out")
     fn = lib().uwb_dmas_batch if beamformer == UWB_DMAS else lib().uwb_das_batch
-    bc, gc = batch.c(), grid_c(grid)
+    bc, gc = (bc if bc is not None else batch.c()), grid_c(grid)
     check(fn(ctypes.byref(bc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)), "image_batch")
     return out
 
