@@ -45,7 +45,10 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2      # wave64 FP32 instructions per second
 # HBM bytes per launch of the DMAS kernel at the default batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a 256 MiB copy); valid only for the kernel
 # sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
-TRAFFIC = {"source_hash": "b5be7710d1a3cc59", "batch": 256, "bytes": 311048631}
+TRAFFIC = {"source_hash": "b5be7710d1a3cc59", "batch": 256, "bytes": 311048631,
+           "valu_per_va": 60.2}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of the DMAS kernel
+LDS_PEAK = 128 * 256 * 2.4e9        # B/s: 128 B/clk/CU
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2   # wave64 FP32 VALU instructions/s (two cycles each)
 
 
 def _kernel_source_hash() -> str:
@@ -196,6 +199,8 @@ def main():
 
     fl = flops_per_va(1, W) * va
     achieved = fl / (med["dmas"] * 1e-3)
+    counters_valid = TRAFFIC["source_hash"] == _kernel_source_hash()
+    va_rate = va / (med["dmas"] * 1e-3)            # DMAS voxel·antenna/s
     traffic = TRAFFIC["bytes"] if (TRAFFIC["source_hash"] == _kernel_source_hash() and B == TRAFFIC["batch"]) \
         else None
     out = {
@@ -220,7 +225,12 @@ def main():
                      "flops_per_voxel_antenna": flops_per_va(1, W),
                      "avg_launch_ms": round(med["dmas"], 5),
                      "hbm_gbs": round(traffic / (med["dmas"] * 1e-3) / 1e9, 1) if traffic else None,
-                     "hbm_frac": round(traffic / (med["dmas"] * 1e-3) / 8e12, 4) if traffic else None},
+                     "hbm_frac": round(traffic / (med["dmas"] * 1e-3) / 8e12, 4) if traffic else None,
+                     # the gather's other on-chip bounds: 48 B of LDS reads per voxel·antenna against
+                     # 128 B/clk/CU, and VALU issue (counted instructions, while the sources match)
+                     "lds_frac": round(va_rate * 48 / LDS_PEAK, 4),
+                     "valu_issue_frac": round(va_rate * TRAFFIC["valu_per_va"] / 64 / VALU_ISSUE_PEAK, 4)
+                     if counters_valid else None},
         "components_ms": {k: round(v, 5) for k, v in med.items()},
         "das_gvas": round(das_gvas, 2),
         "dmas_gvas": round(dmas_gvas, 2),
