@@ -45,7 +45,7 @@ VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2      # wave64 FP32 instructions per second
 # HBM bytes per launch of the DMAS kernel at the default batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a 256 MiB copy); valid only for the kernel
 # sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
-TRAFFIC = {"source_hash": "b5be7710d1a3cc59", "batch": 256, "bytes": 311048631,
+TRAFFIC = {"source_hash": "f1d84d8ef9492e59", "batch": 256, "bytes": 311049571,
            "valu_per_va": 60.2}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of the DMAS kernel
 LDS_PEAK = 128 * 256 * 2.4e9        # B/s: 128 B/clk/CU
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2   # wave64 FP32 VALU instructions/s (two cycles each)

@@ -195,30 +195,51 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
             } else {
                 leg_d2(e, part);
             }
-#pragma unroll
-            for (int v = 0; v < VPL; ++v) {
+            // software-pipelined over the lane's voxels: voxel v + 1's delay and window reads are
+            // issued before voxel v's taps, so their LDS latency overlaps arithmetic
+            auto locate = [&](int v, float &f, const float *&p) {
                 float tau;
                 if (MS) tau = dtx[v] + __builtin_amdgcn_sqrtf(leg_v(er, partr, v));
                 else tau = __builtin_amdgcn_sqrtf(leg_v(e, part, v)) - t0s;
                 const float fl = floorf(tau);
-                const float f = tau - fl;
-                const float g = 1.f - f;
+                f = tau - fl;
                 int idx = (int)fl + base;
                 idx = min(max(idx, lob), hib);
-                const float *p = stage + idx;
-                float y[W + 1];
+                p = stage + idx;
+            };
+            float fc, yc[W + 1];
+            {
+                const float *p;
+                locate(0, fc, p);
 #pragma unroll
-                for (int k = 0; k <= W; ++k) y[k] = p[k];
+                for (int k = 0; k <= W; ++k) yc[k] = p[k];
+            }
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) {
+                float fn = 0.f, yn[W + 1];
+                if (v + 1 < VPL) {
+                    const float *p;
+                    locate(v + 1, fn, p);
+#pragma unroll
+                    for (int k = 0; k <= W; ++k) yn[k] = p[k];
+                }
+                __builtin_amdgcn_sched_barrier(0);   // keep those reads ahead of this voxel's taps
+                const float f = fc, g = 1.f - fc;
                 if (BF == UWB_DAS) {
 #pragma unroll
-                    for (int k = 0; k < W; ++k) acc[v][k] = fmaf(f, y[k + 1], fmaf(g, y[k], acc[v][k]));
+                    for (int k = 0; k < W; ++k) acc[v][k] = fmaf(f, yc[k + 1], fmaf(g, yc[k], acc[v][k]));
                 } else {
 #pragma unroll
                     for (int k = 0; k < W; ++k) {
-                        const float s = fmaf(f, y[k + 1], g * y[k]);
+                        const float s = fmaf(f, yc[k + 1], g * yc[k]);
                         pre[v][k] = fmaf(s, acc[v][k], pre[v][k]);
                         acc[v][k] += s;
                     }
+                }
+                if (v + 1 < VPL) {
+                    fc = fn;
+#pragma unroll
+                    for (int k = 0; k <= W; ++k) yc[k] = yn[k];
                 }
             }
         }
