@@ -310,9 +310,11 @@ int uwb_segment_composite_batch(const uwb_scan_batch *scans, const uwb_grid *fin
  * All scans of a plan are planar (nz == 1) or all volumetric.
  * uwb_batch_run enqueues one replay on `stream`.
  * uwb_batch_autotune times every candidate configuration on this batch
- * (`reps` replays each, on `stream`, synchronising), keeps the fastest, and if
- * the environment variable UWB_TUNE_CACHE names a file, records it there; a
- * later plan of the same batch shape created with cfg == NULL reuses it.
+ * (`reps` replays each, on `stream`, synchronising) and keeps, among those
+ * within 2 % of the fastest, the one whose median scan completes first (the
+ * serving latency); if the environment variable UWB_TUNE_CACHE names a file, it
+ * records the choice there, and a later plan of the same batch shape created
+ * with cfg == NULL reuses it.
  * uwb_batch_timestamps synchronises `stream` and returns, per scan, the time
  * from the start of the last replay to the moment its last tile finished
  * (ns, device clock; -1 if not finished).
