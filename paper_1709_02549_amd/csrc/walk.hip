@@ -5,8 +5,8 @@
 // Launch sequence per batch (stream-ordered, no host round trip):
 //   per-level walk, for every level l:
 //     k_grid64      g^d lattice of every active scan's box, FP64      -> ws
-//     k_pl_level    one workgroup per scan: parent / child statistics by
-//                   block reductions, W/B test, selection             -> result, state
+//     k_pl_level    one wavefront per scan: parent / child statistics by
+//                   wavefront reductions, W/B test, selection          -> result, state
 //   paper walk:
 //     k_grid64      decimated image of the whole grid                  -> ws
 //     k_walk_paper  one wavefront per scan runs every level on those samples
