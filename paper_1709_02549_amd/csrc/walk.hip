@@ -340,9 +340,8 @@ __global__ __launch_bounds__(kBlock) void k_walk_paper(const WalkArgs a, int n_s
 // ----------------------------------------------------------------------------
 // Level-synchronous per-level walk: for every level, k_grid64 images the g^d
 // lattice of each active scan's box (many workgroups per scan) and k_pl_level
-// takes that level's statistics, W/B test and decision (one workgroup per
-// scan), carrying the previous level's figures in PLState.  Same decisions,
-// same arithmetic as the single-workgroup walk, far more parallelism.
+// takes that level's statistics, W/B test and decision (one wavefront per
+// scan), carrying the previous level's figures in PLState.
 // ----------------------------------------------------------------------------
 __global__ void k_pl_init(const WalkArgs a, int n_scans) {
     const int scan = blockIdx.x * blockDim.x + threadIdx.x;
