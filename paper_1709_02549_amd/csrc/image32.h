@@ -37,6 +37,7 @@ struct TileJob {
     int rs;               // staged samples per channel (LDS stride)
     int chunk;            // channels staged per pass
     int ms;               // multistatic: antennas per side (channel i*ms + j), 0: monostatic
+    int64_t p0;           // band form: first voxel (linear, x fastest) of the band
 };
 
 // Tile geometry.  2D: 16 (x) by 16*VPL (y); lane (tx, ty) owns y = ty + 16 v.
@@ -48,11 +49,28 @@ template <bool D3, int VPL> struct TileShape {
     __device__ static void get(int &x, int &y, int &z) { x = X; y = Y; z = Z; }
 };
 
+// Bounding box (inclusive finest indices) of the voxels p0 .. p1 of an nx x ny x nz grid
+// in linear order: within one row its own columns; across rows whole rows; across
+// slabs whole slabs.
+__host__ __device__ inline void band_box(int64_t p0, int64_t p1, int nx, int ny, int &x0, int &x1, int &y0, int &y1,
+                                         int &z0, int &z1) {
+    const int64_t sxy = (int64_t)nx * ny;
+    const int ax = (int)(p0 % nx), ay = (int)((p0 / nx) % ny), az = (int)(p0 / sxy);
+    const int bx = (int)(p1 % nx), by = (int)((p1 / nx) % ny), bz = (int)(p1 / sxy);
+    z0 = az; z1 = bz;
+    y0 = az == bz ? ay : 0; y1 = az == bz ? by : ny - 1;
+    x0 = (az == bz && ay == by) ? ax : 0; x1 = (az == bz && ay == by) ? bx : nx - 1;
+}
+
 // Monostatic (MS = false): channel i is antenna i, delay s |r - a_i| - t0s (Eq. (1)).
 // Multistatic (MS = true): channel i*M + j, delay (s/2)(|r - a_i| + |r - a_j|) - t0s
 // (Eq. (2)); the table then holds the transmitter's and the receiver's offsets.
-template <int BF, int W, bool D3, int VPL, bool MS = false>
+// BAND (one voxel per lane only): the workgroup images the 256 consecutive voxels
+// from j.p0 (x fastest) instead of a tile -- for small, ragged grids, whose tiles
+// would idle many lanes; j.rs must cover the band's bounding box (band_box).
+template <int BF, int W, bool D3, int VPL, bool MS = false, bool BAND = false>
 __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
+    static_assert(!BAND || VPL == 1, "a band holds one voxel per lane");
     using TS = TileShape<D3, VPL>;
     constexpr int H = (W - 1) / 2;
     constexpr int TX = TS::X, TY = TS::Y, TZ = TS::Z;
@@ -70,14 +88,20 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
     const float qy = (float)(sc * j.g.pitch[1]);
     const float qz = (float)(sc * j.g.pitch[2]);
     const float t0s = (float)j.t0s;
-    // this scan's own staging need must fit the launch's (a batch is sized for its bound)
-    const double ex = (TX - 1) * j.g.pitch[0], ey = (TY - 1) * j.g.pitch[1], ez = (TZ - 1) * j.g.pitch[2];
-    const double need = ceil(j.s * sqrt(ex * ex + ey * ey + ez * ez)) + W + 6;
-    const bool fits = need <= (double)rs || rs >= T + 2 * W + 2;
 
-    // lane -> voxels
+    // lane -> voxels, and the bounding box of the workgroup's voxels (inclusive finest indices)
     int vx, vy[VPL], vz[VPL];
-    if (!D3) {
+    int bx0, by0, bz0, bx1, by1, bz1;
+    bool live = true;   // band form: the lane's voxel exists
+    if (BAND) {
+        const int64_t n = (int64_t)nx * ny * nz, sxy = (int64_t)nx * ny;
+        const int64_t p = j.p0 + tid, p1 = min(j.p0 + kBlock, n) - 1, pc = min(p, p1);
+        live = p <= p1;
+        vx = (int)(pc % nx);
+        vy[0] = (int)((pc / nx) % ny);
+        vz[0] = (int)(pc / sxy);
+        band_box(j.p0, p1, nx, ny, bx0, bx1, by0, by1, bz0, bz1);
+    } else if (!D3) {
         vx = tx0 + (tid & 15);
 #pragma unroll
         for (int v = 0; v < VPL; ++v) { vy[v] = ty0 + (tid >> 4) + 16 * v; vz[v] = 0; }
@@ -86,13 +110,19 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
 #pragma unroll
         for (int v = 0; v < VPL; ++v) { vy[v] = ty0 + ((tid >> 3) & 7); vz[v] = tz0 + (tid >> 6) + 4 * v; }
     }
+    if (!BAND) {
+        bx0 = tx0; by0 = ty0; bz0 = tz0;
+        bx1 = min(tx0 + TX, nx) - 1; by1 = min(ty0 + TY, ny) - 1; bz1 = min(tz0 + TZ, nz) - 1;
+    }
+    // this scan's own staging need must fit the launch's (a batch is sized for its bound)
+    const double ex = (BAND ? bx1 - bx0 : TX - 1) * j.g.pitch[0], ey = (BAND ? by1 - by0 : TY - 1) * j.g.pitch[1],
+                 ez = (BAND ? bz1 - bz0 : TZ - 1) * j.g.pitch[2];
+    const double need = ceil(j.s * sqrt(ex * ex + ey * ey + ez * ez)) + W + 6;
+    const bool fits = need <= (double)rs || rs >= T + 2 * W + 2;
     const float fx = (float)vx;
     float fy[VPL], fz[VPL];
 #pragma unroll
     for (int v = 0; v < VPL; ++v) { fy[v] = (float)vy[v]; fz[v] = (float)vz[v]; }
-
-    // bounding box of the tile's voxels (inclusive finest indices)
-    const int bx1 = min(tx0 + TX, nx) - 1, by1 = min(ty0 + TY, ny) - 1, bz1 = min(tz0 + TZ, nz) - 1;
 
     float acc[VPL][W];
     float pre[BF == UWB_DMAS ? VPL : 1][BF == UWB_DMAS ? W : 1];
@@ -129,9 +159,9 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
                 const double cx = sc * (j.g.origin[0] - ax);
                 const double cy = sc * (j.g.origin[1] - ay);
                 const double cz = sc * (j.g.origin[2] - az);
-                const double lx = cx + tx0 * dqx, hx = cx + bx1 * dqx;
-                const double ly = cy + ty0 * dqy, hy = cy + by1 * dqy;
-                const double lz = cz + tz0 * dqz, hz = cz + bz1 * dqz;
+                const double lx = cx + bx0 * dqx, hx = cx + bx1 * dqx;
+                const double ly = cy + by0 * dqy, hy = cy + by1 * dqy;
+                const double lz = cz + bz0 * dqz, hz = cz + bz1 * dqz;
                 // nearest point of the tile's box to the antenna (the antenna is at 0 here)
                 const double mx = fmin(fmax(0.0, lx), hx), my = fmin(fmax(0.0, ly), hy), mz = fmin(fmax(0.0, lz), hz);
                 tmin += sqrt(mx * mx + my * my + mz * mz);
@@ -254,7 +284,7 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
             en = fmaf(q, q, en);
         }
         if (!fits) en = __builtin_nanf("");
-        if (vx < nx && vy[v] < ny && vz[v] < nz)
+        if (live && vx < nx && vy[v] < ny && vz[v] < nz)
             j.img[((int64_t)vz[v] * ny + vy[v]) * nx + vx] = en;
     }
 }

@@ -2,8 +2,8 @@
 // every scan's region of interest and its maximal-energy voxel (the detection).
 //
 // k_roi32   images the ROI (box read from the scan's result) with the tile body of
-//           the full-resolution FP32 kernel (one voxel per lane, tiles of 16 x 16 or
-//           8 x 8 x 4), the ROI taken as a grid of its own   -> roi32
+//           the full-resolution FP32 kernel (one voxel per lane: tiles, or bands of
+//           256 consecutive voxels for a ragged ROI), the ROI as a grid of its own -> roi32
 // k_roi_pick one wavefront per scan: decides the detection in FP64, as for the
 //           full image -- every ROI voxel whose FP32 energy is within kCandRel of
 //           the ROI's FP32 maximum is re-evaluated in FP64 (a whole wave per voxel,
@@ -13,6 +13,7 @@
 // FP32 rounding moves an energy by about 1e-5 of the peak, far inside kCandRel, so
 // the FP64 maximum is always among the candidates: the decision is the one a
 // double-precision evaluation of the whole ROI would take.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -32,13 +33,16 @@ struct RoiArgs {
     int64_t roi_cap;
     float *roi_img;              // optional copy, scan s at s * roi_img_stride
     int64_t roi_img_stride;
-    int rs, chunk;               // staging stride and channels per pass
+    int lds_bytes;               // staging space of a workgroup
     int bf, window;
 };
 
-// Grid: x = scan, y = tile of the scan's own ROI (row-major over its tiles), so that
-// the workgroups with work -- every scan's first tiles -- are dispatched before the
-// ones past a scan's ROI, which only the largest possible ROI needs.
+// Grid: x = scan, y = group of 256 voxels of the scan's own ROI -- a tile when the ROI
+// is a whole number of tiles, else a band of consecutive voxels (x fastest), so that a
+// ragged ROI idles only part of its last band (as 16 x 16 tiles, a 37 x 37 ROI idles
+// 41 % of the lanes).  The groups with work -- every scan's first ones -- are dispatched
+// before the ones past a scan's ROI, which only the largest possible ROI needs.  Each
+// group's staging stride follows from its own bounding box.
 template <int BF, int W, bool D3, bool MS>
 __global__ __launch_bounds__(kBlock) void k_roi32(const RoiArgs a) {
     extern __shared__ float smem[];
@@ -50,14 +54,16 @@ __global__ __launch_bounds__(kBlock) void k_roi32(const RoiArgs a) {
         j.g.pitch[d] = a.g.pitch[d];
         j.g.origin[d] = a.g.origin[d] + roi[2 * d] * a.g.pitch[d];
     }
+    const int64_t n = (int64_t)j.g.dims[0] * j.g.dims[1] * j.g.dims[2];
     // a ROI larger than its slot (never, for a planned walk) is not imaged
-    if ((int64_t)j.g.dims[0] * j.g.dims[1] * j.g.dims[2] > a.roi_cap) return;
+    if (n > a.roi_cap) return;
+    // tiles of 16 x 16 (2D) or 8 x 8 x 4 when the ROI is a whole number of them (compact spans),
+    // else bands: either way kBlock voxels per workgroup, as many groups
     int tx, ty, tz;
     TileShape<D3, 1>::get(tx, ty, tz);
-    const int ntx = (j.g.dims[0] + tx - 1) / tx, nty = (j.g.dims[1] + ty - 1) / ty;
-    const int ntz = (j.g.dims[2] + tz - 1) / tz;
-    const int ntiles = ntx * nty * ntz;
-    if ((int)blockIdx.y >= ntiles) return;   // uniform per workgroup
+    const bool tiled = j.g.dims[0] % tx == 0 && j.g.dims[1] % ty == 0 && j.g.dims[2] % tz == 0;
+    const int64_t ngroups = (n + kBlock - 1) / kBlock;
+    if ((int64_t)blockIdx.y >= ngroups) return;   // uniform per workgroup
     const ScanConst sc = scan_const(a.ss, scan);
     j.pos = sc.pos;
     j.tr = sc.tr;
@@ -66,15 +72,28 @@ __global__ __launch_bounds__(kBlock) void k_roi32(const RoiArgs a) {
     j.T = a.ss.n_samp;
     j.s = sc.s;
     j.t0s = sc.t0s;
-    j.rs = a.rs;
-    j.chunk = a.chunk;
     j.ms = a.ss.ms;
-    // (more tiles than the grid's 65535 rows: the rows stride over them)
-    for (int t = blockIdx.y; t < ntiles; t += gridDim.y) {
-        j.tx0 = (t % ntx) * tx;
-        j.ty0 = ((t / ntx) % nty) * ty;
-        j.tz0 = (t / (ntx * nty)) * tz;
-        image_tile<BF, W, D3, 1, MS>(j, smem);
+    const int ntx = j.g.dims[0] / tx, nty = j.g.dims[1] / ty;
+    // (more groups than the grid's 65535 rows: the rows stride over them)
+    for (int64_t b = blockIdx.y; b < ngroups; b += gridDim.y) {
+        int x0, x1, y0, y1, z0, z1;
+        if (tiled) {
+            j.tx0 = x0 = (int)(b % ntx) * tx;
+            j.ty0 = y0 = (int)((b / ntx) % nty) * ty;
+            j.tz0 = z0 = (int)(b / ((int64_t)ntx * nty)) * tz;
+            x1 = x0 + tx - 1; y1 = y0 + ty - 1; z1 = z0 + tz - 1;
+        } else {
+            j.tx0 = j.ty0 = j.tz0 = 0;
+            j.p0 = b * kBlock;
+            band_box(j.p0, min(j.p0 + kBlock, n) - 1, j.g.dims[0], j.g.dims[1], x0, x1, y0, y1, z0, z1);
+        }
+        // staging stride and channels per pass for this group (uniform: kept in scalar registers)
+        j.rs = __builtin_amdgcn_readfirstlane(staged_samples(sc.s, (x1 - x0) * a.g.pitch[0], (y1 - y0) * a.g.pitch[1],
+                                                             (z1 - z0) * a.g.pitch[2], W, a.ss.n_samp));
+        j.chunk = __builtin_amdgcn_readfirstlane(min(a.lds_bytes / (j.rs * 4 + (MS ? 32 : 16)), min(j.M, kBlock)));
+        if (j.chunk < 1) continue;   // never: the host sizes the LDS for the widest group
+        if (tiled) image_tile<BF, W, D3, 1, MS, false>(j, smem);
+        else image_tile<BF, W, D3, 1, MS, true>(j, smem);
     }
 }
 
@@ -194,8 +213,6 @@ bool launch_bf(int window, bool d3, dim3 grid, size_t lds, hipStream_t st, const
 int launch_roi(const WalkArgs &w, int bf, int n_scans, hipStream_t st) {
     if (n_scans < 1) return UWB_OK;
     const bool d3 = w.g.dims[2] > 1;
-    int tx, ty, tz;
-    tile_shape(d3, 1, &tx, &ty, &tz);
     RoiArgs a;
     a.ss = w.ss;
     a.g = w.g;
@@ -206,20 +223,18 @@ int launch_roi(const WalkArgs &w, int bf, int n_scans, hipStream_t st) {
     a.roi_img_stride = w.roi_img_stride;
     a.bf = bf;
     a.window = w.window;
-    const int64_t tiles = (int64_t)((w.roi_side[0] + tx - 1) / tx) * ((w.roi_side[1] + ty - 1) / ty) *
-                          ((w.roi_side[2] + tz - 1) / tz);   // of the largest ROI
-    if (tiles < 1) return UWB_EUNSUPPORTED;
-    // staging sized for the largest samples-per-metre of the batch (lower bounds of v and dt)
+    const int64_t bands = (w.roi_cap + kBlock - 1) / kBlock;   // of the largest ROI
+    if (bands < 1) return UWB_EUNSUPPORTED;
+    // LDS: every channel at the widest span a band can have (the whole largest ROI), within
+    // the budget; the kernel sizes each band's own stride and chunk to it
     const double s_max = 2.0 / (w.ss.v * w.ss.dt);
-    a.rs = staged_samples(s_max, (tx - 1) * w.g.pitch[0], (ty - 1) * w.g.pitch[1], (tz - 1) * w.g.pitch[2], w.window,
-                          w.ss.n_samp);
-    const int per_ch = a.rs * 4 + (w.ss.ms ? 32 : 16);   // staged samples + table entries
+    const int rs_max = staged_samples(s_max, (w.roi_side[0] - 1) * w.g.pitch[0], (w.roi_side[1] - 1) * w.g.pitch[1],
+                                      (w.roi_side[2] - 1) * w.g.pitch[2], w.window, w.ss.n_samp);
+    const int per_ch = rs_max * 4 + (w.ss.ms ? 32 : 16);   // staged samples + table entries
     if (per_ch > kLdsBudget) return UWB_EUNSUPPORTED;
-    a.chunk = kLdsBudget / per_ch;
-    if (a.chunk > kBlock) a.chunk = kBlock;
-    if (a.chunk > w.ss.n_ant) a.chunk = w.ss.n_ant;
-    const size_t lds = (size_t)a.chunk * per_ch;
-    const dim3 grid((unsigned)n_scans, (unsigned)(tiles < 65535 ? tiles : 65535));
+    a.lds_bytes = (int)std::min<int64_t>((int64_t)per_ch * std::min(w.ss.n_ant, kBlock), kLdsBudget);
+    const size_t lds = (size_t)a.lds_bytes;
+    const dim3 grid((unsigned)n_scans, (unsigned)(bands < 65535 ? bands : 65535));
     const bool ok = bf == UWB_DMAS ? launch_bf<UWB_DMAS>(w.window, d3, grid, lds, st, a)
                                    : launch_bf<UWB_DAS>(w.window, d3, grid, lds, st, a);
     if (!ok) return UWB_EINVAL;
