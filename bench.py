@@ -40,12 +40,11 @@ def flops_per_va(bf: int, window: int) -> int:
 
 # MI355X vector FP32: 256 CU x 4 SIMD x 32 FP32 lanes per clock x 2 flop (FMA) x 2.4 GHz
 PEAK_FP32 = 157.3e12
-VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2      # wave64 FP32 instructions per second (2 cycles each)
 
 # HBM bytes per launch of the DMAS kernel at the default batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a 256 MiB copy); valid only for the kernel
 # sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
-TRAFFIC = {"source_hash": "f1d84d8ef9492e59", "batch": 256, "bytes": 311049571,
+TRAFFIC = {"source_hash": "cc3a337e564f70d8", "batch": 256, "bytes": 311048047,
            "valu_per_va": 60.2}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of the DMAS kernel
 LDS_PEAK = 128 * 256 * 2.4e9        # B/s: 128 B/clk/CU
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2   # wave64 FP32 VALU instructions/s (two cycles each)
