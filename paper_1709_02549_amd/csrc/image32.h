@@ -49,6 +49,14 @@ template <bool D3, int VPL> struct TileShape {
     __device__ static void get(int &x, int &y, int &z) { x = X; y = Y; z = Z; }
 };
 
+// floor(x) as an int in one instruction (x finite and within the int range; the
+// compiler fuses floor and conversion only under finite-math flags)
+__device__ __forceinline__ int floor_to_int(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 // Bounding box (inclusive finest indices) of the voxels p0 .. p1 of an nx x ny x nz grid
 // in linear order: within one row its own columns; across rows whole rows; across
 // slabs whole slabs.
@@ -199,8 +207,13 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
         for (int jj = 0; jj < nch; ++jj) {
             const float4 e = tab[TE * jj];
             const float4 er = tab[TE * jj + (MS ? 1 : 0)];
-            const int base = __float_as_int(e.w);
-            const int lob = jj * rs, hib = jj * rs + rs - (W + 1);
+            // window start in the stage = floor(tau) + base, kept within the channel's span
+            // [jj rs, jj rs + rs - W - 1]: tau is clamped to the equivalent integer bounds
+            // [lof, hif] before the floor (same index; a clamped window lies wholly in the
+            // staged zero padding, so its fraction does not matter)
+            const int base = __builtin_amdgcn_readfirstlane(__float_as_int(e.w));
+            const float *sb = stage + base;
+            const float lof = (float)(jj * rs - base), hif = lof + (float)(rs - (W + 1));
             // squared distance from the lane's voxels to one leg's antenna: leg_d2 forms the part
             // shared by the lane's voxels, leg_v adds voxel v's own coordinate
             auto leg_d2 = [&](const float4 &t, float &part) {
@@ -231,11 +244,9 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
                 float tau;
                 if (MS) tau = dtx[v] + __builtin_amdgcn_sqrtf(leg_v(er, partr, v));
                 else tau = __builtin_amdgcn_sqrtf(leg_v(e, part, v)) - t0s;
-                const float fl = floorf(tau);
-                f = tau - fl;
-                int idx = (int)fl + base;
-                idx = min(max(idx, lob), hib);
-                p = stage + idx;
+                tau = __builtin_amdgcn_fmed3f(tau, lof, hif);
+                f = __builtin_amdgcn_fractf(tau);
+                p = sb + floor_to_int(tau);
             };
             float fc, yc[W + 1];
             {

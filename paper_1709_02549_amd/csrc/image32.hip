@@ -46,7 +46,7 @@ struct Args {
 };
 
 template <int BF, int W, bool D3, bool MS>
-__global__ __launch_bounds__(kBlock) void k_image32(const Args a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_image32(const Args a) {
     constexpr int VPL = kImageVpl;
     extern __shared__ float smem[];
     const int scan = blockIdx.y;
