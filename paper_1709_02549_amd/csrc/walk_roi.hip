@@ -4,12 +4,13 @@
 // k_roi32   images the ROI (box read from the scan's result) with the tile body of
 //           the full-resolution FP32 kernel (one voxel per lane: tiles, or bands of
 //           256 consecutive voxels for a ragged ROI), the ROI as a grid of its own -> roi32
-// k_roi_pick one wavefront per scan: decides the detection in FP64, as for the
+// k_roi_pick one workgroup per scan: decides the detection in FP64, as for the
 //           full image -- every ROI voxel whose FP32 energy is within kCandRel of
 //           the ROI's FP32 maximum is re-evaluated in FP64 (a whole wave per voxel,
-//           channels over the lanes), and the winner is the lowest finest-grid index
-//           within the FP64 tie band kTieRel of the largest of those values; it also
-//           copies the ROI image to the caller's buffer      -> result, roi_img
+//           channels over the lanes, four voxels at a time), and the winner is the
+//           lowest finest-grid index within the FP64 tie band kTieRel of the largest
+//           of those values; it also copies the ROI image to the caller's buffer
+//                                                            -> result, roi_img
 // FP32 rounding moves an energy by about 1e-5 of the peak, far inside kCandRel, so
 // the FP64 maximum is always among the candidates: the decision is the one a
 // double-precision evaluation of the whole ROI would take.
@@ -105,32 +106,11 @@ __device__ __forceinline__ void roi_pos(const RoiArgs &a, const int *roi, int rn
     rz = a.g.origin[2] + (double)(roi[4] + kz) * a.g.pitch[2];
 }
 
-// One wavefront per scan.  Lane l remembers the l-th FP64-evaluated candidate (in
-// index order), so the tie band needs no second evaluation unless a scan has more
-// than 64 candidates.
-__global__ __launch_bounds__(kBlock) void k_roi_pick(const RoiArgs a, int n_scans) {
-    const int scan = blockIdx.x * kRoiWaves + (threadIdx.x >> 6);
-    if (scan >= n_scans) return;   // uniform per wavefront
-    const int lane = threadIdx.x & 63;
-    uwb_segment_result &R = a.res[scan];
-    const int *roi = R.roi;
-    const int rnx = roi[1] - roi[0], rny = roi[3] - roi[2], rnz = roi[5] - roi[4];
-    const int64_t n = min((int64_t)rnx * rny * rnz, a.roi_cap);
-    const float *v = a.roi32 + (int64_t)scan * a.roi_cap;
-    float *copy = a.roi_img ? a.roi_img + (int64_t)scan * a.roi_img_stride : nullptr;
-
-    // FP32 maximum (and the caller's copy of the image)
-    float m = -INFINITY;
-    for (int64_t p = lane; p < n; p += 64) {
-        const float x = v[p];
-        m = fmaxf(m, x);
-        if (copy) copy[p] = x;
-    }
-    m = wave_maxf(m);
-    const float thr32 = m - (float)kCandRel * fabsf(m);
-
-    // FP64 energies of the candidates in index order, channels over the lanes
-    const ScanConst sc = scan_const(a.ss, scan);
+// The winner among a ROI's FP32 candidates, on one wavefront: candidates evaluated in
+// index order, lane l remembering the l-th, so the tie band needs no second evaluation
+// unless there are more than 64.  Every lane returns the same (index, value).
+__device__ void pick_serial(const RoiArgs &a, const ScanConst &sc, const int *roi, int rnx, int rny, int64_t n,
+                            const float *v, float thr32, int lane, long long &b, double &pv) {
     const int M = a.ss.n_ant, T = a.ss.n_samp;
     double best = -INFINITY;
     int count = 0;
@@ -152,10 +132,8 @@ __global__ __launch_bounds__(kBlock) void k_roi_pick(const RoiArgs a, int n_scan
         }
     }
     const double thr64 = best - kTieRel * fabs(best);
-
-    // lowest ROI index (= lowest finest-grid index) within the FP64 tie band, with its value
-    long long b = LLONG_MAX;
-    double pv = __builtin_nan("");
+    b = LLONG_MAX;
+    pv = __builtin_nan("");
     if (count <= 64) {
         long long mine = lane < count && my_val >= thr64 ? my_idx : LLONG_MAX;
         b = wave_min_ll(mine);
@@ -176,7 +154,89 @@ __global__ __launch_bounds__(kBlock) void k_roi_pick(const RoiArgs a, int n_scan
             }
         }
     }
-    if (lane != 0) return;
+}
+
+constexpr int kPickCap = 512;   // candidates listed in LDS per scan
+
+// One workgroup per scan.  The FP32 maximum over all 256 lanes; the candidates listed in
+// index order in LDS; the four wavefronts evaluate them in parallel (each candidate on a
+// whole wavefront, channels over the lanes, so a candidate's FP64 value does not depend
+// on which wavefront takes it); the winner is the lowest listed candidate within the tie
+// band.  More candidates than the list holds (a flat image) go to the serial pick.
+__global__ __launch_bounds__(kBlock) void k_roi_pick(const RoiArgs a) {
+    __shared__ int cand[kPickCap];
+    __shared__ double cval[kPickCap];
+    __shared__ float redf[kRoiWaves];
+    __shared__ double redd[kRoiWaves];
+    __shared__ long long redl[kRoiWaves];
+    __shared__ int redi[kRoiWaves];
+    const int scan = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uwb_segment_result &R = a.res[scan];
+    const int *roi = R.roi;
+    const int rnx = roi[1] - roi[0], rny = roi[3] - roi[2], rnz = roi[5] - roi[4];
+    const int64_t n = min((int64_t)rnx * rny * rnz, a.roi_cap);
+    const float *v = a.roi32 + (int64_t)scan * a.roi_cap;
+    float *copy = a.roi_img ? a.roi_img + (int64_t)scan * a.roi_img_stride : nullptr;
+
+    // FP32 maximum (and the caller's copy of the image)
+    float m = -INFINITY;
+    for (int64_t p = tid; p < n; p += kBlock) {
+        const float x = v[p];
+        m = fmaxf(m, x);
+        if (copy) copy[p] = x;
+    }
+    m = wave_maxf(m);
+    if (lane == 0) redf[wave] = m;
+    __syncthreads();
+    m = fmaxf(fmaxf(redf[0], redf[1]), fmaxf(redf[2], redf[3]));
+    const float thr32 = m - (float)kCandRel * fabsf(m);
+
+    // candidates (FP32 energy within kCandRel of the maximum) in index order
+    int count = 0;   // uniform
+    for (int64_t p0 = 0; p0 < n; p0 += kBlock) {
+        const int64_t p = p0 + tid;
+        const bool c = p < n && v[p] >= thr32;
+        const unsigned long long mask = __ballot(c);
+        if (lane == 0) redi[wave] = __popcll(mask);
+        __syncthreads();
+        int slot = count + __popcll(mask & ((1ull << lane) - 1));
+        for (int w = 0; w < wave; ++w) slot += redi[w];
+        if (c && slot < kPickCap) cand[slot] = (int)p;
+        count += redi[0] + redi[1] + redi[2] + redi[3];
+        __syncthreads();   // redi read by every lane before the next round writes it
+    }
+
+    const ScanConst sc = scan_const(a.ss, scan);
+    long long b = LLONG_MAX;
+    double pv = __builtin_nan("");
+    if (count > kPickCap || n > INT_MAX) {   // uniform over the workgroup
+        if (wave == 0) pick_serial(a, sc, roi, rnx, rny, n, v, thr32, lane, b, pv);
+    } else {
+        for (int c = wave; c < count; c += kRoiWaves) {   // uniform per wavefront
+            double rx, ry, rz;
+            roi_pos(a, roi, rnx, rny, cand[c], rx, ry, rz);
+            const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, lane, 64);
+            if (lane == 0) cval[c] = e;
+        }
+        __syncthreads();
+        double best = -INFINITY;
+        for (int c = tid; c < count; c += kBlock) best = fmax(best, cval[c]);
+        best = wave_max(best);
+        if (lane == 0) redd[wave] = best;
+        __syncthreads();
+        best = fmax(fmax(redd[0], redd[1]), fmax(redd[2], redd[3]));
+        const double thr64 = best - kTieRel * fabs(best);
+        long long first = LLONG_MAX;   // each lane's lowest list position in the band
+        for (int c = tid; c < count; c += kBlock)
+            if (cval[c] >= thr64) { first = c; break; }
+        first = wave_min_ll(first);
+        if (lane == 0) redl[wave] = first;
+        __syncthreads();
+        first = min(min(redl[0], redl[1]), min(redl[2], redl[3]));
+        if (first != LLONG_MAX) { b = cand[first]; pv = cval[first]; }
+    }
+    if (tid != 0) return;
     if (b == LLONG_MAX) {   // no finite candidate (e.g. a NaN image)
         R.argmax = -1;
         R.peak = __builtin_nan("");
@@ -239,8 +299,7 @@ int launch_roi(const WalkArgs &w, int bf, int n_scans, hipStream_t st) {
                                    : launch_bf<UWB_DAS>(w.window, d3, grid, lds, st, a);
     if (!ok) return UWB_EINVAL;
     if (hipGetLastError() != hipSuccess) return UWB_EHIP;
-    hipLaunchKernelGGL(k_roi_pick, dim3((unsigned)((n_scans + kRoiWaves - 1) / kRoiWaves)), dim3(kBlock), 0, st, a,
-                       n_scans);
+    hipLaunchKernelGGL(k_roi_pick, dim3((unsigned)n_scans), dim3(kBlock), 0, st, a);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }
 

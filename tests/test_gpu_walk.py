@@ -134,14 +134,17 @@ def test_frame_level_and_depth_limits():
         _compare(uwb().segment_refine(uwb().DeviceScan.from_host(s), s.grid, gp), oracle.walk(s, op))
 
 
-@pytest.mark.parametrize("walk,kw", [("paper", dict(min_tumour=0.01)), ("per_level", dict(coarse=8))])
+@pytest.mark.parametrize("walk,kw", [("paper", dict(min_tumour=0.01, frame_final=0.25)),
+                                     ("per_level", dict(coarse=8, frame_final=0.25)),
+                                     ("paper", dict(min_tumour=0.01, frame_final=1.0))])
 @pytest.mark.parametrize("bf", [0, 1])
 def test_flat_scan_ties_everywhere(walk, kw, bf):
     """All-zero traces: every energy is 0, every child and every ROI voxel ties, so each choice falls to the
-    lowest index; the ROI's 100-400 tied voxels exceed the pick's 64-entry candidate list (its second pass)."""
+    lowest index.  100 and 400 tied ROI voxels fill the pick's candidate list in LDS; 1024 (the whole-frame
+    ROI) overflow its 512 entries and take the serial pick, whose 64-entry lane list overflows too."""
     s = synth.c1_scan(3)
     s0 = synth.Scan(s.ant_pos, np.zeros_like(s.traces), s.dt, s.t0, s.v, s.grid)
-    op, gp = _params(beamformer=bf, walk=walk, metric="max", frame_final=0.25, **kw)
+    op, gp = _params(beamformer=bf, walk=walk, metric="max", **kw)
     o = oracle.walk(s0, op)
     g = uwb().segment_refine(uwb().DeviceScan.from_host(s0), s0.grid, gp, want_roi=True)
     assert g.child == o.child and tuple(g.roi) == tuple(o.roi)
