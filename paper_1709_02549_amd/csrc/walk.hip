@@ -7,6 +7,8 @@
 //     k_grid64      g^d lattice of every active scan's box, FP64      -> ws
 //     k_pl_level    one wavefront per scan: parent / child statistics by
 //                   wavefront reductions, W/B test, selection          -> result, state
+//   or, for lattices of at most 256 points and batches up to 1024 scans, every
+//   level in one launch of k_pl_fused (walk_grid.hip), one workgroup per scan
 //   paper walk:
 //     k_grid64      decimated image of the whole grid                  -> ws
 //     k_walk_paper  one wavefront per scan runs every level on those samples
@@ -21,6 +23,7 @@
 
 #include "uwb_internal.h"
 #include "walk_internal.h"
+#include "walk_level.h"
 
 namespace uwb {
 namespace {
@@ -49,66 +52,6 @@ __device__ void block_max(double (&v)[N], double *red) {
     }
 }
 
-// ----------------------------------------------------------------------------
-// sample sets: a lattice of points with values, and membership in boxes
-// ----------------------------------------------------------------------------
-struct Lattice {
-    int x0[3];      // finest index of lattice point k = 0 along each axis
-    int step;       // D
-    int cnt[3];     // points per axis
-    __device__ int count() const { return cnt[0] * cnt[1] * cnt[2]; }
-    __device__ void coord(int p, int &x, int &y, int &z) const {
-        const int kx = p % cnt[0], ky = (p / cnt[0]) % cnt[1], kz = p / (cnt[0] * cnt[1]);
-        x = x0[0] + step * kx;
-        y = x0[1] + step * ky;
-        z = x0[2] + step * kz;
-    }
-};
-
-__device__ __forceinline__ bool in_box(const int *b, int x, int y, int z) {
-    return x >= b[0] && x < b[1] && y >= b[2] && y < b[3] && z >= b[4] && z < b[5];
-}
-
-// child c of box b, split at lo + floor(side/2) along the active axes (Morton bits)
-__device__ __forceinline__ void split_box(const int *b, int c, int nact, int *out) {
-    for (int i = 0; i < 6; ++i) out[i] = b[i];
-    for (int d = 0; d < nact; ++d) {
-        const int lo = b[2 * d], hi = b[2 * d + 1];
-        const int mid = lo + (hi - lo) / 2;
-        if ((c >> d) & 1) out[2 * d] = mid;
-        else out[2 * d + 1] = mid;
-    }
-}
-
-// widen each active side by floor(frac * side) on both ends, clipped to the grid
-__device__ __forceinline__ void expand_box(const int *b, double frac, int nact, const int *dims, int *out) {
-    for (int i = 0; i < 6; ++i) out[i] = b[i];
-    for (int d = 0; d < nact; ++d) {
-        const int lo = b[2 * d], hi = b[2 * d + 1];
-        const int e = (int)floor(frac * (double)(hi - lo));
-        out[2 * d] = max(0, lo - e);
-        out[2 * d + 1] = min(dims[d], hi + e);
-    }
-}
-
-// Decision metric of Section III on one child set (stats of raw and normalised values).
-__device__ double metric_value(int metric, double n, double mean, double m2, double mx, double nmean, double nvar,
-                               double pnvar) {
-    switch (metric) {
-        case UWB_MEAN: return mean;
-        case UWB_VAR: return m2 / n;
-        case UWB_MAX: return mx;
-        case UWB_MAX_OVER_MEAN: return mean != 0.0 ? mx / mean : 0.0;
-        case UWB_EQ5:
-        case UWB_EQ5_CLAMPED: {
-            double a = nvar > 0.0 ? (nvar - pnvar) / nvar : 0.0;
-            if (metric == UWB_EQ5_CLAMPED) a = fmin(fmax(a, 0.0), 1.0);
-            return (1.0 - a) * nmean + a * nvar;
-        }
-    }
-    return 0.0;
-}
-
 // FP64 energies of every point of lattice L into lv (LDS), trace spans staged in LDS.
 __device__ void eval_lattice(const WalkArgs &a, const ScanConst &sc, const Lattice &L, double *lv, Stage &st,
                              int *tmp) {
@@ -135,121 +78,6 @@ __device__ void eval_lattice(const WalkArgs &a, const ScanConst &sc, const Latti
         if (ok && tid % G == 0) lv[p] = e;
     }
     __syncthreads();
-}
-
-struct LevelStats {
-    double pn, pmean, pm2;
-    double count[8];
-};
-
-// The same statistics for one scan on one wavefront (no workgroup barriers): for
-// the per-level walk, whose every level's lattice lies inside its box, and for the
-// paper walk (paper = true), whose samples are the decimated lattice points inside
-// the current box.  Passes 2 and 3 run only when the metric or the W/B stop needs
-// them.  Every lane returns the result.
-template <int NACT>
-__device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, const double *src, const int *box,
-                                       int side, bool paper, int cbox[8][6], double sc8[8]) {
-    constexpr int NCH = 1 << NACT;
-    const int lane = threadIdx.x & 63;
-    const int P = L.count();
-    int sbx[NCH][6];
-    const int half = side / 2;
-    // the per-level walk scores each child on its box widened by the level frame; the
-    // paper walk on the child's own samples
-    const int efr = paper ? 0 : (int)floor(a.frame_level * (double)half);
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        split_box(box, c, NACT, cbox[c]);
-        for (int i = 0; i < 6; ++i) sbx[c][i] = cbox[c][i];
-        for (int d = 0; d < NACT; ++d) {
-            sbx[c][2 * d] = max(box[2 * d], cbox[c][2 * d] - efr);
-            sbx[c][2 * d + 1] = min(box[2 * d + 1], cbox[c][2 * d + 1] + efr);
-        }
-    }
-    const bool need2 = a.term == UWB_TERM_WB || a.metric == UWB_VAR || a.metric == UWB_EQ5 ||
-                       a.metric == UWB_EQ5_CLAMPED;
-    const bool need3 = a.metric == UWB_EQ5 || a.metric == UWB_EQ5_CLAMPED;
-    // pass 1: counts, sums, maxima
-    double pn = 0.0, psum = 0.0, pmax = -INFINITY;
-    double cn[NCH], csum[NCH], cmx[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) { cn[c] = 0.0; csum[c] = 0.0; cmx[c] = -INFINITY; }
-    for (int p = lane; p < P; p += 64) {
-        int x, y, z;
-        L.coord(p, x, y, z);
-        if (!in_box(box, x, y, z)) continue;
-        const double v = src[p];
-        pn += 1.0; psum += v; pmax = fmax(pmax, v);
-#pragma unroll
-        for (int c = 0; c < NCH; ++c)
-            if (in_box(sbx[c], x, y, z)) { cn[c] += 1.0; csum[c] += v; cmx[c] = fmax(cmx[c], v); }
-    }
-    pn = wave_sum(pn);
-    psum = wave_sum(psum);
-    pmax = wave_max(pmax);
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) { cn[c] = wave_sum(cn[c]); csum[c] = wave_sum(csum[c]); cmx[c] = wave_max(cmx[c]); }
-    const double pmean = psum / pn;
-    const double scale = pmax > 0.0 ? pmax : 1.0;    // Eq. (5) normalisation
-    double cmean[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) cmean[c] = csum[c] / cn[c];
-    // pass 2: raw squared deviations and normalised sums
-    double pm2 = 0.0, pnsum = 0.0, cm2[NCH], cnsum[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) { cm2[c] = 0.0; cnsum[c] = 0.0; }
-    if (need2) {
-        for (int p = lane; p < P; p += 64) {
-            int x, y, z;
-            L.coord(p, x, y, z);
-            if (!in_box(box, x, y, z)) continue;
-            const double v = src[p];
-            const double vn = pmax > 0.0 ? v / scale : v;
-            pm2 += (v - pmean) * (v - pmean);
-            pnsum += vn;
-#pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                if (in_box(sbx[c], x, y, z)) { cm2[c] += (v - cmean[c]) * (v - cmean[c]); cnsum[c] += vn; }
-        }
-        pm2 = wave_sum(pm2);
-        pnsum = wave_sum(pnsum);
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) { cm2[c] = wave_sum(cm2[c]); cnsum[c] = wave_sum(cnsum[c]); }
-    }
-    const double pnmean = pnsum / pn;
-    double cnmean[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) cnmean[c] = cnsum[c] / cn[c];
-    // pass 3: normalised squared deviations (Eq. 5 variances)
-    double pv = 0.0, cv[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) cv[c] = 0.0;
-    if (need3) {
-        for (int p = lane; p < P; p += 64) {
-            int x, y, z;
-            L.coord(p, x, y, z);
-            if (!in_box(box, x, y, z)) continue;
-            const double vn = pmax > 0.0 ? src[p] / scale : src[p];
-            pv += (vn - pnmean) * (vn - pnmean);
-#pragma unroll
-            for (int c = 0; c < NCH; ++c)
-                if (in_box(sbx[c], x, y, z)) cv[c] += (vn - cnmean[c]) * (vn - cnmean[c]);
-        }
-        pv = wave_sum(pv);
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) cv[c] = wave_sum(cv[c]);
-    }
-    LevelStats out;
-    out.pn = pn;
-    out.pmean = pmean;
-    out.pm2 = pm2;
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        out.count[c] = cn[c];
-        sc8[c] = metric_value(a.metric, cn[c], cmean[c], cm2[c], cmx[c], cnmean[c], cv[c] / cn[c], pv / pn);
-    }
-    return out;
 }
 
 // ----------------------------------------------------------------------------
@@ -360,65 +188,9 @@ __global__ void k_pl_init(const WalkArgs a, int n_scans) {
 
 template <int NACT>
 __global__ __launch_bounds__(kBlock) void k_pl_level(const WalkArgs a, int lev, int n_scans) {
-    constexpr int NCH = 1 << NACT;
     const int scan = blockIdx.x * kWaves + (threadIdx.x >> 6);   // one wavefront per scan
     if (scan >= n_scans) return;
-    PLState &S = a.state[scan];
-    if (!S.active) return;                     // uniform per wavefront; no workgroup barriers below
-    uwb_segment_result &R = a.out[scan];
-    int box[6];
-    for (int i = 0; i < 6; ++i) box[i] = R.box[lev][i];
-    const int side = a.g.dims[0] >> lev;
-    const int step = side / a.coarse;
-    Lattice L;
-    for (int d = 0; d < 3; ++d) {
-        L.x0[d] = d < NACT ? box[2 * d] + step / 2 : 0;
-        L.cnt[d] = d < NACT ? a.coarse : 1;
-    }
-    L.step = step;
-    const int P = L.count();
-    const double *src = a.lat64 + (int64_t)scan * a.lat_stride + (int64_t)lev * P;
-    int cbox[8][6];
-    double sc8[8];
-    const LevelStats ls = wave_level_stats<NACT>(a, L, src, box, side, false, cbox, sc8);
-    if ((threadIdx.x & 63) != 0) return;       // the rest is one lane's bookkeeping
-    PLState st = S;
-    st.nvox += P;
-    bool stop = false;
-    if (a.term == UWB_TERM_WB && lev >= 1) {
-        const double pooled = (st.prev_n * st.prev_mean + ls.pn * ls.pmean) / (st.prev_n + ls.pn);
-        const double W = st.prev_m2 + ls.pm2;
-        const double B = st.prev_n * (st.prev_mean - pooled) * (st.prev_mean - pooled) +
-                         ls.pn * (ls.pmean - pooled) * (ls.pmean - pooled);
-        R.wb[st.n_wb][0] = W;
-        R.wb[st.n_wb][1] = B;
-        ++st.n_wb;
-        if (lev >= 2 && (B <= st.prev_b || W >= st.prev_w)) { st.n_kept = lev - 1; stop = true; }
-        st.prev_w = W;
-        st.prev_b = B;
-    }
-    if (!stop) {
-        st.prev_n = ls.pn;
-        st.prev_mean = ls.pmean;
-        st.prev_m2 = ls.pm2;
-        if (lev == a.depth) {
-            st.n_kept = a.depth;
-            stop = true;
-        } else {
-            double best = -INFINITY;
-            for (int c = 0; c < NCH; ++c) best = fmax(best, sc8[c]);
-            const double thr = best - kTieRel * fabs(best);
-            int sel = 0;
-            for (int c = NCH - 1; c >= 0; --c)
-                if (sc8[c] >= thr) sel = c;
-            R.child[st.made] = sel;
-            for (int c = 0; c < 8; ++c) R.score[st.made][c] = c < NCH ? sc8[c] : 0.0;
-            ++st.made;
-            for (int i = 0; i < 6; ++i) R.box[lev + 1][i] = cbox[sel][i];
-        }
-    }
-    if (stop) st.active = 0;
-    S = st;
+    pl_level_step<NACT>(a, lev, scan);
 }
 
 __global__ void k_pl_finish(const WalkArgs a, int n_scans) {
@@ -775,6 +547,17 @@ void size_walk_lds(WalkArgs *a, int n_ant) {
     a->lds_lattice = (size_t)12 * a->stage_ant + 4 * (size_t)a->lattice_stage_cap;
 }
 
+// The per-level walk runs as one fused launch (one workgroup per scan, every level) when
+// a level's lattice is one workgroup's worth of points and the batch is small enough
+// that launch gaps, not occupancy, decide the time: measured on 512 x 512 scans, g = 16,
+// 28 % faster at 256 scans, 3 % at 1024, 8 % slower at 4096; a lattice of several groups
+// (g = 32) is slower fused at every batch size, its groups serialised in one workgroup.
+constexpr int kFuseMaxScans = 1024;
+static bool fuse_levels(const WalkArgs &a, int n_scans) {
+    const int64_t pts = (int64_t)a.coarse * a.coarse * (a.g.dims[2] > 1 ? a.coarse : 1);
+    return pts <= kBlock && n_scans <= kFuseMaxScans;
+}
+
 static Grid64Args grid_args(const WalkArgs &a, int mode) {
     Grid64Args g;
     g.ss = a.ss;
@@ -838,7 +621,15 @@ int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st) {
         const int levels = a.term == UWB_TERM_WB ? a.depth + 1 : a.depth;
         const int nact = a.g.dims[2] > 1 ? 3 : 2;
         const int cnt[3] = {a.coarse, a.coarse, nact == 3 ? a.coarse : 1};
-        for (int lev = 0; lev < levels; ++lev) {
+        const bool fused = fuse_levels(a, n_scans);
+        if (fused) {
+            Grid64Args g = grid_args(a, kGridBox);
+            g.state = a.state;
+            g.out64 = a.lat64;
+            g.out_stride = a.lat_stride;
+            if ((rc = launch_pl_fused(g, a, levels, n_scans, st))) return rc;
+        }
+        for (int lev = 0; !fused && lev < levels; ++lev) {
             Grid64Args g = grid_args(a, kGridBox);
             g.lev = lev;
             g.step = (a.g.dims[0] >> lev) / a.coarse;

@@ -25,6 +25,7 @@
 
 #include "image32.h"
 #include "walk_internal.h"
+#include "walk_level.h"
 
 namespace uwb {
 namespace {
@@ -51,7 +52,43 @@ struct Group {
 };
 
 template <int BF, int W, bool MS>
-__device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const Group &G, unsigned char *dsm);
+__device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const Group &G, unsigned char *dsm,
+                             int64_t out_offset);
+
+// Group t of a c0 x c1 x c2 lattice as lane tid sees it: a tile when the lattice is a whole
+// number of tiles (tiled), else the band of points t * 256 .. in lattice order.
+template <bool D3>
+__device__ __forceinline__ Group make_group(int c0, int c1, int c2, bool tiled, int64_t t, int tid) {
+    using TS = Tile64<D3>;
+    const int64_t n = (int64_t)c0 * c1 * c2;
+    Group G;
+    if (tiled) {
+        const int ntx = c0 / TS::X, nty = c1 / TS::Y;
+        G.lo[0] = (int)(t % ntx) * TS::X;
+        G.lo[1] = (int)((t / ntx) % nty) * TS::Y;
+        G.lo[2] = (int)(t / ((int64_t)ntx * nty)) * TS::Z;
+        G.hi[0] = G.lo[0] + TS::X - 1;
+        G.hi[1] = G.lo[1] + TS::Y - 1;
+        G.hi[2] = G.lo[2] + TS::Z - 1;
+        if (!D3) { G.k[0] = G.lo[0] + (tid & 15); G.k[1] = G.lo[1] + (tid >> 4); G.k[2] = 0; }
+        else { G.k[0] = G.lo[0] + (tid & 7); G.k[1] = G.lo[1] + ((tid >> 3) & 7); G.k[2] = G.lo[2] + (tid >> 6); }
+        G.valid = true;
+        G.p = ((int64_t)G.k[2] * c1 + G.k[1]) * c0 + G.k[0];
+    } else {
+        const int64_t p0 = t * kBlock, p1 = min(p0 + kBlock, n) - 1;
+        G.valid = p0 + tid <= p1;
+        G.p = min(p0 + tid, p1);
+        const int64_t s01 = (int64_t)c0 * c1;
+        G.k[0] = (int)(G.p % c0); G.k[1] = (int)((G.p / c0) % c1); G.k[2] = (int)(G.p / s01);
+        const int ax = (int)(p0 % c0), ay = (int)((p0 / c0) % c1), az = (int)(p0 / s01);
+        const int bx = (int)(p1 % c0), by = (int)((p1 / c0) % c1), bz = (int)(p1 / s01);
+        // a band within one row spans its own columns; across rows, whole rows; across slabs, whole slabs
+        G.lo[2] = az; G.hi[2] = bz;
+        G.lo[1] = az == bz ? ay : 0; G.hi[1] = az == bz ? by : c1 - 1;
+        G.lo[0] = (az == bz && ay == by) ? ax : 0; G.hi[0] = (az == bz && ay == by) ? bx : c0 - 1;
+    }
+    return G;
+}
 
 // MS: the scans' channels are the transmitter-receiver pairs of a multistatic array.
 // DAS with windows up to 13 samples fits five waves per SIMD without spilling: asked of
@@ -94,37 +131,49 @@ void k_grid64(const Grid64Args a) {
     const int64_t ngroups = (n + kBlock - 1) / kBlock;   // tiles or bands: the same count when tiled
     const int64_t t = blockIdx.x;   // the launch holds enough workgroups for the largest lattice
     if (t >= ngroups) return;       // uniform per workgroup
-    Group G;
-    if (tiled) {
-        const int ntx = c0 / TS::X, nty = c1 / TS::Y;
-        G.lo[0] = (int)(t % ntx) * TS::X;
-        G.lo[1] = (int)((t / ntx) % nty) * TS::Y;
-        G.lo[2] = (int)(t / ((int64_t)ntx * nty)) * TS::Z;
-        G.hi[0] = G.lo[0] + TS::X - 1;
-        G.hi[1] = G.lo[1] + TS::Y - 1;
-        G.hi[2] = G.lo[2] + TS::Z - 1;
-        if (!D3) { G.k[0] = G.lo[0] + (tid & 15); G.k[1] = G.lo[1] + (tid >> 4); G.k[2] = 0; }
-        else { G.k[0] = G.lo[0] + (tid & 7); G.k[1] = G.lo[1] + ((tid >> 3) & 7); G.k[2] = G.lo[2] + (tid >> 6); }
-        G.valid = true;
-        G.p = ((int64_t)G.k[2] * c1 + G.k[1]) * c0 + G.k[0];
-    } else {
-        const int64_t p0 = t * kBlock, p1 = min(p0 + kBlock, n) - 1;
-        G.valid = p0 + tid <= p1;
-        G.p = min(p0 + tid, p1);
-        const int64_t s01 = (int64_t)c0 * c1;
-        G.k[0] = (int)(G.p % c0); G.k[1] = (int)((G.p / c0) % c1); G.k[2] = (int)(G.p / s01);
-        const int ax = (int)(p0 % c0), ay = (int)((p0 / c0) % c1), az = (int)(p0 / s01);
-        const int bx = (int)(p1 % c0), by = (int)((p1 / c0) % c1), bz = (int)(p1 / s01);
-        // a band within one row spans its own columns; across rows, whole rows; across slabs, whole slabs
-        G.lo[2] = az; G.hi[2] = bz;
-        G.lo[1] = az == bz ? ay : 0; G.hi[1] = az == bz ? by : c1 - 1;
-        G.lo[0] = (az == bz && ay == by) ? ax : 0; G.hi[0] = (az == bz && ay == by) ? bx : c0 - 1;
+    const Group G = make_group<D3>(c0, c1, c2, tiled, t, tid);
+    grid64_group<BF, W, MS>(a, L, scan, G, dsm, a.out_offset);
+}
+
+// The per-level walk in one launch, one workgroup per scan: at every level the workgroup
+// images the coarse^d lattice of the scan's box group by group (as k_grid64 does), then
+// its first wavefront takes the level's statistics and decision; the barriers between
+// the phases publish the lattice values and the next box (global memory) to the whole
+// workgroup.  Values and decisions are those of the level-synchronous kernels.
+template <int BF, int W, bool D3, bool MS>
+__global__ __launch_bounds__(kBlock) void k_pl_fused(const Grid64Args a, const WalkArgs w, int levels) {
+    using TS = Tile64<D3>;
+    extern __shared__ __align__(16) unsigned char dsm[];
+    const int scan = blockIdx.x;
+    const int c0 = w.coarse, c1 = w.coarse, c2 = D3 ? w.coarse : 1;
+    const int64_t n = (int64_t)c0 * c1 * c2;
+    const bool tiled = c0 % TS::X == 0 && c1 % TS::Y == 0 && c2 % TS::Z == 0;
+    const int64_t ngroups = (n + kBlock - 1) / kBlock;
+    for (int lev = 0; lev < levels; ++lev) {
+        if (!w.state[scan].active) break;   // uniform: published by the barrier closing the previous level
+        const int *box = w.out[scan].box[lev];
+        const int step = (w.g.dims[0] >> lev) / w.coarse;
+        Lat L;
+        for (int d = 0; d < 3; ++d) {
+            const bool act = d < 2 || D3;
+            L.x0[d] = act ? box[2 * d] + step / 2 : 0;
+            L.cnt[d] = act ? w.coarse : 1;
+        }
+        L.step = step;
+        const int64_t off = (int64_t)lev * n;
+        if (n + off <= a.out_stride) {   // always, for a planned walk
+            for (int64_t t = 0; t < ngroups; ++t)
+                grid64_group<BF, W, MS>(a, L, scan, make_group<D3>(c0, c1, c2, tiled, t, threadIdx.x), dsm, off);
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) pl_level_step<D3 ? 3 : 2>(w, lev, scan);
+        __syncthreads();
     }
-    grid64_group<BF, W, MS>(a, L, scan, G, dsm);
 }
 
 template <int BF, int W, bool MS>
-__device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const Group &G, unsigned char *dsm) {
+__device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const Group &G, unsigned char *dsm,
+                             int64_t out_offset) {
     constexpr int H = (W - 1) / 2;
     const int tid = threadIdx.x;
     const ScanConst sc = scan_const(a.ss, scan);
@@ -243,7 +292,7 @@ __device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const 
     }
     if (chunk < 1) e = __builtin_nan("");   // a span longer than the staging space (rejected on the host)
     if (G.valid) {
-        a.out64[(int64_t)scan * a.out_stride + a.out_offset + G.p] = e;
+        a.out64[(int64_t)scan * a.out_stride + out_offset + G.p] = e;
         if (a.out32) a.out32[(int64_t)scan * a.out32_stride + G.p] = (float)e;
     }
 }
@@ -260,27 +309,36 @@ int lds_budget(const void *kern, std::atomic<int> &cache) {
     return b;
 }
 
+// w: null for k_grid64 (grid from the caller), else the walk of the fused per-level kernel
+// (one workgroup per scan, levels levels).
 template <int BF, int W, bool D3, bool MS>
-int launch_k(dim3 grid, Grid64Args a, int rs_max, hipStream_t st) {
-    static std::atomic<int> budget;
-    const int lim = lds_budget(reinterpret_cast<const void *>(&k_grid64<BF, W, D3, MS>), budget);
+int launch_k(dim3 grid, Grid64Args a, int rs_max, const WalkArgs *w, int levels, hipStream_t st) {
+    static std::atomic<int> budget, budget_fused;
+    const void *kern = w ? reinterpret_cast<const void *>(&k_pl_fused<BF, W, D3, MS>)
+                         : reinterpret_cast<const void *>(&k_grid64<BF, W, D3, MS>);
+    const int lim = lds_budget(kern, w ? budget_fused : budget);
     if (kTabBytes + 4 * rs_max > lim) return UWB_EUNSUPPORTED;   // not even one channel's span fits
     a.lds_bytes = (int)std::min<int64_t>((int64_t)(kTabBytes + 4 * rs_max) * std::min(a.ss.n_ant, kBlock), lim);
-    hipLaunchKernelGGL((k_grid64<BF, W, D3, MS>), grid, dim3(kBlock), a.lds_bytes, st, a);
+    if (w) hipLaunchKernelGGL((k_pl_fused<BF, W, D3, MS>), grid, dim3(kBlock), a.lds_bytes, st, a, *w, levels);
+    else hipLaunchKernelGGL((k_grid64<BF, W, D3, MS>), grid, dim3(kBlock), a.lds_bytes, st, a);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }
 
 // rs_max: staged samples per channel of the widest group of the launch.
 template <int BF, int W>
-int launch_w(bool d3, dim3 grid, const Grid64Args &a, int rs_max, hipStream_t st) {
-    if (a.ss.ms) return d3 ? launch_k<BF, W, true, true>(grid, a, rs_max, st) : launch_k<BF, W, false, true>(grid, a, rs_max, st);
-    return d3 ? launch_k<BF, W, true, false>(grid, a, rs_max, st) : launch_k<BF, W, false, false>(grid, a, rs_max, st);
+int launch_w(bool d3, dim3 grid, const Grid64Args &a, int rs_max, const WalkArgs *w, int levels, hipStream_t st) {
+    if (a.ss.ms)
+        return d3 ? launch_k<BF, W, true, true>(grid, a, rs_max, w, levels, st)
+                  : launch_k<BF, W, false, true>(grid, a, rs_max, w, levels, st);
+    return d3 ? launch_k<BF, W, true, false>(grid, a, rs_max, w, levels, st)
+              : launch_k<BF, W, false, false>(grid, a, rs_max, w, levels, st);
 }
 
 template <int BF>
-int launch_bf(int window, bool d3, dim3 grid, const Grid64Args &a, int rs_max, hipStream_t st) {
+int launch_bf(int window, bool d3, dim3 grid, const Grid64Args &a, int rs_max, const WalkArgs *w, int levels,
+              hipStream_t st) {
     switch (window) {
-#define UWB_W(w) case w: return launch_w<BF, w>(d3, grid, a, rs_max, st);
+#define UWB_W(w_) case w_: return launch_w<BF, w_>(d3, grid, a, rs_max, w, levels, st);
         UWB_WINDOWS(UWB_W)
 #undef UWB_W
     }
@@ -327,8 +385,25 @@ int launch_grid64(Grid64Args a, const int *max_cnt, int max_step, int n_scans, h
                                       (double)ext[1] * max_step * a.g.pitch[1],
                                       (double)ext[2] * max_step * a.g.pitch[2], a.window, a.ss.n_samp);
     const dim3 grid((unsigned)wgs, (unsigned)n_scans);
-    return a.bf == UWB_DMAS ? launch_bf<UWB_DMAS>(a.window, d3, grid, a, rs_max, st)
-                            : launch_bf<UWB_DAS>(a.window, d3, grid, a, rs_max, st);
+    return a.bf == UWB_DMAS ? launch_bf<UWB_DMAS>(a.window, d3, grid, a, rs_max, nullptr, 0, st)
+                            : launch_bf<UWB_DAS>(a.window, d3, grid, a, rs_max, nullptr, 0, st);
+}
+
+// The per-level walk's levels in one launch (a: the kGridBox arguments of its lattices).
+int launch_pl_fused(Grid64Args a, const WalkArgs &w, int levels, int n_scans, hipStream_t st) {
+    if (n_scans < 1 || levels < 1) return UWB_OK;
+    const bool d3 = a.g.dims[2] > 1;
+    const int cnt[3] = {w.coarse, w.coarse, d3 ? w.coarse : 1};
+    // LDS: sized for level 0, whose groups span the widest boxes
+    const int step0 = a.g.dims[0] / w.coarse;
+    int64_t ext[3];
+    group_extent(cnt, d3, ext);
+    const double s_max = 2.0 / (a.ss.v * a.ss.dt);
+    const int rs_max = staged_samples(s_max, (double)ext[0] * step0 * a.g.pitch[0], (double)ext[1] * step0 * a.g.pitch[1],
+                                      (double)ext[2] * step0 * a.g.pitch[2], a.window, a.ss.n_samp);
+    const dim3 grid((unsigned)n_scans);
+    return a.bf == UWB_DMAS ? launch_bf<UWB_DMAS>(a.window, d3, grid, a, rs_max, &w, levels, st)
+                            : launch_bf<UWB_DAS>(a.window, d3, grid, a, rs_max, &w, levels, st);
 }
 
 }  // namespace uwb

@@ -61,6 +61,8 @@ struct Grid64Args {
     int lds_bytes;                     // filled by launch_grid64
 };
 int launch_grid64(Grid64Args a, const int *max_cnt, int max_step, int n_scans, hipStream_t st);
+// Every level of the per-level walk in one launch, one workgroup per scan (walk_grid.hip).
+int launch_pl_fused(Grid64Args a, const WalkArgs &w, int levels, int n_scans, hipStream_t st);
 
 // Points the workspace pointers of a planned walk into ws (size from plan_walk).
 void assign_walk_ws(WalkArgs *a, void *ws, int n_scans);

@@ -152,6 +152,26 @@ def test_flat_scan_ties_everywhere(walk, kw, bf):
     assert g.peak == 0.0 and not g.roi_image.any()
 
 
+@pytest.mark.parametrize("bf,metric,term", [(0, "max", "fixed"), (1, "eq5", "wb")])
+def test_walk_batch_size_invariance(bf, metric, term):
+    """A per-level walk of small lattices runs all its levels in one launch for batches up to 1024 scans and
+    level by level beyond: 8 scans and 1100 copies of them must give the same results, bit for bit."""
+    u = uwb()
+    scans = [synth.c1_scan(k) for k in range(8)]
+    _, gp = _params(beamformer=bf, coarse=8, metric=metric, term=term, frame_level=0.25, frame_final=0.25)
+    small = u.segment_refine_batch(u.DeviceBatch.from_host(scans), scans[0].grid, gp, want_roi=True)
+    big = u.segment_refine_batch(u.DeviceBatch.from_host([scans[k % 8] for k in range(1100)]), scans[0].grid, gp,
+                                 want_roi=True)
+    for k in (0, 1, 7, 8, 555, 1099):
+        a, b = small[k % 8], big[k]
+        assert a.child == b.child and a.n_levels == b.n_levels and a.term_level == b.term_level
+        assert [tuple(x) for x in a.boxes] == [tuple(x) for x in b.boxes] and tuple(a.roi) == tuple(b.roi)
+        assert a.argmax == b.argmax and a.peak == b.peak
+        assert all(np.array_equal(x, y) for x, y in zip(a.scores, b.scores))
+        assert all(np.array_equal(x, y) for x, y in zip(a.wb, b.wb)) and len(a.wb) == len(b.wb)
+        assert np.array_equal(a.roi_image, b.roi_image)
+
+
 def test_walk_deterministic():
     s = synth.c2_scan(2)
     u = uwb()
