@@ -6,13 +6,15 @@
 //   A  per 4096-voxel chunk: FP32 maximum                         -> cmax32[c]
 //   B  one workgroup: thr32 = max32 - kCandRel |max32|
 //   C  per chunk: every voxel with I32 >= thr32 is re-evaluated in FP64 by a whole
-//      wave (antennas split over the 64 lanes); chunk maximum and a short list
-//      of (index, value)                                          -> cmax64[c], list
+//      wave (antennas split over the 64 lanes, the chunk's four waves taking the
+//      candidates in turn); chunk maximum and a short list of (index, value)
+//                                                                 -> cmax64[c], list
 //   D  one workgroup: thr64 = max64 - 1e-12 |max64|
 //   E  per chunk: lowest index among candidates with FP64 value >= thr64 (from the
 //      list, or re-evaluated when the chunk had more candidates than the list holds)
 //   F  one workgroup: lowest index over chunks -> uwb_peak
 #include <climits>
+#include <cstdint>
 #include <cmath>
 
 #include "uwb_internal.h"
@@ -71,14 +73,26 @@ __device__ __forceinline__ float block_maxf(float x, float *red) {
     return r;
 }
 
+// 16-byte loads when every scan's image starts 16-byte aligned (voxels per scan a
+// multiple of 4) and the chunk is whole: four float4 per lane, all issued before use.
 __global__ __launch_bounds__(kBlock) void k_chunk_max32(const Args a) {
     __shared__ float red[kBlock / 64];
     const int scan = blockIdx.y, c = blockIdx.x;
     const float *img = a.img + (int64_t)scan * a.nvox;
+    const int64_t c0 = (int64_t)c * kChunkVox;
     float m = -INFINITY;
-    for (int k = 0; k < kPerThread; ++k) {
-        const int64_t v = (int64_t)c * kChunkVox + k * kBlock + threadIdx.x;
-        if (v < a.nvox) m = fmaxf(m, img[v]);
+    if ((a.nvox & 3) == 0 && c0 + kChunkVox <= a.nvox && (reinterpret_cast<uintptr_t>(a.img) & 15) == 0) {
+        const float4 *v4 = reinterpret_cast<const float4 *>(img + c0);
+        float4 x[kPerThread / 4];
+#pragma unroll
+        for (int k = 0; k < kPerThread / 4; ++k) x[k] = v4[k * kBlock + threadIdx.x];
+#pragma unroll
+        for (int k = 0; k < kPerThread / 4; ++k) m = fmaxf(m, fmaxf(fmaxf(x[k].x, x[k].y), fmaxf(x[k].z, x[k].w)));
+    } else {
+        for (int k = 0; k < kPerThread; ++k) {
+            const int64_t v = c0 + k * kBlock + threadIdx.x;
+            if (v < a.nvox) m = fmaxf(m, img[v]);
+        }
     }
     m = block_maxf(m, red);
     if (threadIdx.x == 0) a.chunks[(int64_t)scan * a.nchunks + c].max32 = m;
@@ -96,37 +110,76 @@ __global__ __launch_bounds__(kBlock) void k_reduce32(const Args a) {
     }
 }
 
-// Stage C: FP64 evaluation of the chunk's candidates.
+constexpr int kEvalCap = 512;   // candidates of a chunk listed in LDS for stage C
+
+// Stage C: FP64 evaluation of the chunk's candidates.  They are listed in index order in
+// LDS and the four wavefronts evaluate them four at a time (each candidate on a whole
+// wavefront, so its value does not depend on which one takes it); a chunk with more
+// candidates than the list holds has every wavefront evaluate its own in turn.
 __global__ __launch_bounds__(kBlock) void k_chunk_eval64(const Args a) {
     __shared__ double wmax[kBlock / 64];
+    __shared__ int wcnt[kBlock / 64];
     __shared__ int lcount;
     __shared__ int64_t lidx[kList];
     __shared__ double lval[kList];
+    __shared__ int cidx[kEvalCap];
+    __shared__ double cval[kEvalCap];
     const int scan = blockIdx.y, c = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     ChunkRec &rec = a.chunks[(int64_t)scan * a.nchunks + c];
     const float thr = a.scans[scan].thr32;
+    const int64_t c0 = (int64_t)c * kChunkVox;
     if (threadIdx.x == 0) lcount = 0;
     __syncthreads();
     double best = -INFINITY;
-    if (rec.max32 >= thr) {
+    if (rec.max32 >= thr) {   // uniform over the workgroup
         const ScanConst sc = scan_const(a.ss, scan);
         const float *img = a.img + (int64_t)scan * a.nvox;
+        int count = 0;        // uniform
         for (int k = 0; k < kPerThread; ++k) {
-            const int64_t v = (int64_t)c * kChunkVox + k * kBlock + threadIdx.x;
-            const bool cand = v < a.nvox && img[v] >= thr;
-            unsigned long long mask = __ballot(cand);
-            while (mask) {
-                const int l = __builtin_ctzll(mask);
-                mask &= mask - 1;
-                const int64_t vv = (int64_t)c * kChunkVox + k * kBlock + wave * 64 + l;
+            const int off = k * kBlock + threadIdx.x;
+            const bool cand = c0 + off < a.nvox && img[c0 + off] >= thr;
+            const unsigned long long mask = __ballot(cand);
+            if (lane == 0) wcnt[wave] = __popcll(mask);
+            __syncthreads();
+            int slot = count + __popcll(mask & ((1ull << lane) - 1));
+            for (int w = 0; w < wave; ++w) slot += wcnt[w];
+            if (cand && slot < kEvalCap) cidx[slot] = off;
+            for (int w = 0; w < kBlock / 64; ++w) count += wcnt[w];
+            __syncthreads();   // wcnt read by every lane before the next round writes it
+        }
+        if (count <= kEvalCap) {
+            for (int i = wave; i < count; i += kBlock / 64) {   // uniform per wavefront
+                const int64_t vv = c0 + cidx[i];
                 double rx, ry, rz;
                 voxel_pos(a.g, vv, rx, ry, rz);
                 const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, lane, 64);
                 best = fmax(best, e);
-                if (lane == 0) {
-                    const int slot = atomicAdd(&lcount, 1);
-                    if (slot < kList) { lidx[slot] = vv; lval[slot] = e; }
+                if (lane == 0) cval[i] = e;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {   // the first kList candidates in index order
+                lcount = count;
+                for (int i = 0; i < count && i < kList; ++i) { lidx[i] = c0 + cidx[i]; lval[i] = cval[i]; }
+            }
+        } else {
+            for (int k = 0; k < kPerThread; ++k) {
+                const int64_t v = c0 + k * kBlock + threadIdx.x;
+                const bool cand = v < a.nvox && img[v] >= thr;
+                unsigned long long mask = __ballot(cand);
+                while (mask) {
+                    const int l = __builtin_ctzll(mask);
+                    mask &= mask - 1;
+                    const int64_t vv = c0 + k * kBlock + wave * 64 + l;
+                    double rx, ry, rz;
+                    voxel_pos(a.g, vv, rx, ry, rz);
+                    const double e =
+                        energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, lane, 64);
+                    best = fmax(best, e);
+                    if (lane == 0) {
+                        const int slot = atomicAdd(&lcount, 1);
+                        if (slot < kList) { lidx[slot] = vv; lval[slot] = e; }
+                    }
                 }
             }
         }
@@ -209,10 +262,11 @@ __global__ __launch_bounds__(kBlock) void k_chunk_select(const Args a) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_final(const Args a) {
-    __shared__ long long sb[kBlock];
-    __shared__ double sv[kBlock];
-    __shared__ int sn[kBlock];
+    __shared__ long long sb[kBlock / 64];
+    __shared__ double sv[kBlock / 64];
+    __shared__ int sn[kBlock / 64];
     const int scan = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     long long b = LLONG_MAX;
     double bv = 0.0;
     int n = 0;
@@ -224,15 +278,18 @@ __global__ __launch_bounds__(kBlock) void k_final(const Args a) {
             bv = r.best_val;
         }
     }
-    sb[threadIdx.x] = b;
-    sv[threadIdx.x] = bv;
-    sn[threadIdx.x] = n;
+    // lowest index over the workgroup, with its value (indices are distinct across chunks)
+    const long long wb = wave_min_ll(b);
+    const unsigned long long owner = __ballot(b == wb && wb != LLONG_MAX);
+    const double wv = owner ? __shfl(bv, __builtin_ctzll(owner), 64) : 0.0;
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+    if (lane == 0) { sb[wave] = wb; sv[wave] = wv; sn[wave] = n; }
     __syncthreads();
     if (threadIdx.x == 0) {
         long long best = LLONG_MAX;
         double val = 0.0;
         int cnt = 0;
-        for (int i = 0; i < kBlock; ++i) {
+        for (int i = 0; i < kBlock / 64; ++i) {
             cnt += sn[i];
             if (sb[i] < best) { best = sb[i]; val = sv[i]; }
         }

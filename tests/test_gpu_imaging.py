@@ -187,14 +187,17 @@ def test_batch_equals_single_and_deterministic(bf):
         assert peaks[k].index == oracle.argmax_grid(oracle.image_grid(s, bf))[0]
 
 
-def test_flat_image_argmax_is_lowest_index():
+@pytest.mark.parametrize("n", [16, 64])
+def test_flat_image_argmax_is_lowest_index(n):
     """All-equal energies (constant traces, every window inside the trace): every voxel is a candidate;
-    the FP64 decision keeps the lowest index among ties within the 1e-12 band."""
-    g = Grid((0.0, 0.0, 0.0), (1e-4, 1e-4, 1e-4), (64, 64, 1))
+    the FP64 decision keeps the lowest index among ties within the 1e-12 band.  256 candidates fit a chunk's
+    candidate list (evaluated by its four wavefronts, then re-evaluated for the tie band past the 8 the
+    chunk record keeps); 4096 overflow it (each wavefront evaluates its own)."""
+    g = Grid((0.0, 0.0, 0.0), (1e-4, 1e-4, 1e-4), (n, n, 1))
     ant = np.array([[-0.1, 0.0, 0.0]], np.float32)
     s = synth.Scan(ant, np.ones((1, 4096), np.float32), 2e-11, 0.0, 1e8, g)
     ds, img = _gpu_image(s, 0)
     p = uwb().argmax(ds, g, img, 0)
     want = oracle.argmax_grid(oracle.image_grid(s, 0))
     assert p.index == want[0] == 0
-    assert p.candidates == 64 * 64
+    assert p.candidates == n * n
