@@ -42,6 +42,25 @@ struct Lat {
     int x0[3], step, cnt[3];
 };
 
+// Square root of a squared distance (finite, >= 0): the hardware reciprocal square root
+// refined by one step of Goldschmidt's coupled iteration for sqrt(x) and 1/(2 sqrt(x)),
+// then two Newton corrections of the residual x - g^2 -- the steps of the compiler's
+// general double-precision expansion, whose result it equals for x >= 2^-767, without
+// that expansion's rescaling of tiny inputs and its zero and infinity cases (7 of its 18
+// instructions).  x is raised to 1e-300 first, so a point on an antenna is 1e-150 m from it.
+__device__ __forceinline__ double sqrt_dist(double x) {
+    x = fmax(x, 1e-300);
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+
 // One group of up to 256 points of the lattice L: lane point k (lattice indices,
 // valid or not), the group's bounding box lo..hi (lattice indices) and the
 // output offset of the lane's point.
@@ -254,18 +273,18 @@ __device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const 
                     const double dx = rx - tab[8 * jj + 0];
                     const double dy = ry - tab[8 * jj + 1];
                     const double dz = rz - tab[8 * jj + 2];
-                    dtx = sqrt(dx * dx + dy * dy + dz * dz);
+                    dtx = sqrt_dist(dx * dx + dy * dy + dz * dz);
                 }
                 rxi = rxi + 1 == sc.ms ? 0 : rxi + 1;
                 const double ux = rx - tab[8 * jj + 3];
                 const double uy = ry - tab[8 * jj + 4];
                 const double uz = rz - tab[8 * jj + 5];
-                tau = 0.5 * sc.s * (dtx + sqrt(ux * ux + uy * uy + uz * uz)) - sc.t0s;
+                tau = 0.5 * sc.s * (dtx + sqrt_dist(ux * ux + uy * uy + uz * uz)) - sc.t0s;
             } else {    // Eq. (1)
                 const double dx = rx - tab[8 * jj + 0];
                 const double dy = ry - tab[8 * jj + 1];
                 const double dz = rz - tab[8 * jj + 2];
-                tau = sc.s * sqrt(dx * dx + dy * dy + dz * dz) - sc.t0s;
+                tau = sc.s * sqrt_dist(dx * dx + dy * dy + dz * dz) - sc.t0s;
             }
             const double fl = floor(tau);
             const double f = tau - fl;
