@@ -44,8 +44,8 @@ PEAK_FP32 = 157.3e12
 # HBM bytes per launch of the DMAS kernel at the default batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a 256 MiB copy); valid only for the kernel
 # sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
-TRAFFIC = {"source_hash": "cc3a337e564f70d8", "batch": 256, "bytes": 311048047,
-           "valu_per_va": 60.2}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of the DMAS kernel
+TRAFFIC = {"source_hash": "61df8e190e098481", "batch": 256, "bytes": 311049699,
+           "valu_per_va": 58.0}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of the DMAS kernel
 LDS_PEAK = 128 * 256 * 2.4e9        # B/s: 128 B/clk/CU
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2   # wave64 FP32 VALU instructions/s (two cycles each)
 
