@@ -25,6 +25,40 @@ __host__ __device__ inline int staged_samples(double s, double ex, double ey, do
 }
 void tile_shape(bool d3, int vpl, int *tx, int *ty, int *tz);
 
+constexpr int kStageBatch = 8;   // rows of 64 samples a wavefront loads before writing them
+
+// Copies the staged span [first(j), first(j) + rs) of channels j = 0 .. nch-1 (trace j at
+// tr + j * T) to stage + j * rs, zero outside [0, T).  The workgroup's wavefronts take the
+// channels in turn, a row of 64 samples per load; each wavefront issues kStageBatch rows'
+// loads before their LDS writes, so that many loads are in flight instead of one.
+template <typename First>
+__device__ __forceinline__ void stage_spans(float *stage, int rs, int nch, const float *tr, int T, First first) {
+    constexpr int NW = kBlock / 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nrow = (rs + 63) >> 6;
+    const int total = (nch > wave ? (nch - wave + NW - 1) / NW : 0) * nrow;   // this wavefront's rows
+    int q = 0, row = 0;   // the batch's first row: channel wave + NW q, samples 64 row ..
+    for (int r0 = 0; r0 < total; r0 += kStageBatch) {
+        float v[kStageBatch];
+        int dst[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int jj = wave + NW * q, m = 64 * row + lane;
+            dst[u] = -1;
+            v[u] = 0.f;
+            if (r0 + u < total && m < rs) {
+                dst[u] = jj * rs + m;
+                const int gidx = first(jj) + m;
+                if (gidx >= 0 && gidx < T) v[u] = tr[(int64_t)jj * T + gidx];
+            }
+            if (++row == nrow) { row = 0; ++q; }
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u)
+            if (dst[u] >= 0) stage[dst[u]] = v[u];
+    }
+}
+
 // One tile of one scan.
 struct TileJob {
     const float *pos;     // [M][3]
@@ -189,16 +223,8 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
         }
         __syncthreads();
         // stage [lo, lo + rs) of every antenna of the chunk
-        const int wave = tid >> 6, lane = tid & 63;
-        for (int jj = wave; jj < nch; jj += kBlock / 64) {
-            const int ilo = jj * rs - H - __float_as_int(tab[TE * jj].w);
-            const float *tr = j.tr + (int64_t)(a0 + jj) * T;
-            float *dst = stage + jj * rs;
-            for (int m = lane; m < rs; m += 64) {
-                const int gidx = ilo + m;
-                dst[m] = (gidx >= 0 && gidx < T) ? tr[gidx] : 0.f;
-            }
-        }
+        stage_spans(stage, rs, nch, j.tr + (int64_t)a0 * T, T,
+                    [&](int jj) { return jj * rs - H - __float_as_int(tab[TE * jj].w); });
         __syncthreads();
 
         // bistatic: receiver of the chunk's first channel (channels run in order, so a

@@ -252,16 +252,7 @@ __device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const 
             tab[8 * tid + 6] = lo;
         }
         __syncthreads();
-        const int wave = tid >> 6, lane = tid & 63;
-        for (int jj = wave; jj < nch; jj += kBlock / 64) {
-            const int ilo = (int)tab[8 * jj + 6];
-            const float *tr = sc.tr + (int64_t)(a0 + jj) * T;
-            float *dst = stage + jj * rs;
-            for (int m = lane; m < rs; m += 64) {
-                const int gi = ilo + m;
-                dst[m] = (gi >= 0 && gi < T) ? tr[gi] : 0.f;
-            }
-        }
+        stage_spans(stage, rs, nch, sc.tr + (int64_t)a0 * T, T, [&](int jj) { return (int)tab[8 * jj + 6]; });
         __syncthreads();
         // bistatic: receiver of the chunk's first channel (channels run in order, so a
         // transmitter's distance carries over a chunk boundary)
