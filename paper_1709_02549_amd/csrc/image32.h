@@ -28,12 +28,11 @@ void tile_shape(bool d3, int vpl, int *tx, int *ty, int *tz);
 constexpr int kStageBatch = 8;   // rows of 64 samples a wavefront loads before writing them
 
 // Copies the staged span [first(j), first(j) + rs) of channels j = 0 .. nch-1 (trace j at
-// tr + j * T) to stage + j * rs, zero outside [0, T).  The workgroup's wavefronts take the
-// channels in turn, a row of 64 samples per load; each wavefront issues kStageBatch rows'
+// tr + j * T) to stage + j * rs, zero outside [0, T).  The workgroup's NW wavefronts take
+// the channels in turn, a row of 64 samples per load; each wavefront issues kStageBatch rows'
 // loads before their LDS writes, so that many loads are in flight instead of one.
-template <typename First>
+template <int NW = kBlock / 64, typename First>
 __device__ __forceinline__ void stage_spans(float *stage, int rs, int nch, const float *tr, int T, First first) {
-    constexpr int NW = kBlock / 64;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nrow = (rs + 63) >> 6;
     const int total = (nch > wave ? (nch - wave + NW - 1) / NW : 0) * nrow;   // this wavefront's rows

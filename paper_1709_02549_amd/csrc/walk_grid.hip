@@ -190,6 +190,25 @@ __global__ __launch_bounds__(kBlock) void k_pl_fused(const Grid64Args a, const W
     }
 }
 
+// Window taps K0 .. K1-1 of one channel at one point: the linearly interpolated samples
+// (window starting at p, fraction f) into the DAS sums S_k and the DMAS prefix sums P_k.
+// The lattice arithmetic is written as explicit fused operations, so that the kernels
+// that instantiate it (k_grid64, k_pl_fused) take the same roundings and give the same
+// values bit for bit, whatever the compiler would contract in each context.
+template <int BF, int W, int K0, int K1>
+__device__ __forceinline__ void taps64(const float *p, double f, double (&S)[W], double (&P)[BF == UWB_DMAS ? W : 1]) {
+    float y[K1 - K0 + 1];
+#pragma unroll
+    for (int k = K0; k <= K1; ++k) y[k - K0] = p[k];
+    const double g = 1.0 - f;
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+        const double s = fma(f, (double)y[k - K0 + 1], g * (double)y[k - K0]);
+        if constexpr (BF == UWB_DMAS) P[k] = fma(s, S[k], P[k]);
+        S[k] += s;
+    }
+}
+
 template <int BF, int W, bool MS>
 __device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const Group &G, unsigned char *dsm,
                              int64_t out_offset) {
@@ -200,9 +219,9 @@ __device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const 
     double *tab = reinterpret_cast<double *>(dsm);   // [chunk][8]
 
     // lane point -> finest indices -> position
-    const double rx = a.g.origin[0] + (L.x0[0] + L.step * G.k[0]) * a.g.pitch[0];
-    const double ry = a.g.origin[1] + (L.x0[1] + L.step * G.k[1]) * a.g.pitch[1];
-    const double rz = a.g.origin[2] + (L.x0[2] + L.step * G.k[2]) * a.g.pitch[2];
+    const double rx = fma((double)(L.x0[0] + L.step * G.k[0]), a.g.pitch[0], a.g.origin[0]);
+    const double ry = fma((double)(L.x0[1] + L.step * G.k[1]), a.g.pitch[1], a.g.origin[1]);
+    const double rz = fma((double)(L.x0[2] + L.step * G.k[2]), a.g.pitch[2], a.g.origin[2]);
 
     // the group's bounding box (metres); its staging stride and the channels per chunk follow from it
     double blo[3], bhi[3];
@@ -259,23 +278,24 @@ __device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const 
         int rxi = MS ? a0 % sc.ms : 0;
         for (int jj = 0; jj < nch; ++jj) {
             double tau;
+            // (explicit fused operations, as in taps64)
             if (MS) {   // Eq. (2): both legs; the transmitter's leg is shared by its receivers
                 if (rxi == 0) {   // a new transmitter (uniform over the workgroup)
                     const double dx = rx - tab[8 * jj + 0];
                     const double dy = ry - tab[8 * jj + 1];
                     const double dz = rz - tab[8 * jj + 2];
-                    dtx = sqrt_dist(dx * dx + dy * dy + dz * dz);
+                    dtx = sqrt_dist(fma(dz, dz, fma(dy, dy, dx * dx)));
                 }
                 rxi = rxi + 1 == sc.ms ? 0 : rxi + 1;
                 const double ux = rx - tab[8 * jj + 3];
                 const double uy = ry - tab[8 * jj + 4];
                 const double uz = rz - tab[8 * jj + 5];
-                tau = 0.5 * sc.s * (dtx + sqrt_dist(ux * ux + uy * uy + uz * uz)) - sc.t0s;
+                tau = fma(0.5 * sc.s, dtx + sqrt_dist(fma(uz, uz, fma(uy, uy, ux * ux))), -sc.t0s);
             } else {    // Eq. (1)
                 const double dx = rx - tab[8 * jj + 0];
                 const double dy = ry - tab[8 * jj + 1];
                 const double dz = rz - tab[8 * jj + 2];
-                tau = sc.s * sqrt_dist(dx * dx + dy * dy + dz * dz) - sc.t0s;
+                tau = fma(sc.s, sqrt_dist(fma(dz, dz, fma(dy, dy, dx * dx))), -sc.t0s);
             }
             const double fl = floor(tau);
             const double f = tau - fl;
@@ -283,22 +303,14 @@ __device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const 
             // guards non-finite inputs (every span fits by construction)
             const double off = fmin(fmax(fl - H - tab[8 * jj + 6], 0.0), (double)(rs - (W + 1)));
             const float *p = stage + jj * rs + (int)off;
-            float y[W + 1];
-#pragma unroll
-            for (int k = 0; k <= W; ++k) y[k] = p[k];
-#pragma unroll
-            for (int k = 0; k < W; ++k) {
-                const double s = (1.0 - f) * (double)y[k] + f * (double)y[k + 1];
-                if (BF == UWB_DMAS) P[k] += s * S[k];
-                S[k] += s;
-            }
+            taps64<BF, W, 0, W>(p, f, S, P);
         }
     }
     double e = 0.0;
 #pragma unroll
     for (int k = 0; k < W; ++k) {
         const double q = BF == UWB_DMAS ? P[k] : S[k];
-        e += q * q;
+        e = fma(q, q, e);
     }
     if (chunk < 1) e = __builtin_nan("");   // a span longer than the staging space (rejected on the host)
     if (G.valid) {
@@ -309,11 +321,11 @@ __device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const 
 
 // Staging budget per workgroup: the CU's LDS shared by as many workgroups as the
 // kernel's registers let run at once (queried once per instantiation), at most kGridLdsMax.
-int lds_budget(const void *kern, std::atomic<int> &cache) {
+int lds_budget(const void *kern, int block, std::atomic<int> &cache) {
     int b = cache.load(std::memory_order_relaxed);
     if (b > 0) return b;
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kBlock, 0) != hipSuccess || nb < 1) nb = 5;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, block, 0) != hipSuccess || nb < 1) nb = 5;
     b = std::min(kGridLdsMax, (kLdsPerCu / nb) & ~255);
     cache.store(b, std::memory_order_relaxed);
     return b;
@@ -326,7 +338,7 @@ int launch_k(dim3 grid, Grid64Args a, int rs_max, const WalkArgs *w, int levels,
     static std::atomic<int> budget, budget_fused;
     const void *kern = w ? reinterpret_cast<const void *>(&k_pl_fused<BF, W, D3, MS>)
                          : reinterpret_cast<const void *>(&k_grid64<BF, W, D3, MS>);
-    const int lim = lds_budget(kern, w ? budget_fused : budget);
+    const int lim = lds_budget(kern, kBlock, w ? budget_fused : budget);
     if (kTabBytes + 4 * rs_max > lim) return UWB_EUNSUPPORTED;   // not even one channel's span fits
     a.lds_bytes = (int)std::min<int64_t>((int64_t)(kTabBytes + 4 * rs_max) * std::min(a.ss.n_ant, kBlock), lim);
     if (w) hipLaunchKernelGGL((k_pl_fused<BF, W, D3, MS>), grid, dim3(kBlock), a.lds_bytes, st, a, *w, levels);
