@@ -41,11 +41,12 @@ def flops_per_va(bf: int, window: int) -> int:
 # MI355X vector FP32: 256 CU x 4 SIMD x 32 FP32 lanes per clock x 2 flop (FMA) x 2.4 GHz
 PEAK_FP32 = 157.3e12
 
-# HBM bytes per launch of the DMAS kernel at the default batch, from two rocprofv3 --pmc runs
+# HBM bytes per launch of the step's imaging kernel (DMAS writing the DAS image too) at the default
+# batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a 256 MiB copy); valid only for the kernel
 # sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
-TRAFFIC = {"source_hash": "61df8e190e098481", "batch": 256, "bytes": 311049699,
-           "valu_per_va": 58.0}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of the DMAS kernel
+TRAFFIC = {"source_hash": "0f51eae975962d3e", "batch": 256, "bytes": 579537544,
+           "valu_per_va": 58.5}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of that launch
 LDS_PEAK = 128 * 256 * 2.4e9        # B/s: 128 B/clk/CU
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2   # wave64 FP32 VALU instructions/s (two cycles each)
 
@@ -77,6 +78,8 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the batched-serving measurement")
     ap.add_argument("--ms-batch", type=int, default=512, help="multistatic scans (12-antenna ring, 200x200 grid)")
     ap.add_argument("--no-ms", action="store_true", help="skip the multistatic and no-tumour-check measurements")
+    ap.add_argument("--no-separate", action="store_true",
+                    help="skip timing the DAS and DMAS kernels as separate launches (profiling runs)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (HBM counter reference)")
     args = ap.parse_args()
@@ -120,19 +123,17 @@ def main():
         walk_bufs[bf] = (torch.empty(ctypes.sizeof(uwb.UwbSegmentResult) * B, dtype=torch.uint8, device=dev),
                          torch.empty(need, dtype=torch.uint8, device=dev))
 
-    ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in ("das", "dmas", "arg", "walk")}
+    ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in ("img", "arg", "walk")}
     times = {k: [] for k in ev}
 
     def step(record: bool):
         def mark(k, i):
             if record:
                 ev[k][i].record()
-        mark("das", 0)
-        uwb.image_batch(batch, grid, 0, W, img_das, bc=bc)
-        mark("das", 1)
-        mark("dmas", 0)
-        uwb.image_batch(batch, grid, 1, W, img_dmas, bc=bc)
-        mark("dmas", 1)
+        # both full-resolution images from one launch: the DMAS kernel's running sums are the DAS sums
+        mark("img", 0)
+        uwb.das_dmas_batch(batch, grid, W, img_das, img_dmas, bc=bc)
+        mark("img", 1)
         mark("arg", 0)
         uwb.argmax_batch_async(batch, grid, img_das, 0, W, pk_das, ws_argmax, bc=bc)
         uwb.argmax_batch_async(batch, grid, img_dmas, 1, W, pk_dmas, ws_argmax, bc=bc)
@@ -164,8 +165,26 @@ def main():
     value = 2 * va / (ms_step * 1e-3) / 1e9        # Gvoxel*antenna/s, DAS + DMAS, whole step
 
     med = {k: float(np.median(v)) for k, v in times.items()}
-    das_gvas = va / (med["das"] * 1e-3) / 1e9
-    dmas_gvas = va / (med["dmas"] * 1e-3) / 1e9
+
+    # the two beamformers as separate launches (after the timed steps), for their own rates
+    def launch_ms(fn, reps=7):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    sep = {}
+    if not args.no_separate:
+        sep["das"] = launch_ms(lambda: uwb.image_batch(batch, grid, 0, W, img_das, bc=bc))
+        sep["dmas"] = launch_ms(lambda: uwb.image_batch(batch, grid, 1, W, img_dmas, bc=bc))
+    dmas_ms = sep.get("dmas", med["img"])
 
     # the two walks of a step are launch-bound at this batch (about a dozen small kernels each): the
     # same calls replayed as one HIP graph (kernels only: no memsets, no host synchronisation)
@@ -196,10 +215,11 @@ def main():
     das_vs_dmas = float(np.mean([within1(a.index, b.index) for a, b in zip(full_das, full)]))
     hier_vox = float(np.mean([r.voxels_evaluated for r in res[1]]))
 
-    fl = flops_per_va(1, W) * va
-    achieved = fl / (med["dmas"] * 1e-3)
+    # the timed launch: DMAS plus the DAS energy of its running sums (2 W flops per voxel)
+    fpva = flops_per_va(1, W) + 2.0 * W / M
+    achieved = fpva * va / (med["img"] * 1e-3)
     counters_valid = TRAFFIC["source_hash"] == _kernel_source_hash()
-    va_rate = va / (med["dmas"] * 1e-3)            # DMAS voxel·antenna/s
+    va_rate = va / (med["img"] * 1e-3)             # voxel·antenna/s of the launch
     traffic = TRAFFIC["bytes"] if (TRAFFIC["source_hash"] == _kernel_source_hash() and B == TRAFFIC["batch"]) \
         else None
     out = {
@@ -216,27 +236,30 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "2D monostatic ring, 32 antennas x 2048 samples, 512x512 grid, window 11, "
-                               f"full-res DAS+DMAS + argmax + quadtree walks (g={args.coarse}, max metric)",
+                               f"full-res DAS+DMAS (one launch) + argmax + quadtree walks (g={args.coarse}, "
+                               "max metric)",
                    "batch_scans": B, "distinct_scans": len(distinct), "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "kernel": "k_image32 DMAS (W=11, 2D)",
+        "roofline": {"bound": "alu", "kernel": "k_image32 DMAS writing DAS too (W=11, 2D)",
                      "achieved": round(achieved / 1e12, 3), "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32, 4), "traffic": traffic,
-                     "flops_per_voxel_antenna": flops_per_va(1, W),
-                     "avg_launch_ms": round(med["dmas"], 5),
-                     "hbm_gbs": round(traffic / (med["dmas"] * 1e-3) / 1e9, 1) if traffic else None,
-                     "hbm_frac": round(traffic / (med["dmas"] * 1e-3) / 8e12, 4) if traffic else None,
+                     "flops_per_voxel_antenna": round(fpva, 2),
+                     "avg_launch_ms": round(med["img"], 5),
+                     "hbm_gbs": round(traffic / (med["img"] * 1e-3) / 1e9, 1) if traffic else None,
+                     "hbm_frac": round(traffic / (med["img"] * 1e-3) / 8e12, 4) if traffic else None,
                      # the gather's other on-chip bounds: 48 B of LDS reads per voxel·antenna against
                      # 128 B/clk/CU, and VALU issue (counted instructions, while the sources match)
                      "lds_frac": round(va_rate * 48 / LDS_PEAK, 4),
                      "valu_issue_frac": round(va_rate * TRAFFIC["valu_per_va"] / 64 / VALU_ISSUE_PEAK, 4)
                      if counters_valid else None},
         "components_ms": {k: round(v, 5) for k, v in med.items()},
-        "das_gvas": round(das_gvas, 2),
-        "dmas_gvas": round(dmas_gvas, 2),
+        "das_dmas_one_launch_gvas": round(2 * va / (med["img"] * 1e-3) / 1e9, 2),
+        "separate_launch_ms": {k: round(v, 5) for k, v in sep.items()},
+        "das_gvas": round(va / (sep["das"] * 1e-3) / 1e9, 2) if sep else None,
+        "dmas_gvas": round(va / (sep["dmas"] * 1e-3) / 1e9, 2) if sep else None,
         "hierarchical": {
             "walk_scans_per_s": round(2 * B / (med["walk"] * 1e-3), 1),
             "walk_scans_per_s_hip_graph": round(2 * B / (walk_graph_ms * 1e-3), 1),
-            "full_dmas_scans_per_s": round(B / ((med["dmas"] + med["arg"] / 2) * 1e-3), 1),
+            "full_dmas_scans_per_s": round(B / ((dmas_ms + med["arg"] / 2) * 1e-3), 1),
             "dmas_walk_within_1_voxel_of_full_dmas": loc[1],
             "das_walk_within_1_voxel_of_full_dmas": loc[0],
             "full_das_within_1_voxel_of_full_dmas": das_vs_dmas,

@@ -116,6 +116,23 @@ int uwb_dmas_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t wi
                    void *stream);
 
 /*
+ * Both images in one pass.  The DMAS sum is accumulated as sum_j s_j A_j with
+ * A_j = sum_{i<j} s_i (Section II-B); once every antenna is in, A is the DAS
+ * window sum of Eq. (3).  These calls write the DMAS image (img_dmas, as
+ * uwb_dmas) and the DAS image (img_das, I = sum_k A_k^2) of the same scans from
+ * one launch, at the cost of the DMAS image alone.  The DAS values are those of
+ * uwb_das up to FP32 rounding (the interpolated sample is formed once and then
+ * added, where uwb_das folds it into the sum directly); the DMAS values equal
+ * uwb_dmas's bit for bit.  img_das and img_dmas: device, the uwb_das layout
+ * ([n_scans][nz][ny][nx] for the batch forms), caller-owned, not overlapping
+ * (else UWB_EINVAL); other arguments and errors as uwb_das / uwb_das_batch.
+ */
+int uwb_das_dmas(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img_das, float *img_dmas,
+                 void *stream);
+int uwb_das_dmas_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img_das,
+                       float *img_dmas, void *stream);
+
+/*
  * Detection (Section II-A): the tumour is at the voxel of maximal energy.
  * The decision is taken in FP64 so it does not depend on FP32 rounding:
  * every voxel whose FP32 energy is within 1e-3 (relative) of the FP32 maximum
@@ -230,6 +247,9 @@ int uwb_das_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid,
                               void *stream);
 int uwb_dmas_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img,
                                void *stream);
+/* Both multistatic images in one pass (as uwb_das_dmas_batch, Eq. (2) delays). */
+int uwb_das_dmas_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window,
+                                   float *img_das, float *img_dmas, void *stream);
 int uwb_argmax_multistatic(const uwb_scan *scan, const uwb_grid *grid, int32_t window, int32_t beamformer,
                            const float *img, uwb_peak *out, void *workspace, size_t workspace_bytes, void *stream);
 int uwb_argmax_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window,

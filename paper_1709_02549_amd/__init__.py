@@ -18,7 +18,7 @@ from ._abi import (METRICS, TERMS, UWB_DAS, UWB_DMAS, UWB_MAX_LEVELS, WALKS, Uwb
                    UwbBatchItem, UwbError, UwbGenRecipe, UwbGrid, UwbPeak, UwbScan, UwbScanBatch, UwbSegmentResult,
                    UwbSegmentTree, check, lib)
 
-__all__ = ["BatchPlan", "CNN", "generate_disc_scans", "learned_refine_batch", "cnn_training_inputs", "DeviceScan", "DeviceBatch", "das", "dmas", "image", "das_batch", "dmas_batch", "image_batch",
+__all__ = ["BatchPlan", "CNN", "generate_disc_scans", "learned_refine_batch", "cnn_training_inputs", "DeviceScan", "DeviceBatch", "das", "dmas", "das_dmas", "image", "das_batch", "dmas_batch", "das_dmas_batch", "image_batch",
            "argmax", "argmax_batch", "segment_refine", "segment_refine_batch", "auto_decimation",
            "SegmentTree", "UwbError"]
 
@@ -107,6 +107,20 @@ def image(scan: DeviceScan, grid, beamformer: int, window: int = 11, out: torch.
     return out
 
 
+def das_dmas(scan: DeviceScan, grid, window: int = 11, out_das=None, out_dmas=None):
+    """DAS and DMAS images [nz, ny, nx] of one scan from one launch. Returns (das, dmas)."""
+    if out_das is None:
+        out_das = torch.empty(_img_shape(grid), dtype=torch.float32, device=scan.traces.device)
+    if out_dmas is None:
+        out_dmas = torch.empty(_img_shape(grid), dtype=torch.float32, device=scan.traces.device)
+    _need_cuda(out_das, "out_das")
+    _need_cuda(out_dmas, "out_dmas")
+    sc, gc = scan.c(), grid_c(grid)
+    check(lib().uwb_das_dmas(ctypes.byref(sc), ctypes.byref(gc), window, out_das.data_ptr(), out_dmas.data_ptr(),
+                             _stream(out_das.device)), "uwb_das_dmas")
+    return out_das, out_dmas
+
+
 def das(scan, grid, window=11, out=None):
     return image(scan, grid, UWB_DAS, window, out)
 
@@ -125,6 +139,22 @@ def image_batch(batch: DeviceBatch, grid, beamformer: int, window: int = 11, out
     bc, gc = (bc if bc is not None else batch.c()), grid_c(grid)
     check(fn(ctypes.byref(bc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)), "image_batch")
     return out
+
+
+def das_dmas_batch(batch: DeviceBatch, grid, window: int = 11, out_das=None, out_dmas=None, bc=None):
+    """DAS and DMAS images of a batch from one launch (the DMAS kernel's running sums are the DAS sums).
+    Returns (das, dmas), each [n_scans, nz, ny, nx] float32."""
+    shape = (batch.n_scans,) + _img_shape(grid)
+    if out_das is None:
+        out_das = torch.empty(shape, dtype=torch.float32, device=batch.traces.device)
+    if out_dmas is None:
+        out_dmas = torch.empty(shape, dtype=torch.float32, device=batch.traces.device)
+    _need_cuda(out_das, "out_das")
+    _need_cuda(out_dmas, "out_dmas")
+    bc, gc = (bc if bc is not None else batch.c()), grid_c(grid)
+    check(lib().uwb_das_dmas_batch(ctypes.byref(bc), ctypes.byref(gc), window, out_das.data_ptr(),
+                                   out_dmas.data_ptr(), _stream(out_das.device)), "das_dmas_batch")
+    return out_das, out_dmas
 
 
 def das_batch(batch, grid, window=11, out=None):
@@ -651,6 +681,23 @@ def image_multistatic(scan: DeviceScan, grid, beamformer: int, window: int = 11,
     sc, gc = _ms_scan_c(scan), grid_c(grid)
     check(fn(ctypes.byref(sc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)), "image_multistatic")
     return out
+
+
+def das_dmas_multistatic_batch(batch: DeviceBatch, grid, window: int = 11, out_das=None, out_dmas=None, bc=None):
+    """Both multistatic images from one launch. Returns (das, dmas)."""
+    shape = (batch.n_scans,) + _img_shape(grid)
+    if out_das is None:
+        out_das = torch.empty(shape, dtype=torch.float32, device=batch.traces.device)
+    if out_dmas is None:
+        out_dmas = torch.empty(shape, dtype=torch.float32, device=batch.traces.device)
+    _need_cuda(out_das, "out_das")
+    _need_cuda(out_dmas, "out_dmas")
+    bc = bc if bc is not None else _ms_batch_c(batch)
+    gc = grid_c(grid)
+    check(lib().uwb_das_dmas_multistatic_batch(ctypes.byref(bc), ctypes.byref(gc), window, out_das.data_ptr(),
+                                               out_dmas.data_ptr(), _stream(out_das.device)),
+          "das_dmas_multistatic_batch")
+    return out_das, out_dmas
 
 
 def image_multistatic_batch(batch: DeviceBatch, grid, beamformer: int, window: int = 11, out=None, bc=None):

@@ -107,6 +107,20 @@ static int image_common(int bf, const ScanSet &ss, int n, const uwb_grid *grid, 
     return launch_image32(bf, ss, n, g, window, img, (hipStream_t)stream);
 }
 
+// Both images from one DMAS launch; the two outputs must not overlap.
+static int image_both_common(const ScanSet &ss, int n, const uwb_grid *grid, int32_t window, float *img_das,
+                             float *img_dmas, void *stream) {
+    GridView g;
+    int st = check_grid(grid, &g);
+    if (st) return st;
+    if ((st = check_window(window))) return st;
+    if (!img_das || !img_dmas) return UWB_EINVAL;
+    const uintptr_t bytes = (uintptr_t)n * (uintptr_t)g.dims[0] * g.dims[1] * g.dims[2] * sizeof(float);
+    const uintptr_t a = (uintptr_t)img_das, b = (uintptr_t)img_dmas;
+    if (a < b + bytes && b < a + bytes) return UWB_EINVAL;
+    return launch_image32(UWB_DMAS, ss, n, g, window, img_dmas, (hipStream_t)stream, img_das);
+}
+
 static int argmax_common(const ScanSet &ss, int n, const uwb_grid *grid, int32_t window, int32_t bf,
                          const float *img, uwb_peak *out, void *ws, size_t ws_bytes, void *stream) {
     GridView g;
@@ -176,6 +190,27 @@ int uwb_dmas(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *
     ScanSet ss;
     int st = scan_set(scan, &ss);
     return st ? st : image_common(UWB_DMAS, ss, 1, grid, window, img, stream);
+}
+
+int uwb_das_dmas(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img_das, float *img_dmas,
+                 void *stream) {
+    ScanSet ss;
+    int st = scan_set(scan, &ss);
+    return st ? st : image_both_common(ss, 1, grid, window, img_das, img_dmas, stream);
+}
+
+int uwb_das_dmas_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img_das,
+                       float *img_dmas, void *stream) {
+    ScanSet ss;
+    int st = batch_set(scans, &ss);
+    return st ? st : image_both_common(ss, scans->n_scans, grid, window, img_das, img_dmas, stream);
+}
+
+int uwb_das_dmas_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window,
+                                   float *img_das, float *img_dmas, void *stream) {
+    ScanSet ss;
+    int st = batch_set_ms(scans, &ss);
+    return st ? st : image_both_common(ss, scans->n_scans, grid, window, img_das, img_dmas, stream);
 }
 
 int uwb_das_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img, void *stream) {

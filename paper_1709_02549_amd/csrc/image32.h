@@ -71,6 +71,7 @@ struct TileJob {
     int chunk;            // channels staged per pass
     int ms;               // multistatic: antennas per side (channel i*ms + j), 0: monostatic
     int64_t p0;           // band form: first voxel (linear, x fastest) of the band
+    float *img_das = nullptr;   // DMAS only, optional: the DAS image of the same voxels
 };
 
 // Tile geometry.  2D: 16 (x) by 16*VPL (y); lane (tx, ty) owns y = ty + 16 v.
@@ -311,17 +312,24 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
         }
     }
 
+    // the DMAS running sums acc_k = sum of s_k over every antenna are the DAS window sums
+    // (Eq. (3)): a DMAS tile writes the DAS image too when asked, at no extra reads
+    float *const das = BF == UWB_DMAS ? j.img_das : nullptr;
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
-        float en = 0.f;
+        float en = 0.f, ed = 0.f;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             const float q = (BF == UWB_DMAS) ? pre[v][k] : acc[v][k];
             en = fmaf(q, q, en);
+            if (BF == UWB_DMAS) ed = fmaf(acc[v][k], acc[v][k], ed);
         }
-        if (!fits) en = __builtin_nanf("");
-        if (live && vx < nx && vy[v] < ny && vz[v] < nz)
-            j.img[((int64_t)vz[v] * ny + vy[v]) * nx + vx] = en;
+        if (!fits) en = ed = __builtin_nanf("");
+        if (live && vx < nx && vy[v] < ny && vz[v] < nz) {
+            const int64_t o = ((int64_t)vz[v] * ny + vy[v]) * nx + vx;
+            j.img[o] = en;
+            if (das) das[o] = ed;
+        }
     }
 }
 

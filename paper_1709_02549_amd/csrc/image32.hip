@@ -17,6 +17,9 @@
 // fixed summation order: results are bitwise reproducible and independent of
 // the tile shape.
 //
+// A DMAS launch can also write the DAS image: the running sums A_k are the DAS
+// window sums, so it costs one more energy per voxel and no extra reads.
+//
 // The tile body is shared by two kernels: k_image32 maps blockIdx to (tile,
 // scan) for same-shaped batches; k_batch32 is a persistent kernel that pulls
 // (scan, tile) items of uneven scans from a work list (see batch.hip).
@@ -39,6 +42,7 @@ struct Args {
     ScanSet ss;
     GridView g;
     float *img;
+    float *img_das;         // DMAS launch, optional: the DAS images too (same layout)
     int64_t img_stride;     // elements between scans
     int tiles_x, tiles_y;   // tiles along x and y (z = rest)
     int rs;                 // staged samples per antenna (stride in LDS)
@@ -57,6 +61,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     j.pos = sc.pos;
     j.tr = sc.tr;
     j.img = a.img + (int64_t)scan * a.img_stride;
+    j.img_das = a.img_das ? a.img_das + (int64_t)scan * a.img_stride : nullptr;
     j.M = a.ss.n_ant;
     j.T = a.ss.n_samp;
     j.s = sc.s;
@@ -97,7 +102,8 @@ hipError_t launch_bf(int window, bool d3, dim3 grid, size_t lds, hipStream_t st,
 }  // namespace
 
 int launch_image32(int bf, const ScanSet &ss, int n_scans, const GridView &g, int window, float *img,
-                   hipStream_t stream) {
+                   hipStream_t stream, float *img_das) {
+    if (img_das && bf != UWB_DMAS) return UWB_EINVAL;
     const bool d3 = g.dims[2] > 1;
     int tx, ty, tz;
     tile_shape(d3, kImageVpl, &tx, &ty, &tz);
@@ -105,6 +111,7 @@ int launch_image32(int bf, const ScanSet &ss, int n_scans, const GridView &g, in
     a.ss = ss;
     a.g = g;
     a.img = img;
+    a.img_das = img_das;
     a.img_stride = (int64_t)g.dims[0] * g.dims[1] * g.dims[2];
     a.tiles_x = (g.dims[0] + tx - 1) / tx;
     a.tiles_y = (g.dims[1] + ty - 1) / ty;

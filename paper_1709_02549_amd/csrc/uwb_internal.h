@@ -291,8 +291,9 @@ __device__ __forceinline__ double energy64_dispatch(int bf, const ScanConst &sc,
 
 // Host-side launchers implemented in the .hip files.
 namespace uwb {
+// img_das (DMAS only, optional): the DAS images of the same scans, from the same launch.
 int launch_image32(int bf, const ScanSet &ss, int n_scans, const GridView &g, int window, float *img,
-                   hipStream_t stream);
+                   hipStream_t stream, float *img_das = nullptr);
 int launch_argmax(int bf, const ScanSet &ss, int n_scans, const GridView &g, int window, const float *img,
                   uwb_peak *out, void *ws, hipStream_t stream);
 size_t argmax_ws_bytes(const GridView &g, int n_scans);

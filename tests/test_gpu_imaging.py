@@ -201,3 +201,56 @@ def test_flat_image_argmax_is_lowest_index(n):
     want = oracle.argmax_grid(oracle.image_grid(s, 0))
     assert p.index == want[0] == 0
     assert p.candidates == n * n
+
+
+# ----------------------------------------------------------------------------------
+# both images from one launch
+# ----------------------------------------------------------------------------------
+
+def _ragged_scan(dims, seed):
+    rng = np.random.default_rng(seed)
+    n = np.array(dims)
+    pitch = 0.1 / max(n.max(), 8)
+    g = Grid(tuple(-0.5 * pitch * (n - 1)), (pitch, pitch * 1.25, pitch * 0.8), dims)
+    ant = synth.hemisphere_antennas(24) if dims[2] > 1 else synth.ring_antennas(12)
+    tum = rng.uniform(-0.02, 0.02, 3) * (1 if dims[2] > 1 else np.array([1, 1, 0]))
+    s = synth.point_scan(ant, g, tum[None, :], [1.0], 1024, synth.C0 / 3)
+    s.traces = (s.traces + 0.01 * rng.standard_normal(s.traces.shape)).astype(np.float32)
+    return s
+
+
+@pytest.mark.parametrize("case", ["c1-0", "c1-1", "ragged-2d", "ragged-3d"])
+def test_das_dmas_one_launch(case):
+    """The DMAS launch's running sums are the DAS sums: both images from one launch.  DMAS equals uwb_dmas bit
+    for bit; DAS meets the oracle's bar (and uwb_das's to FP32 rounding); ragged 2D and 3D grids."""
+    s = {"c1-0": lambda: synth.c1_scan(0), "c1-1": lambda: synth.c1_scan(1),
+         "ragged-2d": lambda: _ragged_scan((100, 76, 1), 5), "ragged-3d": lambda: _ragged_scan((19, 21, 11), 6)}[case]()
+    u = uwb()
+    ds = u.DeviceScan.from_host(s)
+    das, dmas = u.das_dmas(ds, s.grid)
+    torch.cuda.synchronize()
+    assert torch.equal(dmas, u.image(ds, s.grid, 1))
+    want = oracle.image_grid(s, 0)
+    _check_image(das.cpu().numpy(), want)
+    _check_image(dmas.cpu().numpy(), oracle.image_grid(s, 1))
+    ref = u.image(ds, s.grid, 0).cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(das.cpu().numpy() - ref)) <= 1e-4 * float(np.max(want))
+    assert u.argmax(ds, s.grid, das, 0).index == oracle.argmax_grid(want)[0]
+
+
+def test_das_dmas_batch_and_errors():
+    scans = [synth.c1_scan(k, n_grid=64) for k in range(4)]
+    u = uwb()
+    b = u.DeviceBatch.from_host(scans)
+    das, dmas = u.das_dmas_batch(b, scans[0].grid)
+    torch.cuda.synchronize()
+    assert torch.equal(dmas, u.image_batch(b, scans[0].grid, 1))
+    for k, s in enumerate(scans):
+        _check_image(das[k].cpu().numpy(), oracle.image_grid(s, 0))
+    # overlapping outputs are refused, nothing is launched
+    buf = torch.empty((2 * 4 + 1,) + das.shape[1:], dtype=torch.float32, device="cuda")
+    with pytest.raises(u.UwbError):
+        u.das_dmas_batch(b, scans[0].grid, out_das=buf[0:4], out_dmas=buf[3:7])
+    u.das_dmas_batch(b, scans[0].grid, out_das=buf[0:4], out_dmas=buf[4:8])   # adjacent is fine
+    torch.cuda.synchronize()
+    assert torch.equal(buf[4:8], dmas) and torch.equal(buf[0:4], das)

@@ -135,3 +135,15 @@ def test_argument_errors():
     bad = u.DeviceScan(ds.ant_pos, ds.traces[:100].contiguous(), ds.dt, ds.t0, ds.v)
     with pytest.raises(ValueError):
         u.image_multistatic(bad, s.grid, 0)
+
+
+def test_das_dmas_multistatic_one_launch():
+    """Both multistatic images from one launch: DMAS bit for bit as the DMAS call, DAS at the image bar."""
+    u = uwb()
+    scans = [synth.ms_scan(k, 2) for k in range(3)]
+    b = u.DeviceBatch.from_host(scans)
+    das, dmas = u.das_dmas_multistatic_batch(b, scans[0].grid)
+    torch.cuda.synchronize()
+    assert torch.equal(dmas, u.image_multistatic_batch(b, scans[0].grid, 1))
+    for i, s in enumerate(scans):
+        _check_image(das[i].cpu().numpy(), oracle.image_grid(s, 0))
