@@ -112,8 +112,11 @@ def main():
     pk_dmas = torch.empty_like(pk_das)
     trees = {bf: uwb.SegmentTree(beamformer=bf, coarse=args.coarse, metric="max", frame_final=0.25) for bf in (0, 1)}
     walk_out = {}
-    ws_argmax = torch.empty(int(uwb.lib().uwb_argmax_workspace_bytes(
-        __import__("ctypes").byref(uwb.grid_c(grid)), B)), dtype=torch.uint8, device=dev)
+    ws_argmax = {bf: torch.empty(int(uwb.lib().uwb_argmax_workspace_bytes(
+        __import__("ctypes").byref(uwb.grid_c(grid)), B)), dtype=torch.uint8, device=dev) for bf in (0, 1)}
+    # the DAS and DMAS detections, and the two walks, are independent and latency-bound: each pair runs
+    # on two streams (default priority), the DMAS one on `side`, forked from and joined to the main stream
+    side = torch.cuda.Stream(device=dev)
     ws_walk = {bf: uwb.Workspace() for bf in (0, 1)}
     walk_bufs = {}
     for bf in (0, 1):
@@ -134,14 +137,21 @@ def main():
         mark("img", 0)
         uwb.das_dmas_batch(batch, grid, W, img_das, img_dmas, bc=bc)
         mark("img", 1)
+        main = torch.cuda.current_stream(dev)
         mark("arg", 0)
-        uwb.argmax_batch_async(batch, grid, img_das, 0, W, pk_das, ws_argmax, bc=bc)
-        uwb.argmax_batch_async(batch, grid, img_dmas, 1, W, pk_dmas, ws_argmax, bc=bc)
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            uwb.argmax_batch_async(batch, grid, img_dmas, 1, W, pk_dmas, ws_argmax[1], bc=bc)
+        uwb.argmax_batch_async(batch, grid, img_das, 0, W, pk_das, ws_argmax[0], bc=bc)
+        main.wait_stream(side)
         mark("arg", 1)
         mark("walk", 0)
-        for bf in (0, 1):
+        side.wait_stream(main)
+        for bf in (1, 0):
             out, ws = walk_bufs[bf]
-            uwb.segment_refine_batch_async(batch, grid, trees[bf], W, out=out, workspace=ws, bc=bc)
+            with torch.cuda.stream(side if bf == 1 else main):
+                uwb.segment_refine_batch_async(batch, grid, trees[bf], W, out=out, workspace=ws, bc=bc)
+        main.wait_stream(side)
         mark("walk", 1)
 
     if args.copy_ref_mib > 0:
