@@ -99,6 +99,29 @@ def test_image_argument_errors(fn):
     assert f(ctypes.byref(_scan()), ctypes.byref(_grid(origin=(float("inf"), 0, 0))), 11, FAKE, None) == E
 
 
+def test_das_dmas_argument_errors():
+    """Both-images calls: a missing or overlapping output is refused before anything is launched (an 8 x 8
+    image is 256 bytes per scan)."""
+    a = _abi()
+    g = _grid()
+    E = a.UWB_EINVAL
+    p = 0x10000000
+    v = ctypes.c_void_p
+    f = a.lib().uwb_das_dmas
+    s = ctypes.byref(_scan())
+    assert f(s, ctypes.byref(g), 11, None, v(p), None) == E
+    assert f(s, ctypes.byref(g), 11, v(p), None, None) == E
+    assert f(s, ctypes.byref(g), 11, v(p), v(p), None) == E
+    assert f(s, ctypes.byref(g), 11, v(p), v(p + 252), None) == E
+    assert f(s, ctypes.byref(g), 11, v(p + 252), v(p), None) == E
+    assert f(s, ctypes.byref(g), 2, v(p), v(p + 256), None) == E
+    fb = a.lib().uwb_das_dmas_batch
+    bb = a.UwbScanBatch(n_scans=2, n_ant=4, n_samp=64, ant_pos=FAKE, traces=FAKE, params=FAKE, v_min=1e8,
+                        dt_min=2e-11)
+    assert fb(ctypes.byref(bb), ctypes.byref(g), 11, v(p), v(p + 256), None) == E   # 512 bytes each
+    assert fb(ctypes.byref(bb), ctypes.byref(g), 11, v(p), None, None) == E
+
+
 def test_batch_argument_errors():
     a = _abi()
     f = a.lib().uwb_das_batch
