@@ -28,7 +28,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP32 work per voxel*antenna with a W-sample window:
+# Algorithmic FP32 work per voxel*antenna with a W-sample window (counted from the operations the
+# method prescribes, not from the kernel's instruction mix):
 #   delay 11 flops (3 sub, 3 mul, 2 add, sqrt, scale, offset)
 #   per window offset: interpolation 3 flops; DAS +1 add; DMAS +3 (product, sum, prefix)
 FLOPS_DELAY = 11

@@ -157,7 +157,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
-                              "(python -c 'import __graft_entry__ as g; g.build()')")
+                              "(python -m paper_1709_02549_amd.build)")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in PROTOTYPES.items():
             if hasattr(L, name):
