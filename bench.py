@@ -201,9 +201,13 @@ def main():
     # same calls replayed as one HIP graph (kernels only: no memsets, no host synchronisation)
     wg = torch.cuda.CUDAGraph()
     with torch.cuda.graph(wg):
-        for bf in (0, 1):
+        cap = torch.cuda.current_stream(dev)       # the two walks forked onto two streams, as in the step
+        side.wait_stream(cap)
+        for bf in (1, 0):
             out, ws = walk_bufs[bf]
-            uwb.segment_refine_batch_async(batch, grid, trees[bf], W, out=out, workspace=ws, bc=bc)
+            with torch.cuda.stream(side if bf == 1 else cap):
+                uwb.segment_refine_batch_async(batch, grid, trees[bf], W, out=out, workspace=ws, bc=bc)
+        cap.wait_stream(side)
     wg.replay()
     torch.cuda.synchronize()
     g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
