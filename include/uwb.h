@@ -224,7 +224,9 @@ typedef struct {
     double peak;                            /* FP64 energy there */
     int64_t voxels_evaluated;               /* focal points beamformed in total */
     int32_t learned_mask;                   /* learned walk: bit l set if the CNN decided split l */
-    int32_t reserved;
+    int32_t guard_hits;                     /* ROI voxels whose FP32 energy came within 1e-3 of the
+                                               ROI's FP32 maximum and were re-evaluated in FP64 to
+                                               decide the detection (>= 1 when argmax >= 0) */
 } uwb_segment_result;
 
 /*
@@ -461,6 +463,25 @@ int uwb_generate_disc_scans(const uwb_gen_recipe *recipe, const float *ant_pos, 
 int uwb_auto_decimation(double min_tumour, double pitch);
 
 /* Static description of a status code (never NULL). */
+/*
+ * Machine probe: the LDS read bandwidth of the device, the on-chip resource the
+ * gather of the imaging kernels draws on (W + 1 staged samples per voxel-antenna,
+ * Eq. (3)).  Launches n_groups workgroups of 256 lanes, each streaming `iters`
+ * reads of `width` bytes (4, 8 or 16: ds_read_b32 / _b64 / _b128) per lane from a
+ * 32 KiB LDS array with conflict-free addresses, and times the launch with HIP
+ * events.  Synchronous: returns after the stream has drained.
+ *   iters       >= 8, a multiple of 8
+ *   n_groups    1 .. 65536 (use many per CU to fill the device)
+ *   bytes_per_s host out: LDS bytes read per second over the whole device
+ *   clock_hz    host out: the shader clock measured during the loop (median over
+ *               workgroups of the cycle counter against the constant 100 MHz counter)
+ * Allocates and frees a small device buffer (the values read are written out so
+ * that no read is dropped).  Errors: UWB_EINVAL for out-of-range arguments,
+ * UWB_ENOMEM, UWB_EHIP.
+ */
+int uwb_probe_lds_read(int32_t width, int32_t iters, int32_t n_groups, double *bytes_per_s, double *clock_hz,
+                       void *stream);
+
 const char *uwb_status_string(int status);
 
 /* Library version string, e.g. "uwb 0.1 gfx950". */

@@ -27,11 +27,24 @@ def _stream(device=None) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def _need_cuda(t: torch.Tensor, name: str, dtype=torch.float32):
+def _need_cuda(t: torch.Tensor, name: str, dtype=torch.float32, numel: int | None = None):
+    """t must be a contiguous CUDA tensor of dtype; with numel, it must hold at least that many elements (the
+    library takes raw pointers: a short buffer would be written or read past its end on the device)."""
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
     if t.dtype != dtype or not t.is_contiguous():
         raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, the call needs {numel}")
+
+
+def _need_bytes(t: torch.Tensor, name: str, nbytes: int):
+    """A byte buffer (records, workspace) of at least nbytes on the device."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous CUDA (HIP) tensor")
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise ValueError(f"{name} holds {have} bytes, the call needs {nbytes}")
 
 
 @dataclasses.dataclass
@@ -50,8 +63,10 @@ class DeviceScan:
                    float(s.dt), float(s.t0), float(s.v))
 
     def c(self) -> UwbScan:
-        _need_cuda(self.ant_pos, "ant_pos")
         _need_cuda(self.traces, "traces")
+        if self.traces.dim() != 2:
+            raise ValueError("traces must be [M, T]")
+        _need_cuda(self.ant_pos, "ant_pos", numel=3 * self.traces.shape[0])
         return UwbScan(self.traces.shape[0], self.traces.shape[1], self.ant_pos.data_ptr(), self.traces.data_ptr(),
                        self.dt, self.t0, self.v)
 
@@ -75,9 +90,15 @@ class DeviceBatch:
         return int(self.traces.shape[0])
 
     def c(self) -> UwbScanBatch:
-        _need_cuda(self.ant_pos, "ant_pos")
         _need_cuda(self.traces, "traces")
-        _need_cuda(self.params, "params", torch.float64)
+        if self.traces.dim() != 3:
+            raise ValueError("traces must be [B, M, T]")
+        b, m = int(self.traces.shape[0]), int(self.traces.shape[1])
+        if self.ant_pos.dim() != 3 or self.ant_pos.shape[2] != 3 or \
+                tuple(self.ant_pos.shape[:2]) not in ((b, m), (b, int(round(m ** 0.5)))):
+            raise ValueError("ant_pos must be [B, M, 3] (multistatic: [B, sqrt(M), 3])")
+        _need_cuda(self.ant_pos, "ant_pos")
+        _need_cuda(self.params, "params", torch.float64, numel=3 * b)
         p = self.params.detach().cpu().numpy()
         return UwbScanBatch(self.traces.shape[0], self.traces.shape[1], self.traces.shape[2],
                             self.ant_pos.data_ptr(), self.traces.data_ptr(), self.params.data_ptr(),
@@ -95,11 +116,16 @@ def _img_shape(g):
     return (nz, ny, nx)
 
 
+def _nvox(g) -> int:
+    nx, ny, nz = (int(x) for x in g.dims)
+    return nx * ny * nz
+
+
 def image(scan: DeviceScan, grid, beamformer: int, window: int = 11, out: torch.Tensor | None = None):
     """Full-resolution DAS (beamformer 0) or DMAS (1) image [nz, ny, nx] fp32."""
     if out is None:
         out = torch.empty(_img_shape(grid), dtype=torch.float32, device=scan.traces.device)
-    _need_cuda(out, "out")
+    _need_cuda(out, "out", numel=_nvox(grid))
     fn = lib().uwb_dmas if beamformer == UWB_DMAS else lib().uwb_das
     sc, gc = scan.c(), grid_c(grid)
     check(fn(ctypes.byref(sc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)),
@@ -113,8 +139,8 @@ def das_dmas(scan: DeviceScan, grid, window: int = 11, out_das=None, out_dmas=No
         out_das = torch.empty(_img_shape(grid), dtype=torch.float32, device=scan.traces.device)
     if out_dmas is None:
         out_dmas = torch.empty(_img_shape(grid), dtype=torch.float32, device=scan.traces.device)
-    _need_cuda(out_das, "out_das")
-    _need_cuda(out_dmas, "out_dmas")
+    _need_cuda(out_das, "out_das", numel=_nvox(grid))
+    _need_cuda(out_dmas, "out_dmas", numel=_nvox(grid))
     sc, gc = scan.c(), grid_c(grid)
     check(lib().uwb_das_dmas(ctypes.byref(sc), ctypes.byref(gc), window, out_das.data_ptr(), out_dmas.data_ptr(),
                              _stream(out_das.device)), "uwb_das_dmas")
@@ -134,7 +160,7 @@ def image_batch(batch: DeviceBatch, grid, beamformer: int, window: int = 11, out
     in a graph (building it reads the per-scan parameters back to the host)."""
     if out is None:
         out = torch.empty((batch.n_scans,) + _img_shape(grid), dtype=torch.float32, device=batch.traces.device)
-    _need_cuda(out, "out")
+    _need_cuda(out, "out", numel=batch.n_scans * _nvox(grid))
     fn = lib().uwb_dmas_batch if beamformer == UWB_DMAS else lib().uwb_das_batch
     bc, gc = (bc if bc is not None else batch.c()), grid_c(grid)
     check(fn(ctypes.byref(bc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)), "image_batch")
@@ -149,8 +175,8 @@ def das_dmas_batch(batch: DeviceBatch, grid, window: int = 11, out_das=None, out
         out_das = torch.empty(shape, dtype=torch.float32, device=batch.traces.device)
     if out_dmas is None:
         out_dmas = torch.empty(shape, dtype=torch.float32, device=batch.traces.device)
-    _need_cuda(out_das, "out_das")
-    _need_cuda(out_dmas, "out_dmas")
+    _need_cuda(out_das, "out_das", numel=batch.n_scans * _nvox(grid))
+    _need_cuda(out_dmas, "out_dmas", numel=batch.n_scans * _nvox(grid))
     bc, gc = (bc if bc is not None else batch.c()), grid_c(grid)
     check(lib().uwb_das_dmas_batch(ctypes.byref(bc), ctypes.byref(gc), window, out_das.data_ptr(),
                                    out_dmas.data_ptr(), _stream(out_das.device)), "das_dmas_batch")
@@ -206,7 +232,9 @@ def argmax_async(scan: DeviceScan, grid, img: torch.Tensor, beamformer: int, win
     ws = workspace if workspace is not None else _ws.get(need, img.device)
     if out is None:
         out = torch.empty(ctypes.sizeof(UwbPeak), dtype=torch.uint8, device=img.device)
-    _need_cuda(img, "img")
+    _need_cuda(img, "img", numel=_nvox(grid))
+    _need_bytes(out, "out", ctypes.sizeof(UwbPeak))
+    _need_bytes(ws, "workspace", need)
     check(lib().uwb_argmax(ctypes.byref(sc), ctypes.byref(gc), window, beamformer, img.data_ptr(), out.data_ptr(),
                            ws.data_ptr(), ws.numel(), _stream(img.device)), "uwb_argmax")
     return out
@@ -224,7 +252,9 @@ def argmax_batch_async(batch: DeviceBatch, grid, img: torch.Tensor, beamformer: 
     ws = workspace if workspace is not None else _ws.get(need, img.device)
     if out is None:
         out = torch.empty(ctypes.sizeof(UwbPeak) * batch.n_scans, dtype=torch.uint8, device=img.device)
-    _need_cuda(img, "img")
+    _need_cuda(img, "img", numel=batch.n_scans * _nvox(grid))
+    _need_bytes(out, "out", ctypes.sizeof(UwbPeak) * batch.n_scans)
+    _need_bytes(ws, "workspace", need)
     check(lib().uwb_argmax_batch(ctypes.byref(bc), ctypes.byref(gc), window, beamformer, img.data_ptr(),
                                  out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(img.device)), "uwb_argmax_batch")
     return out
@@ -232,6 +262,14 @@ def argmax_batch_async(batch: DeviceBatch, grid, img: torch.Tensor, beamformer: 
 
 def argmax_batch(batch, grid, img, beamformer, window=11):
     return _peaks(argmax_batch_async(batch, grid, img, beamformer, window), batch.n_scans)
+
+
+def probe_lds_read(width: int = 16, iters: int = 4096, n_groups: int = 256 * 20):
+    """Device LDS read bandwidth: (bytes/s over the device, shader clock Hz measured during the loop)."""
+    bps, hz = ctypes.c_double(), ctypes.c_double()
+    check(lib().uwb_probe_lds_read(int(width), int(iters), int(n_groups), ctypes.byref(bps), ctypes.byref(hz),
+                                   _stream()), "uwb_probe_lds_read")
+    return float(bps.value), float(hz.value)
 
 
 def auto_decimation(min_tumour: float, pitch: float) -> int:
@@ -278,6 +316,7 @@ class SegmentResult:
     peak: float
     voxels_evaluated: int
     learned_mask: int = 0
+    guard_hits: int = 0
     roi_image: np.ndarray | None = None
 
 
@@ -295,7 +334,7 @@ def _results(buf: torch.Tensor, n: int, n_child: int):
             [[float(r.score[j][c]) for c in range(n_child)] for j in range(made)],
             [(float(r.wb[j][0]), float(r.wb[j][1])) for j in range(int(r.n_wb))],
             tuple(int(x) for x in r.roi), int(r.argmax), float(r.peak), int(r.voxels_evaluated),
-            int(r.learned_mask)))
+            int(r.learned_mask), int(r.guard_hits)))
     return out
 
 
@@ -316,6 +355,8 @@ def segment_refine_batch_async(batch: DeviceBatch, grid, tree: SegmentTree, wind
     ws = workspace if workspace is not None else _ws.get(need, dev)
     if out is None:
         out = torch.empty(ctypes.sizeof(UwbSegmentResult) * batch.n_scans, dtype=torch.uint8, device=dev)
+    _need_bytes(out, "out", ctypes.sizeof(UwbSegmentResult) * batch.n_scans)
+    _need_bytes(ws, "workspace", need)
     rp = 0
     if roi_img is not None:
         _need_cuda(roi_img, "roi_img")
@@ -412,7 +453,7 @@ class BatchPlan:
         n = len(self._keep)
         arr = (UwbBatchItem * n)()
         for k, (sc, g, out) in enumerate(self._keep):
-            _need_cuda(out, "out")
+            _need_cuda(out, "out", numel=_nvox(g))
             arr[k] = UwbBatchItem(sc.c(), grid_c(g), out.data_ptr())
         self.device = self._keep[0][2].device
         self._h = ctypes.c_void_p()
@@ -484,6 +525,8 @@ class CNN:
     def _x(x: torch.Tensor):
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.bfloat16 and x.is_contiguous()):
             raise TypeError("x must be a contiguous CUDA bfloat16 tensor [n, 32, 32]")
+        if x.dim() != 3 or tuple(x.shape[1:]) != (32, 32):
+            raise ValueError("x must be [n, 32, 32]")
         return x
 
     def forward(self, x: torch.Tensor, probs: torch.Tensor | None = None) -> torch.Tensor:
@@ -491,6 +534,7 @@ class CNN:
         n = int(x.shape[0])
         if probs is None:
             probs = torch.empty((n, 4), dtype=torch.float32, device=x.device)
+        _need_cuda(probs, "probs", numel=4 * n)
         check(lib().uwb_cnn_forward(self._h, x.data_ptr(), n, probs.data_ptr(), _stream(x.device)), "uwb_cnn_forward")
         return probs
 
@@ -499,14 +543,14 @@ class CNN:
         n = int(x.shape[0])
         g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
         loss = torch.empty(1, dtype=torch.float32, device=x.device)
-        _need_cuda(labels, "labels", torch.int32)
+        _need_cuda(labels, "labels", torch.int32, numel=n)
         check(lib().uwb_cnn_gradients(self._h, x.data_ptr(), labels.data_ptr(), n, g.data_ptr(), loss.data_ptr(),
                                       _stream(x.device)), "uwb_cnn_gradients")
         return g, loss
 
     def train_step(self, x: torch.Tensor, labels: torch.Tensor, lr: float, loss: torch.Tensor | None = None):
         x = self._x(x)
-        _need_cuda(labels, "labels", torch.int32)
+        _need_cuda(labels, "labels", torch.int32, numel=int(x.shape[0]))
         if loss is None:
             loss = torch.empty(1, dtype=torch.float32, device=x.device)
         check(lib().uwb_cnn_train_step(self._h, x.data_ptr(), labels.data_ptr(), int(x.shape[0]), float(lr),
@@ -562,6 +606,8 @@ def learned_refine_batch(batch: DeviceBatch, grid, tree: SegmentTree, cnn: CNN, 
     ws = workspace if workspace is not None else _ws.get(need, dev)
     if out is None:
         out = torch.empty(ctypes.sizeof(UwbSegmentResult) * batch.n_scans, dtype=torch.uint8, device=dev)
+    _need_bytes(out, "out", ctypes.sizeof(UwbSegmentResult) * batch.n_scans)
+    _need_bytes(ws, "workspace", need)
     roi = torch.empty(cap * batch.n_scans, dtype=torch.float32, device=dev) if want_roi else None
     check(lib().uwb_learned_refine_batch(ctypes.byref(bc), ctypes.byref(gc), window, ctypes.byref(tc), cnn._h,
                                          float(threshold), out.data_ptr(), roi.data_ptr() if roi is not None else 0,
@@ -676,7 +722,7 @@ def image_multistatic(scan: DeviceScan, grid, beamformer: int, window: int = 11,
     """Multistatic DAS (Eq. (4)) or DMAS image [nz, ny, nx] fp32."""
     if out is None:
         out = torch.empty(_img_shape(grid), dtype=torch.float32, device=scan.traces.device)
-    _need_cuda(out, "out")
+    _need_cuda(out, "out", numel=_nvox(grid))
     fn = lib().uwb_dmas_multistatic if beamformer == UWB_DMAS else lib().uwb_das_multistatic
     sc, gc = _ms_scan_c(scan), grid_c(grid)
     check(fn(ctypes.byref(sc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)), "image_multistatic")
@@ -690,8 +736,8 @@ def das_dmas_multistatic_batch(batch: DeviceBatch, grid, window: int = 11, out_d
         out_das = torch.empty(shape, dtype=torch.float32, device=batch.traces.device)
     if out_dmas is None:
         out_dmas = torch.empty(shape, dtype=torch.float32, device=batch.traces.device)
-    _need_cuda(out_das, "out_das")
-    _need_cuda(out_dmas, "out_dmas")
+    _need_cuda(out_das, "out_das", numel=batch.n_scans * _nvox(grid))
+    _need_cuda(out_dmas, "out_dmas", numel=batch.n_scans * _nvox(grid))
     bc = bc if bc is not None else _ms_batch_c(batch)
     gc = grid_c(grid)
     check(lib().uwb_das_dmas_multistatic_batch(ctypes.byref(bc), ctypes.byref(gc), window, out_das.data_ptr(),
@@ -703,7 +749,7 @@ def das_dmas_multistatic_batch(batch: DeviceBatch, grid, window: int = 11, out_d
 def image_multistatic_batch(batch: DeviceBatch, grid, beamformer: int, window: int = 11, out=None, bc=None):
     if out is None:
         out = torch.empty((batch.n_scans,) + _img_shape(grid), dtype=torch.float32, device=batch.traces.device)
-    _need_cuda(out, "out")
+    _need_cuda(out, "out", numel=batch.n_scans * _nvox(grid))
     fn = lib().uwb_dmas_multistatic_batch if beamformer == UWB_DMAS else lib().uwb_das_multistatic_batch
     bc = bc if bc is not None else _ms_batch_c(batch)
     gc = grid_c(grid)
@@ -717,7 +763,7 @@ def argmax_multistatic(scan: DeviceScan, grid, img, beamformer: int, window: int
     need = lib().uwb_argmax_workspace_bytes(ctypes.byref(gc), 1)
     ws = _ws.get(need, img.device)
     out = torch.empty(ctypes.sizeof(UwbPeak), dtype=torch.uint8, device=img.device)
-    _need_cuda(img, "img")
+    _need_cuda(img, "img", numel=_nvox(grid))
     check(lib().uwb_argmax_multistatic(ctypes.byref(sc), ctypes.byref(gc), window, beamformer, img.data_ptr(),
                                        out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(img.device)),
           "uwb_argmax_multistatic")
@@ -730,7 +776,7 @@ def argmax_multistatic_batch_async(batch: DeviceBatch, grid, img, beamformer: in
     need = lib().uwb_argmax_workspace_bytes(ctypes.byref(gc), batch.n_scans)
     ws = _ws.get(need, img.device)
     out = torch.empty(ctypes.sizeof(UwbPeak) * batch.n_scans, dtype=torch.uint8, device=img.device)
-    _need_cuda(img, "img")
+    _need_cuda(img, "img", numel=batch.n_scans * _nvox(grid))
     check(lib().uwb_argmax_multistatic_batch(ctypes.byref(bc), ctypes.byref(gc), window, beamformer, img.data_ptr(),
                                              out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(img.device)),
           "uwb_argmax_multistatic_batch")

@@ -54,7 +54,7 @@ class UwbSegmentResult(ctypes.Structure):
                 ("child", c_i32 * UWB_MAX_LEVELS), ("box", (c_i32 * 6) * (UWB_MAX_LEVELS + 1)),
                 ("score", (c_f64 * 8) * UWB_MAX_LEVELS), ("wb", (c_f64 * 2) * (UWB_MAX_LEVELS + 1)),
                 ("n_wb", c_i32), ("roi", c_i32 * 6), ("argmax", c_i64), ("peak", c_f64),
-                ("voxels_evaluated", c_i64), ("learned_mask", c_i32), ("reserved", c_i32)]
+                ("voxels_evaluated", c_i64), ("learned_mask", c_i32), ("guard_hits", c_i32)]
 
 
 class UwbBatchItem(ctypes.Structure):
@@ -144,6 +144,7 @@ PROTOTYPES = {
                                         c_vp, c_vp]),
     "uwb_generate_disc_scans": (c_i32, [ctypes.POINTER(UwbGenRecipe), c_vp, c_vp, c_i32, c_vp, c_vp, c_vp]),
     "uwb_auto_decimation": (c_i32, [c_f64, c_f64]),
+    "uwb_probe_lds_read": (c_i32, [c_i32, c_i32, c_i32, ctypes.POINTER(c_f64), ctypes.POINTER(c_f64), c_vp]),
     "uwb_status_string": (ctypes.c_char_p, [c_i32]),
     "uwb_version": (ctypes.c_char_p, []),
 }

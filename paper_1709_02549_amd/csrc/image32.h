@@ -27,6 +27,14 @@ void tile_shape(bool d3, int vpl, int *tx, int *ty, int *tz);
 
 constexpr int kStageBatch = 8;   // rows of 64 samples a wavefront loads before writing them
 
+// Windows shorter than this take the delay in FP64.  The FP32 delay carries an absolute error of about
+// 2e-5 samples (an ulp of a delay of ~200 samples); an energy summed over 5 or more taps spans a good part
+// of a pulse period and moves by ~1e-5 of itself, but the one or three taps of a short window can sit on a
+// pulse flank where |slope| / |sample| reaches ~8 per sample at a voxel of 1 % of the peak, which would put
+// the relative error of such a voxel at ~3e-4.  In FP64 the delay error is ~1e-13 samples and the only
+// FP32 roundings left are those of the fraction, the interpolation and the sums (~1e-7 relative).
+constexpr int kExactDelayWindow = 5;
+
 // Copies the staged span [first(j), first(j) + rs) of channels j = 0 .. nch-1 (trace j at
 // tr + j * T) to stage + j * rs, zero outside [0, T).  The workgroup's NW wavefronts take
 // the channels in turn, a row of 64 samples per load; each wavefront issues kStageBatch rows'
@@ -267,12 +275,34 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
             // software-pipelined over the lane's voxels: voxel v + 1's delay and window reads are
             // issued before voxel v's taps, so their LDS latency overlaps arithmetic
             auto locate = [&](int v, float &f, const float *&p) {
-                float tau;
-                if (MS) tau = dtx[v] + __builtin_amdgcn_sqrtf(leg_v(er, partr, v));
-                else tau = __builtin_amdgcn_sqrtf(leg_v(e, part, v)) - t0s;
-                tau = __builtin_amdgcn_fmed3f(tau, lof, hif);
-                f = __builtin_amdgcn_fractf(tau);
-                p = sb + floor_to_int(tau);
+                if constexpr (W < kExactDelayWindow) {
+                    // FP64 delay from the positions themselves (Eq. (1) / Eq. (2)); the window start is
+                    // clamped to the same integer bounds as below
+                    const int ch = a0 + jj;
+                    const float *at = j.pos + 3 * (MS ? ch / j.ms : ch), *ar = j.pos + 3 * (MS ? ch % j.ms : ch);
+                    const double rx = j.g.origin[0] + (double)vx * j.g.pitch[0];
+                    const double ry = j.g.origin[1] + (double)vy[v] * j.g.pitch[1];
+                    const double rz = j.g.origin[2] + (double)vz[v] * j.g.pitch[2];
+                    double dist = 0.0;
+#pragma unroll
+                    for (int leg = 0; leg < TE; ++leg) {
+                        const float *ap = leg == 0 ? at : ar;
+                        const double dx = rx - (double)ap[0], dy = ry - (double)ap[1], dz = rz - (double)ap[2];
+                        dist += sqrt(dx * dx + dy * dy + dz * dz);
+                    }
+                    const double tau = sc * dist - j.t0s;
+                    const double fl = floor(tau);
+                    const double n = fmin(fmax(fl, (double)lof), (double)hif);
+                    f = (float)(tau - fl);
+                    p = sb + (int)n;
+                } else {
+                    float tau;
+                    if (MS) tau = dtx[v] + __builtin_amdgcn_sqrtf(leg_v(er, partr, v));
+                    else tau = __builtin_amdgcn_sqrtf(leg_v(e, part, v)) - t0s;
+                    tau = __builtin_amdgcn_fmed3f(tau, lof, hif);
+                    f = __builtin_amdgcn_fractf(tau);
+                    p = sb + floor_to_int(tau);
+                }
             };
             float fc, yc[W + 1];
             {

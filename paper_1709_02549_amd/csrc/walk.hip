@@ -162,6 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_paper(const WalkArgs a, int n_s
         R.argmax = -1;
         R.peak = 0.0;
         R.learned_mask = 0;
+        R.guard_hits = 0;
     }
 }
 
@@ -213,6 +214,7 @@ __global__ void k_pl_finish(const WalkArgs a, int n_scans) {
     R.argmax = -1;
     R.peak = 0.0;
     R.learned_mask = 0;
+    R.guard_hits = 0;
 }
 
 // ----------------------------------------------------------------------------
@@ -356,6 +358,7 @@ __global__ void k_learn_finish(const WalkArgs a, int depth, int n_scans) {
     R.voxels_evaluated = (int64_t)depth * kLearnG * kLearnG + rv;
     R.argmax = -1;
     R.peak = 0.0;
+    R.guard_hits = 0;
 }
 
 // Training inputs: the coarse DAS lattice of every box on the path to `target`

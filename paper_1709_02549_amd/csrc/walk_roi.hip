@@ -237,6 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_roi_pick(const RoiArgs a) {
         if (first != LLONG_MAX) { b = cand[first]; pv = cval[first]; }
     }
     if (tid != 0) return;
+    R.guard_hits = count;   // FP32 candidates re-evaluated in FP64
     if (b == LLONG_MAX) {   // no finite candidate (e.g. a NaN image)
         R.argmax = -1;
         R.peak = __builtin_nan("");

@@ -270,3 +270,14 @@ def test_batch_plan_argument_errors():
     assert L.uwb_batch_plan_create(ctypes.byref(h), mixed, 2, 0, 11, None) == a.UWB_EUNSUPPORTED
     assert L.uwb_batch_run(None, None) == E
     assert L.uwb_batch_plan_destroy(None) == E
+
+
+def test_lds_probe_argument_errors():
+    a = _abi()
+    L = a.lib()
+    v, hz = ctypes.c_double(), ctypes.c_double()
+    E = a.UWB_EINVAL
+    assert L.uwb_probe_lds_read(3, 64, 8, ctypes.byref(v), ctypes.byref(hz), None) == E      # width
+    assert L.uwb_probe_lds_read(16, 7, 8, ctypes.byref(v), ctypes.byref(hz), None) == E      # iters % 8
+    assert L.uwb_probe_lds_read(16, 64, 0, ctypes.byref(v), ctypes.byref(hz), None) == E     # groups
+    assert L.uwb_probe_lds_read(16, 64, 8, None, ctypes.byref(hz), None) == E

@@ -45,7 +45,40 @@ def test_forward_matches_oracle(n):
     net.close()
 
 
+def _abs_gradient(p, xb, lab):
+    """Every gradient element's sum of the magnitudes of the terms it adds up: the oracle's backward pass run on
+    |weights|, |activations| and |upstream gradients|, with every ReLU whose input lies within 2^-6 of its
+    layer's largest pre-activation of zero counted as open (its mask can differ between the two sides).  A
+    stored BF16 activation differs between the GPU and the FP64 oracle by at most one BF16 ulp (2^-7 of it)
+    when the two sides' sums round to neighbouring BF16 values; each term of a gradient element inherits such
+    a relative difference from every rounded activation on its path, so |g_gpu - g_oracle| is bounded by a
+    few 2^-7 times this sum."""
+    logits, (a, pre, feat) = ocnn.forward(p, xb, act_round=ocnn.bf16_round)
+    n = logits.shape[0]
+    prob = ocnn.softmax(logits)
+    dlog = prob.copy()
+    dlog[np.arange(n), lab] -= 1.0
+    dlog = np.abs(dlog) / n
+    dwl = np.einsum("nc,nck->k", dlog, np.abs(feat))
+    dbl = float(dlog.sum())
+    dfeat = dlog[:, :, None] * np.abs(p.wl)[None, None, :]
+    da = np.zeros_like(a[-1])
+    for c in range(4):
+        bx, by = c & 1, c >> 1
+        da[:, :, 2 * by:2 * by + 2, 2 * bx:2 * bx + 2] += dfeat[:, c, :, None, None] / 4.0
+    dw, db = [None] * 4, [None] * 4
+    for i in reversed(range(4)):
+        z = pre[i]
+        open_ = z > -2.0 ** -6 * np.abs(z).max()
+        dz = da * open_
+        dx, dw[i], db[i] = ocnn.conv_backward(np.abs(a[i]), np.abs(p.w[i]), ocnn.STRIDES[i], dz)
+        da = dx
+    return ocnn.Params(dw, db, dwl, dbl).flat()
+
+
 def test_gradients_match_oracle():
+    """Element by element: |g_gpu - g_oracle| <= 4 * 2^-7 * (the element's sum of term magnitudes); per tensor:
+    L2 relative error <= 1e-2."""
     flat, p = _params(3)
     net = uwb().CNN(64, flat)
     xg, xb, lab = _inputs(64, 4)
@@ -53,11 +86,18 @@ def test_gradients_match_oracle():
     g = g.cpu().numpy().astype(np.float64)
     lo, go, _ = ocnn.loss_and_grad(p, xb, lab, act_round=ocnn.bf16_round)
     assert float(loss.cpu()) == pytest.approx(lo, rel=2e-3)
-    # per tensor: relative error of the gradient vector
+    ga = _abs_gradient(p, xb, lab)
+    assert np.all(ga >= np.abs(go) * (1 - 1e-12))          # the magnitude sum bounds the gradient itself
+    ratio = np.abs(g - go) / np.maximum(ga, 1e-300)
+    print(f"gradient error / magnitude sum: max {ratio.max():.3e}, 99.9th percentile "
+          f"{np.percentile(ratio, 99.9):.3e} (bound {4 * 2.0 ** -7:.3e})")
+    assert ratio.max() <= 4 * 2.0 ** -7
     bounds = [0, 288, 288 + 9216, 288 + 2 * 9216, 288 + 3 * 9216, 288 + 3 * 9216 + 128, 28097]
+    rels = []
     for a, b in zip(bounds[:-1], bounds[1:]):
-        rel = np.linalg.norm(g[a:b] - go[a:b]) / max(np.linalg.norm(go[a:b]), 1e-30)
-        assert rel <= 2e-2, (a, b, rel)
+        rels.append(np.linalg.norm(g[a:b] - go[a:b]) / max(np.linalg.norm(go[a:b]), 1e-30))
+    print("per-tensor L2 relative errors:", " ".join(f"{r:.2e}" for r in rels))
+    assert max(rels) <= 1e-2, rels
     net.close()
 
 

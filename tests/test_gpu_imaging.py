@@ -5,11 +5,10 @@ FP32 from values of magnitude <= ~200 samples (unit roundoff 6e-8 -> ~2e-5
 samples), and the pulse changes by at most ~0.8 of its peak per sample, so each
 aligned sample carries ~1e-5 relative error; DAS energy doubles it, DMAS energy
 quadruples it.  The gate is 1e-4 of the image peak everywhere, and 1e-4
-relative on every voxel brighter than 1% of the peak.  For windows of 1 or 3
-samples the energy is one or a few squared samples with no averaging over the
-pulse: at a voxel at 1% of the peak a sample can sit on a flank where
-|slope| / |s| ~ 8 per sample, so 2 * 8 * 2e-5 = 3.2e-4 relative is possible and
-that per-voxel gate is 5e-4 (the peak-normalised gate stays 1e-4).
+relative on every voxel brighter than 1% of the peak.  Windows of 1 or 3
+samples have no averaging over the pulse (a voxel at 1% of the peak can sit on a
+flank where |slope| / |s| ~ 8 per sample, ~3e-4 with an FP32 delay), so the
+kernels take their delay in FP64 and the same 1e-4 gate holds for them.
 Argmax: bit-exact.
 """
 import numpy as np
@@ -39,7 +38,7 @@ def _check_image(got, want, window=11):
     assert err <= REL_PEAK, f"max |dI| / peak = {err:.3e}"
     bright = want >= 1e-2 * peak
     rel = np.max(np.abs(got[bright] - want[bright]) / want[bright])
-    assert rel <= (REL_BRIGHT if window >= 5 else 5e-4), f"bright-voxel relative error {rel:.3e}"
+    assert rel <= REL_BRIGHT, f"bright-voxel relative error {rel:.3e} (window {window})"
     return err
 
 
@@ -120,51 +119,36 @@ def test_dmas_single_antenna_is_zero():
     assert torch.count_nonzero(img).item() == 0
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
 @pytest.mark.parametrize("bf", [0, 1])
-def test_c2_full_size_sampled(bf):
-    """C2 at full size (512 x 512, 32 antennas, T = 2048): 3000 sampled voxels + the argmax."""
-    s = synth.c2_scan(0)
+def test_c2_full_size(seed, bf):
+    """C2 at full size (512 x 512, 32 antennas, T = 2048, 200 clutter scatterers, 20 dB): every voxel against the
+    full oracle image at the image bar, and the detection equal to the oracle's argmax over the whole grid."""
+    s = synth.c2_scan(seed)
     ds, img = _gpu_image(s, bf)
-    got = img.cpu().numpy()
-    rng = np.random.default_rng(1)
-    nx = s.grid.dims[0]
-    sel = rng.choice(nx * nx, 3000, replace=False)
+    want = oracle.image_grid(s, bf)
+    _check_image(img.cpu().numpy(), want)
     p = uwb().argmax(ds, s.grid, img, bf)
-    sel = np.unique(np.concatenate([sel, [p.index]]))
-    idx = np.stack([sel % nx, sel // nx, np.zeros_like(sel)], 1)
-    want = oracle.image_indices(s, bf, idx)
-    peak = p.value
-    assert np.max(np.abs(got.ravel()[sel] - want)) / peak <= REL_PEAK
-    # the argmax itself: FP64 value agrees, and no sampled voxel beats it
-    j = int(np.searchsorted(sel, p.index))
-    assert want[j] == pytest.approx(p.value, rel=1e-12)
-    assert want.max() <= p.value * (1 + 1e-12)
-    # the maximum over a 9 x 9 neighbourhood in the oracle is the same voxel
-    ix, iy = p.index % nx, p.index // nx
-    xs = np.arange(max(0, ix - 4), min(nx, ix + 5))
-    ys = np.arange(max(0, iy - 4), min(nx, iy + 5))
-    nb = np.stack(np.meshgrid(xs, ys, [0], indexing="ij"), -1).reshape(-1, 3)
-    vals = oracle.image_indices(s, bf, nb)
-    a = oracle.select_max(vals, oracle.linear_index(nb, s.grid.dims))[0]
-    assert a == p.index
+    a, v = oracle.argmax_grid(want)
+    assert p.index == a
+    assert p.value == pytest.approx(v, rel=1e-12)
 
 
 @pytest.mark.parametrize("bf", [0, 1])
-def test_c3_full_size_sampled(bf):
-    """C3 at full size (256^3, 64 antennas, T = 4096): 400 sampled voxels."""
+def test_c3_full_size(bf):
+    """C3 at full size (256^3, 64 antennas on the hemisphere, T = 4096, 1000 clutter scatterers): all 16.8 M voxels
+    against the full oracle image (direct pairwise DMAS: 3.7e11 pair products, tens of seconds on the host), and
+    the detection equal to the oracle's argmax over the whole volume."""
     s = synth.c3_scan(0)
     ds, img = _gpu_image(s, bf)
-    got = img.cpu().numpy()
-    rng = np.random.default_rng(2)
-    n = s.grid.dims[0]
-    sel = rng.choice(n ** 3, 400, replace=False)
     p = uwb().argmax(ds, s.grid, img, bf)
-    sel = np.unique(np.concatenate([sel, [p.index]]))
-    idx = np.stack([sel % n, (sel // n) % n, sel // (n * n)], 1)
-    want = oracle.image_indices(s, bf, idx)
-    assert np.max(np.abs(got.ravel()[sel] - want)) / p.value <= REL_PEAK
-    j = int(np.searchsorted(sel, p.index))
-    assert want[j] == pytest.approx(p.value, rel=1e-12)
+    got = img.cpu().numpy()
+    del img
+    want = oracle.image_grid(s, bf)
+    _check_image(got, want)
+    a, v = oracle.argmax_grid(want)
+    assert p.index == a
+    assert p.value == pytest.approx(v, rel=1e-12)
 
 
 @pytest.mark.parametrize("bf", [0, 1])

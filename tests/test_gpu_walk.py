@@ -21,6 +21,17 @@ def _params(**kw):
     return oracle.TreeParams(**kw), uwb().SegmentTree(**kw)
 
 
+# largest relative GPU - oracle difference of the walk's FP64 scores and W/B figures over the session
+# (printed in the terminal summary; the decisions themselves are compared exactly)
+SCORE_DIFF = {"score": 0.0, "wb": 0.0}
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    d = np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+    return float(np.max(np.where(a == b, 0.0, d))) if d.size else 0.0
+
+
 def _compare(g, o, exact_scores=1e-9):
     assert g.child == o.child
     assert g.n_levels == o.n_levels and g.term_level == o.term_level
@@ -31,20 +42,26 @@ def _compare(g, o, exact_scores=1e-9):
     assert g.voxels_evaluated == o.voxels_evaluated
     for a, b in zip(g.scores, o.scores):
         np.testing.assert_allclose(a, b, rtol=exact_scores, atol=1e-300)
+        SCORE_DIFF["score"] = max(SCORE_DIFF["score"], _rel(a, b))
     assert len(g.wb) == len(o.wb)
     for a, b in zip(g.wb, o.wb):
         np.testing.assert_allclose(a, b, rtol=1e-9)
+        SCORE_DIFF["wb"] = max(SCORE_DIFF["wb"], _rel(a, b))
+    # the detection was decided in FP64 over the ROI's near-maximal FP32 candidates, the winner among them
+    if g.argmax >= 0:
+        x0, x1, y0, y1, z0, z1 = g.roi
+        assert 1 <= g.guard_hits <= (x1 - x0) * (y1 - y0) * (z1 - z0)
     if o.roi_image is not None and g.roi_image is not None:
         roi_close(g.roi_image, o.roi_image)
 
 
 def roi_close(got, want, window=11):
     """The ROI is imaged in FP32 (its detection is decided in FP64, checked above): the full-image bar,
-    |error| <= 1e-4 x peak everywhere and <= 1e-4 relative above 1 % of the peak (5e-4 for windows under 5)."""
+    |error| <= 1e-4 x peak everywhere and <= 1e-4 relative above 1 % of the peak."""
     peak = np.abs(want).max()
     assert np.max(np.abs(got - want)) <= 1e-4 * peak
     big = np.abs(want) > 1e-2 * peak
-    assert np.max(np.abs(got[big] - want[big]) / np.abs(want[big])) <= (5e-4 if window < 5 else 1e-4)
+    assert np.max(np.abs(got[big] - want[big]) / np.abs(want[big])) <= 1e-4
 
 
 def composite_close(got, want, roi):
@@ -150,6 +167,9 @@ def test_flat_scan_ties_everywhere(walk, kw, bf):
     assert g.child == o.child and tuple(g.roi) == tuple(o.roi)
     assert g.argmax == o.argmax == s0.grid.dims[0] * o.roi[2] + o.roi[0]
     assert g.peak == 0.0 and not g.roi_image.any()
+    # every ROI voxel ties with the maximum: each one is re-evaluated in FP64
+    x0, x1, y0, y1, z0, z1 = g.roi
+    assert g.guard_hits == (x1 - x0) * (y1 - y0) * (z1 - z0)
 
 
 @pytest.mark.parametrize("bf,metric,term", [(0, "max", "fixed"), (1, "eq5", "wb")])

@@ -59,6 +59,36 @@ def test_eq5_limits():
     assert metric_value("eq5", x, x) == pytest.approx(0.5)
 
 
+def test_eq5_clamped_by_hand():
+    """The clamped reading of Eq. (5) (alpha limited to [0, 1], Section III prose), on sets small enough to work
+    out by hand.  alpha = (var_c - var_p) / var_c can never exceed 1 (variances are >= 0), so the upper bound
+    never binds; these sets pin the lower bound, the unclamped interior and the normalisation by the parent's
+    maximum, and fail if the clamp is dropped, swapped or applied to the wrong quantity."""
+    # child variance below the parent's: literal alpha = -49.75, clamped to 0 -> M = mean
+    parent = np.array([0.0, 2.0, 1.0, 1.2])            # max 2 -> normalised [0, 1, 0.5, 0.6], variance 0.126875
+    child = np.array([1.0, 1.2])                       # normalised [0.5, 0.6]: mean 0.55, variance 0.0025
+    assert metric_value("eq5_clamped", child, parent) == pytest.approx(0.55, rel=1e-14)
+    # the literal Eq. (5) keeps alpha = -49.75: (1 + 49.75) * 0.55 - 49.75 * 0.0025
+    assert metric_value("eq5", child, parent) == pytest.approx(50.75 * 0.55 - 49.75 * 0.0025, rel=1e-14)
+    # child variance above the parent's: alpha = (0.25 - 0.125) / 0.25 = 0.5 inside [0, 1], both readings agree
+    parent = np.array([0.0, 4.0, 2.0, 2.0])            # normalised [0, 1, 0.5, 0.5], variance 0.125
+    child = np.array([0.0, 4.0])                       # normalised [0, 1]: mean 0.5, variance 0.25
+    for name in ("eq5", "eq5_clamped"):
+        assert metric_value(name, child, parent) == pytest.approx(0.5 * 0.5 + 0.5 * 0.25, rel=1e-14)
+    # parent variance 1/8 of the child's: alpha = 7/8 -> M = mean / 8 + 7 variance / 8
+    parent = np.array([0.0, 1.0] + [0.5] * 14)         # variance 0.5 / 16 = 0.03125 (max 1: no scaling)
+    child = np.array([0.0, 1.0])                       # mean 0.5, variance 0.25
+    sp = np.var(parent)
+    assert sp == pytest.approx(0.03125, rel=1e-14)
+    a = (0.25 - sp) / 0.25
+    assert a == pytest.approx(0.875, rel=1e-14)
+    for name in ("eq5", "eq5_clamped"):
+        assert metric_value(name, child, parent) == pytest.approx((1 - a) * 0.5 + a * 0.25, rel=1e-14)
+    # constant child: variance 0 -> alpha = 0 -> the mean, clamped or not
+    for name in ("eq5", "eq5_clamped"):
+        assert metric_value(name, np.full(3, 2.0), np.array([0.0, 2.0, 4.0])) == pytest.approx(0.5, rel=1e-14)
+
+
 def test_eq5_scale_invariant():
     rng = np.random.default_rng(1)
     p = rng.uniform(0, 1, 64)
