@@ -24,6 +24,8 @@
  *              summed, then the windowed energy is taken:
  *              I(r) = sum_k ( sum_{i<j} s_i(r,k) s_j(r,k) )^2.
  *              Evaluated here as the literal O(M^2) double loop.
+ *   samples    The aligned window samples themselves are exported too, for the
+ *              Capon (MVDR) beamformer of oracle/mvdr.py, which weights them.
  */
 #include <math.h>
 #include <stdint.h>
@@ -125,29 +127,34 @@ int oracle_image_indices(int beamformer, int n_ant, int n_samp, const float *ant
     return used;
 }
 
-/* Same, at explicit positions [n][3] (metres). */
-int oracle_image_points(int beamformer, int n_ant, int n_samp, const float *ant_pos,
-                        const float *traces, double dt, double t0, double v, int window, long n,
-                        const double *pts, double *out, int n_threads)
+/*
+ * The aligned window samples themselves, for beamformers that weight them
+ * (Capon / MVDR): out[p][i][k + h] = s_i(r_p, k), the Eq. (3) argument of
+ * antenna i at window offset k = -h..h, linear interpolation, zero outside the
+ * trace.  out holds n * n_ant * window doubles.
+ */
+int oracle_aligned_samples(int n_ant, int n_samp, const float *ant_pos, const float *traces, double dt,
+                           double t0, double v, int window, const double *origin, const double *pitch, long n,
+                           const int32_t *idx, double *out, int n_threads)
 {
     int used = 1;
+    int h = (window - 1) / 2;
 #ifdef _OPENMP
     if (n_threads <= 0)
         n_threads = omp_get_max_threads();
     used = n_threads;
-#pragma omp parallel num_threads(n_threads)
+#pragma omp parallel for num_threads(n_threads) schedule(dynamic, 64)
 #endif
-    {
-        double *tau = (double *)malloc(sizeof(double) * (size_t)n_ant);
-        double *s = (double *)malloc(sizeof(double) * (size_t)n_ant);
-#ifdef _OPENMP
-#pragma omp for schedule(dynamic, 64)
-#endif
-        for (long p = 0; p < n; ++p)
-            out[p] = focal_point_energy(beamformer, n_ant, n_samp, ant_pos, traces, dt, t0, v,
-                                        window, pts + 3 * p, tau, s);
-        free(tau);
-        free(s);
+    for (long p = 0; p < n; ++p) {
+        double r[3];
+        for (int d = 0; d < 3; ++d)
+            r[d] = origin[d] + (double)idx[3 * p + d] * pitch[d];
+        for (int i = 0; i < n_ant; ++i) {
+            double tau = round_trip_delay(r, ant_pos + 3 * i, v, dt, t0);
+            for (int k = -h; k <= h; ++k)
+                out[((size_t)p * n_ant + i) * window + (k + h)] =
+                    aligned_sample(traces + (size_t)i * n_samp, n_samp, tau, k);
+        }
     }
     return used;
 }
@@ -232,6 +239,36 @@ int oracle_image_indices_ms(int beamformer, int n_ant, int n_samp, const float *
         }
         free(tau);
         free(s);
+    }
+    return used;
+}
+
+/* Multistatic counterpart of oracle_aligned_samples: the M^2 channels (Eq. (2) delay), out [n][M*M][window]. */
+int oracle_aligned_samples_ms(int n_ant, int n_samp, const float *ant_pos, const float *traces, double dt,
+                              double t0, double v, int window, const double *origin, const double *pitch, long n,
+                              const int32_t *idx, double *out, int n_threads)
+{
+    int used = 1;
+    int h = (window - 1) / 2;
+    size_t n_ch = (size_t)n_ant * (size_t)n_ant;
+#ifdef _OPENMP
+    if (n_threads <= 0)
+        n_threads = omp_get_max_threads();
+    used = n_threads;
+#pragma omp parallel for num_threads(n_threads) schedule(dynamic, 16)
+#endif
+    for (long p = 0; p < n; ++p) {
+        double r[3];
+        for (int d = 0; d < 3; ++d)
+            r[d] = origin[d] + (double)idx[3 * p + d] * pitch[d];
+        for (int i = 0; i < n_ant; ++i)
+            for (int j = 0; j < n_ant; ++j) {
+                size_t c = (size_t)i * n_ant + j;
+                double tau = path_delay(r, ant_pos + 3 * i, ant_pos + 3 * j, v, dt, t0);
+                for (int k = -h; k <= h; ++k)
+                    out[((size_t)p * n_ch + c) * window + (k + h)] =
+                        aligned_sample(traces + c * n_samp, n_samp, tau, k);
+            }
     }
     return used;
 }

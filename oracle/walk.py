@@ -58,7 +58,7 @@ MIN_CHILD_SAMPLES = 4
 
 @dataclasses.dataclass
 class TreeParams:
-    beamformer: int = 0          # 0 = DAS, 1 = DMAS
+    beamformer: int = 0          # 0 = DAS, 1 = DMAS, 2 = Capon / MVDR (oracle.mvdr)
     walk: str = "per_level"      # "per_level" | "paper"
     coarse: int = 8              # g: lattice points per side per level (per_level)
     decimation: int = 0          # D (paper); 0 = automatic from min_tumour
@@ -68,6 +68,7 @@ class TreeParams:
     term: str = "fixed"          # "fixed" | "wb"
     frame_level: float = 0.0     # sliding frame, fraction of the child side
     frame_final: float = 0.25    # frame applied to the last box before final imaging
+    loading: float = 3.0         # MVDR diagonal loading, relative to the mean channel power
 
 
 @dataclasses.dataclass
@@ -219,7 +220,7 @@ def walk(scan, params: TreeParams, window: int = 11, image_fn=None, n_threads: i
     n_child = 1 << len(active)
     if image_fn is None:
         def image_fn(idx):
-            return image_indices(scan, params.beamformer, idx, window, n_threads)
+            return image_indices(scan, params.beamformer, idx, window, n_threads, loading=params.loading)
 
     full = (0, dims[0], 0, dims[1], 0, dims[2])
     boxes = [full]
