@@ -158,6 +158,30 @@ int uwb_argmax_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t 
                      size_t workspace_bytes, void *stream);
 
 /*
+ * Allocation-free detection, for callers that cannot allocate device memory
+ * while they run: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  The same computation and result as uwb_argmax_batch
+ * (same kernels, same rule, bit-identical uwb_peak records), with its scratch
+ * taken from a device array the library holds instead of a workspace argument.
+ *   scans, grid, window, beamformer, img, out   as uwb_argmax_batch (device
+ *            img and out, caller-owned)
+ *   Limit: uwb_argmax_workspace_bytes(grid, n_scans) must not exceed
+ *          UWB_ARGMAX_SCRATCH_BYTES (4 MiB: e.g. 256 scans of 512 x 512, or one
+ *          256^3 volume); a larger request returns UWB_ERANGE before anything
+ *          is launched.
+ *   The array is one per GPU (the current device, hipGetDevice, whose queue
+ *   `stream` must be), held from the first call on that device until the
+ *   process ends.  Calls on one GPU share it: calls that overlap on that GPU
+ *   (concurrent streams, or host threads) race and may return wrong results;
+ *   serialise them (one stream, or events).  Calls no hipMalloc / hipFree.
+ *   Errors: as uwb_argmax_batch; UWB_ERANGE as above; UWB_EHIP if the device
+ *   address of the array cannot be obtained.
+ */
+#define UWB_ARGMAX_SCRATCH_BYTES (4u << 20)
+int uwb_argmax_batch_noalloc(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window,
+                             int32_t beamformer, const float *img, uwb_peak *out, void *stream);
+
+/*
  * Coarse-to-fine segment walk (Section III).
  *
  * walk = UWB_WALK_PAPER follows the three phases as written: one image of the

@@ -260,6 +260,22 @@ def argmax_batch_async(batch: DeviceBatch, grid, img: torch.Tensor, beamformer: 
     return out
 
 
+ARGMAX_SCRATCH_BYTES = 4 << 20   # UWB_ARGMAX_SCRATCH_BYTES: the allocation-free detection's scratch limit
+
+
+def argmax_batch_noalloc_async(batch: DeviceBatch, grid, img: torch.Tensor, beamformer: int, out: torch.Tensor,
+                               window: int = 11, bc=None) -> torch.Tensor:
+    """The allocation-free detection (uwb_argmax_batch_noalloc): the library's own device scratch instead of a
+    workspace; the caller passes the output records (one uwb_peak per scan), and nothing is allocated here."""
+    gc = grid_c(grid)
+    bc = bc if bc is not None else batch.c()
+    _need_cuda(img, "img", numel=batch.n_scans * _nvox(grid))
+    _need_bytes(out, "out", ctypes.sizeof(UwbPeak) * batch.n_scans)
+    check(lib().uwb_argmax_batch_noalloc(ctypes.byref(bc), ctypes.byref(gc), window, beamformer, img.data_ptr(),
+                                         out.data_ptr(), _stream(img.device)), "uwb_argmax_batch_noalloc")
+    return out
+
+
 def argmax_batch(batch, grid, img, beamformer, window=11):
     return _peaks(argmax_batch_async(batch, grid, img, beamformer, window), batch.n_scans)
 

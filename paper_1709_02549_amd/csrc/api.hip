@@ -311,6 +311,22 @@ int uwb_argmax_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t 
                               stream);
 }
 
+int uwb_argmax_batch_noalloc(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, int32_t beamformer,
+                             const float *img, uwb_peak *out, void *stream) {
+    ScanSet ss;
+    int st = batch_set(scans, &ss);
+    if (st) return st;
+    GridView g;
+    if ((st = check_grid(grid, &g))) return st;
+    if ((st = check_window(window))) return st;
+    if (beamformer != UWB_DAS && beamformer != UWB_DMAS) return UWB_EINVAL;
+    if (!img || !out) return UWB_EINVAL;
+    if (argmax_ws_bytes(g, scans->n_scans) > (size_t)UWB_ARGMAX_SCRATCH_BYTES) return UWB_ERANGE;
+    void *ws = nullptr;
+    if ((st = argmax_scratch(&ws))) return st;
+    return launch_argmax(beamformer, ss, scans->n_scans, g, window, img, out, ws, (hipStream_t)stream);
+}
+
 int64_t uwb_segment_roi_capacity(const uwb_grid *finest, const uwb_segment_tree *tree) {
     GridView g;
     int st = check_grid(finest, &g);

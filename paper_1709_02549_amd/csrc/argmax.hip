@@ -16,6 +16,7 @@
 #include <climits>
 #include <cstdint>
 #include <cmath>
+#include <mutex>
 
 #include "uwb_internal.h"
 
@@ -340,6 +341,33 @@ int launch_argmax(int bf, const ScanSet &ss, int n_scans, const GridView &g, int
     hipLaunchKernelGGL(k_chunk_select, gc, dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_final, gs, dim3(kBlock), 0, st, a);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
+}
+
+// Scratch of the allocation-free detection (uwb_argmax_batch_noalloc): the chunk and scan records of
+// stages A-F, in a device array that every GPU the library runs on holds once, until the process ends.
+// Every record is written by the stage that produces it before a later stage reads it, so nothing has to
+// start at zero.  Host code never passes the array's name to a kernel (on the host it stands for a
+// host-side shadow, not a device address): it takes each device's address once from
+// hipGetSymbolAddress and hands that pointer to the kernels like any workspace.
+namespace {
+static __device__ __align__(256) unsigned char scratch[UWB_ARGMAX_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+int argmax_scratch(void **ptr) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return UWB_EHIP;
+    if (dev >= kMaxDevices) return UWB_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return UWB_EHIP;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return UWB_OK;
 }
 
 }  // namespace uwb

@@ -297,4 +297,7 @@ int launch_image32(int bf, const ScanSet &ss, int n_scans, const GridView &g, in
 int launch_argmax(int bf, const ScanSet &ss, int n_scans, const GridView &g, int window, const float *img,
                   uwb_peak *out, void *ws, hipStream_t stream);
 size_t argmax_ws_bytes(const GridView &g, int n_scans);
+// This device's scratch of the allocation-free detection (UWB_ARGMAX_SCRATCH_BYTES bytes), its address
+// taken once per device; UWB_EHIP if the runtime cannot give it.
+int argmax_scratch(void **ptr);
 }  // namespace uwb

@@ -151,6 +151,30 @@ def test_argmax_argument_errors():
     assert L.uwb_argmax_workspace_bytes(None, 1) == 0
 
 
+def test_argmax_noalloc_limit_and_errors():
+    """The allocation-free detection refuses requests whose records exceed its fixed scratch (before any HIP
+    call), and the usual argument errors."""
+    a = _abi()
+    L = a.lib()
+    f = L.uwb_argmax_batch_noalloc
+    limit = 4 << 20
+    ok = a.UwbScanBatch(n_scans=256, n_ant=32, n_samp=2048, ant_pos=FAKE, traces=FAKE, params=FAKE, v_min=1e8,
+                        dt_min=2e-11)
+    g512 = _grid(dims=(512, 512, 1))
+    assert 0 < L.uwb_argmax_workspace_bytes(ctypes.byref(g512), 256) <= limit      # the documented example fits
+    assert 0 < L.uwb_argmax_workspace_bytes(ctypes.byref(_grid(dims=(256, 256, 256))), 1) <= limit
+    big = a.UwbScanBatch(n_scans=512, n_ant=32, n_samp=2048, ant_pos=FAKE, traces=FAKE, params=FAKE, v_min=1e8,
+                         dt_min=2e-11)
+    assert L.uwb_argmax_workspace_bytes(ctypes.byref(g512), 512) > limit
+    assert f(ctypes.byref(big), ctypes.byref(g512), 11, 1, FAKE, FAKE, None) == a.UWB_ERANGE
+    assert f(ctypes.byref(ok), ctypes.byref(g512), 11, 2, FAKE, FAKE, None) == a.UWB_EINVAL
+    assert f(ctypes.byref(ok), ctypes.byref(g512), 11, 1, None, FAKE, None) == a.UWB_EINVAL
+    assert f(ctypes.byref(ok), ctypes.byref(g512), 11, 1, FAKE, None, None) == a.UWB_EINVAL
+    assert f(ctypes.byref(ok), ctypes.byref(g512), 4, 1, FAKE, FAKE, None) == a.UWB_EINVAL
+    assert f(None, ctypes.byref(g512), 11, 1, FAKE, FAKE, None) == a.UWB_EINVAL
+    assert f(ctypes.byref(ok), None, 11, 1, FAKE, FAKE, None) == a.UWB_EINVAL
+
+
 def _tree(**kw):
     a = _abi()
     d = dict(beamformer=0, walk=0, coarse=8, decimation=0, min_tumour=0.01, max_depth=0, metric=3, term=0,
