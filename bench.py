@@ -1,19 +1,24 @@
 """Benchmark of the DAS / DMAS hot path on one MI355X.
 
-Workload (the 2D hierarchical-segmentation configuration): B synthetic scans,
-each 32 antennas on a 7 cm ring, 2048 fp32 samples at 50 GS/s, one tumour plus
-200 clutter scatterers, 20 dB SNR, imaged on a 512 x 512 finest grid.  One step
-processes the whole batch, inputs already resident in HBM:
-  full-resolution DAS and DMAS images  -> FP64-decided argmax of each
-  coarse-to-fine quadtree walks (g = 16 down to 16 x 16 boxes, metric = max) with
-  DAS and with DMAS, each ending in a full-resolution ROI and its argmax.
-value = full-resolution voxel*antenna pairs (DAS + DMAS) per second over the
-whole step (walks and argmax included in the time).
+Workload (the 2D hierarchical-segmentation configuration): B distinct synthetic
+scans, each 32 antennas on a 7 cm ring, 2048 fp32 samples at 50 GS/s, one tumour
+plus 200 clutter scatterers, 20 dB SNR, imaged on a 512 x 512 finest grid.  One
+step processes the whole batch, inputs already resident in HBM:
+  full-resolution DAS and DMAS images (one gather feeds both)  -> FP64-decided
+  argmax of each; coarse-to-fine quadtree walks (g = 16 down to 16 x 16 boxes,
+  metric = max) with DAS and with DMAS, each ending in a full-resolution ROI and
+  its argmax.
+value = full-resolution voxel*antenna pairs per second over the whole step (walks
+and argmax included in the time), each pair counted once although it feeds both
+the DAS and the DMAS image.
 
-After the timed steps (outside them) the learned proposer is trained on GPU-
-generated scans of the same recipe (labels from full-resolution DMAS) and the
-learned walk, the metric walks and full-resolution DMAS are compared on held-out
-seeds: fraction within one voxel (L-inf) of the full-DMAS detection, and scans/s.
+Outside the timed steps: the same step's parts as separate launches; the 2D
+single-scan configuration (16 antennas, 128 x 128) as latency; the 3D
+configuration (64 antennas on a hemisphere, 4096 samples, 256^3 voxels) as
+full-resolution throughput and octree walks against full-resolution DMAS; the
+batched uneven-scan plan; the multistatic ring; the learned proposer trained on
+GPU-generated scans and compared with the metric walks and full-resolution DMAS;
+the device's LDS read bandwidth; and the FP64 oracle timed on the host.
 
 Prints one JSON line (progress goes to stderr).  Only N = 1 GPU is supported.
 """
@@ -67,7 +72,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256)
-    ap.add_argument("--distinct", type=int, default=64, help="distinct seeded scans in the batch")
+    ap.add_argument("--distinct", type=int, default=0, help="distinct seeded scans in the batch (0: all)")
     ap.add_argument("--coarse", type=int, default=16, help="walk lattice points per side (g)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -79,6 +84,9 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the batched-serving measurement")
     ap.add_argument("--ms-batch", type=int, default=512, help="multistatic scans (12-antenna ring, 200x200 grid)")
     ap.add_argument("--no-ms", action="store_true", help="skip the multistatic and no-tumour-check measurements")
+    ap.add_argument("--c3-scans", type=int, default=32, help="3D scans for the octree walks against full DMAS")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 3D (256^3) measurements")
+    ap.add_argument("--no-c1", action="store_true", help="skip the single-scan latency measurements")
     ap.add_argument("--no-separate", action="store_true",
                     help="skip timing the DAS and DMAS kernels as separate launches (profiling runs)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
@@ -99,7 +107,7 @@ def main():
     torch.cuda.set_device(dev)
     B, W = args.batch, 11
     t_gen = time.time()
-    distinct = [synth.c2_scan(k) for k in range(min(args.distinct, B))]
+    distinct = [synth.c2_scan(k) for k in range(min(args.distinct, B) if args.distinct > 0 else B)]
     scans = [distinct[k % len(distinct)] for k in range(B)]
     gen_s = time.time() - t_gen
     grid = scans[0].grid
@@ -173,7 +181,9 @@ def main():
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     va = B * nx * ny * nz * M
-    value = 2 * va / (ms_step * 1e-3) / 1e9        # Gvoxel*antenna/s, DAS + DMAS, whole step
+    # Gvoxel*antenna/s over the whole step; each pair is counted once, although its gathered samples feed both
+    # the DAS and the DMAS image
+    value = va / (ms_step * 1e-3) / 1e9
 
     med = {k: float(np.median(v)) for k, v in times.items()}
 
@@ -196,6 +206,17 @@ def main():
         sep["das"] = launch_ms(lambda: uwb.image_batch(batch, grid, 0, W, img_das, bc=bc))
         sep["dmas"] = launch_ms(lambda: uwb.image_batch(batch, grid, 1, W, img_dmas, bc=bc))
     dmas_ms = sep.get("dmas", med["img"])
+
+    # each walk on its own (the step runs the DAS and the DMAS walk on two streams at once)
+    def walk_once(bf):
+        out, ws = walk_bufs[bf]
+        uwb.segment_refine_batch_async(batch, grid, trees[bf], W, out=out, workspace=ws, bc=bc)
+
+    walk_alone = {bf: launch_ms(lambda bf=bf: walk_once(bf), reps=21) for bf in (0, 1)}
+    arg_alone = {bf: launch_ms(lambda bf=bf: uwb.argmax_batch_async(
+        batch, grid, img_dmas if bf else img_das, bf, W, pk_dmas if bf else pk_das, ws_argmax[bf], bc=bc), reps=21)
+        for bf in (0, 1)}
+    # the last launches above leave the step's detections and walk results in place for the accuracy checks
 
     # the two walks of a step are launch-bound at this batch (about a dozen small kernels each): the
     # same calls replayed as one HIP graph (kernels only: no memsets, no host synchronisation)
@@ -235,6 +256,7 @@ def main():
     achieved = fpva * va / (med["img"] * 1e-3)
     counters_valid = TRAFFIC["source_hash"] == _kernel_source_hash()
     va_rate = va / (med["img"] * 1e-3)             # voxel·antenna/s of the launch
+    lds = lds_peak(uwb)
     traffic = TRAFFIC["bytes"] if (TRAFFIC["source_hash"] == _kernel_source_hash() and B == TRAFFIC["batch"]) \
         else None
     out = {
@@ -261,28 +283,45 @@ def main():
                      "avg_launch_ms": round(med["img"], 5),
                      "hbm_gbs": round(traffic / (med["img"] * 1e-3) / 1e9, 1) if traffic else None,
                      "hbm_frac": round(traffic / (med["img"] * 1e-3) / 8e12, 4) if traffic else None,
-                     # the gather's other on-chip bounds: 48 B of LDS reads per voxel·antenna against
-                     # 128 B/clk/CU, and VALU issue (counted instructions, while the sources match)
-                     "lds_frac": round(va_rate * 48 / LDS_PEAK, 4),
+                     # the gather's other on-chip bounds: 48 B of LDS reads per voxel·antenna against the LDS
+                     # read bandwidth measured on this device (and against the 128 B/clk/CU prior), and VALU
+                     # issue (counted instructions, while the sources match the counters)
+                     "lds_frac": round(va_rate * 48 / lds["bytes_per_s"], 4),
+                     "lds_frac_vs_128B_clk_cu_prior": round(va_rate * 48 / LDS_PEAK, 4),
                      "valu_issue_frac": round(va_rate * TRAFFIC["valu_per_va"] / 64 / VALU_ISSUE_PEAK, 4)
                      if counters_valid else None},
+        "value_counts": "each full-resolution voxel·antenna once; one gather feeds both the DAS and the DMAS image",
         "components_ms": {k: round(v, 5) for k, v in med.items()},
-        "das_dmas_one_launch_gvas": round(2 * va / (med["img"] * 1e-3) / 1e9, 2),
+        "das_dmas_one_launch_gvas_per_image": round(va / (med["img"] * 1e-3) / 1e9, 2),
+        "das_dmas_one_launch_gvas_two_image_sum": round(2 * va / (med["img"] * 1e-3) / 1e9, 2),
         "separate_launch_ms": {k: round(v, 5) for k, v in sep.items()},
         "das_gvas": round(va / (sep["das"] * 1e-3) / 1e9, 2) if sep else None,
         "dmas_gvas": round(va / (sep["dmas"] * 1e-3) / 1e9, 2) if sep else None,
+        "lds_read_peak": lds,
         "hierarchical": {
-            "walk_scans_per_s": round(2 * B / (med["walk"] * 1e-3), 1),
-            "walk_scans_per_s_hip_graph": round(2 * B / (walk_graph_ms * 1e-3), 1),
-            "full_dmas_scans_per_s": round(B / ((dmas_ms + med["arg"] / 2) * 1e-3), 1),
+            # one walk per scan: the DMAS walk timed on its own
+            "dmas_walk_scans_per_s": round(B / (walk_alone[1] * 1e-3), 1),
+            "das_walk_scans_per_s": round(B / (walk_alone[0] * 1e-3), 1),
+            "walk_ms": {"dmas": round(walk_alone[1], 5), "das": round(walk_alone[0], 5),
+                        "both_on_two_streams": round(med["walk"], 5),
+                        "both_on_two_streams_hip_graph": round(walk_graph_ms, 5)},
+            # full-resolution DMAS imaging plus its detection, timed on their own
+            "full_dmas_scans_per_s": round(B / ((dmas_ms + arg_alone[1]) * 1e-3), 1),
             "dmas_walk_within_1_voxel_of_full_dmas": loc[1],
             "das_walk_within_1_voxel_of_full_dmas": loc[0],
             "full_das_within_1_voxel_of_full_dmas": das_vs_dmas,
+            # reported only when the walk's localisation matches full DMAS on every scan of the batch
+            "dmas_walk_speedup_vs_full_dmas_at_equal_error":
+                round((dmas_ms + arg_alone[1]) / walk_alone[1], 2) if loc[1] >= 1.0 else None,
             "voxels_per_walk": hier_vox,
             "voxel_ratio_full_over_walk": round(nx * ny / hier_vox, 1),
         },
         "input_generation_s": round(gen_s, 2),
     }
+    if not args.no_c1:
+        out["c1_latency"] = c1_block(uwb, synth, dev)
+    if not args.no_c3:
+        out["c3"] = c3_block(args, uwb, synth, dev)
 
     if not args.no_c5:
         out["learned"] = learned_block(args, uwb, synth, dev)
@@ -309,8 +348,126 @@ def main():
         out["cpu_baseline"] = {"value": round(vox_done / el / 1e9, 4), "unit": "Gvoxel·antenna/s",
                                "cores": int(used), "kind": "oracle",
                                "sample": f"{n_done} full 512x512 scans, DAS + direct-pairwise DMAS, FP64, "
-                                         f"{el:.1f} s"}
+                                         f"{el:.1f} s",
+                               "build": "gcc " + " ".join(oracle.build_flags()) +
+                                        " (plain C, one focal point at a time, OpenMP over focal points)"}
     print(json.dumps(out), flush=True)
+
+
+def lds_peak(uwb):
+    """LDS read bandwidth of the device (16-byte reads, conflict-free, 20 workgroups per CU), and the same in bytes
+    per clock per CU at the shader clock measured during the loop."""
+    bps, hz = max(uwb.probe_lds_read(16, 4096, 256 * 20) for _ in range(3))
+    return {"bytes_per_s": bps, "tb_per_s": round(bps / 1e12, 2), "clock_ghz": round(hz / 1e9, 3),
+            "bytes_per_clk_per_cu": round(bps / (hz * 256), 1) if hz > 0 else None,
+            "probe": "ds_read_b128 stream, 256 lanes x 20 workgroups per CU, 4096 reads per lane"}
+
+
+def _event_ms(fn, reps=50):
+    """Median over reps of one call bracketed by HIP events on the current stream."""
+    import numpy as np
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def c1_block(uwb, synth, dev):
+    """2D single scan (16-antenna ring, 1024 samples, 128 x 128, window 11): too small to fill the device, so
+    reported as the latency of one call (median of 50, HIP events)."""
+    s = synth.c1_scan(0)
+    ds = uwb.DeviceScan.from_host(s, dev)
+    g = s.grid
+    nx, ny, nz = g.dims
+    va = nx * ny * nz * s.n_ant
+    das, dmas = uwb.das_dmas(ds, g)
+    pk = uwb.argmax_async(ds, g, dmas, 1)
+    lat = {"das_ms": _event_ms(lambda: uwb.image(ds, g, 0, out=das)),
+           "dmas_ms": _event_ms(lambda: uwb.image(ds, g, 1, out=dmas)),
+           "das_dmas_one_launch_ms": _event_ms(lambda: uwb.das_dmas(ds, g, out_das=das, out_dmas=dmas)),
+           "argmax_ms": _event_ms(lambda: uwb.argmax_async(ds, g, dmas, 1, out=pk)),
+           "dmas_image_and_detection_ms": _event_ms(lambda: (uwb.image(ds, g, 1, out=dmas),
+                                                             uwb.argmax_async(ds, g, dmas, 1, out=pk)))}
+    out = {k: round(v, 5) for k, v in lat.items()}
+    out.update({"workload": "2D monostatic ring, 16 antennas x 1024 samples, 128x128 grid, window 11, one scan",
+                "voxel_antenna": va, "dmas_gvas_at_this_latency": round(va / (lat["dmas_ms"] * 1e-3) / 1e9, 2)})
+    return out
+
+
+def c3_block(args, uwb, synth, dev):
+    """3D: 64 antennas on a hemisphere (Fibonacci), 4096 samples, eps_r uniform in 8-10 per scan, 1000 clutter
+    scatterers, 20 dB, 256^3 voxels.  Full-resolution DAS / DMAS throughput on one scan per launch, then octree
+    walks (g = 8 and 16) on a batch of distinct scans against the full-resolution DMAS detection."""
+    import ctypes
+    import numpy as np
+    import torch
+    n = args.c3_scans
+    scans = [synth.c3_scan(k) for k in range(n)]
+    g = scans[0].grid
+    nx, ny, nz = g.dims
+    M = scans[0].n_ant
+    va = nx * ny * nz * M
+    ds = uwb.DeviceScan.from_host(scans[0], dev)
+    das = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
+    dmas = torch.empty_like(das)
+    t = {"das_ms": _event_ms(lambda: uwb.image(ds, g, 0, out=das), reps=11),
+         "dmas_ms": _event_ms(lambda: uwb.image(ds, g, 1, out=dmas), reps=11),
+         "das_dmas_one_launch_ms": _event_ms(lambda: uwb.das_dmas(ds, g, out_das=das, out_dmas=dmas), reps=11),
+         "argmax_dmas_ms": _event_ms(lambda: uwb.argmax_async(ds, g, dmas, 1), reps=11)}
+    del das
+    # full-resolution DMAS detection of every scan (the reference of the walks' localisation error)
+    full = []
+    for s in scans:
+        d = uwb.DeviceScan.from_host(s, dev)
+        uwb.image(d, g, 1, out=dmas)
+        full.append(uwb.argmax(d, g, dmas, 1).index)
+        del d
+    del dmas
+    torch.cuda.empty_cache()
+    b = uwb.DeviceBatch.from_host(scans, dev)
+    bc = b.c()
+
+    def within1(a, c):
+        ia = np.array([a % nx, (a // nx) % ny, a // (nx * ny)])
+        ic = np.array([c % nx, (c // nx) % ny, c // (nx * ny)])
+        return bool(np.max(np.abs(ia - ic)) <= 1)
+
+    walks = {}
+    full_ms = t["dmas_ms"] + t["argmax_dmas_ms"]
+    for gg in (8, 16):
+        for m in ("max", "mean"):
+            tree = uwb.SegmentTree(beamformer=1, coarse=gg, metric=m, frame_final=0.25)
+            gc, tc = uwb.grid_c(g), tree.c()
+            need = uwb.lib().uwb_segment_workspace_bytes(ctypes.byref(gc), ctypes.byref(tc), n)
+            ws = torch.empty(need, dtype=torch.uint8, device=dev)
+            res_buf = torch.empty(ctypes.sizeof(uwb.UwbSegmentResult) * n, dtype=torch.uint8, device=dev)
+            ms = _event_ms(lambda tree=tree, ws=ws, res_buf=res_buf: uwb.segment_refine_batch_async(
+                b, g, tree, out=res_buf, workspace=ws, bc=bc), reps=11)
+            res = uwb._results(res_buf, n, 8)
+            w1 = float(np.mean([within1(r.argmax, f) for r, f in zip(res, full)]))
+            vox = float(np.mean([r.voxels_evaluated for r in res]))
+            walks[f"g{gg}_{m}"] = {"scans_per_s": round(n / (ms * 1e-3), 1), "ms_per_batch": round(ms, 4),
+                                   "within_1_voxel_of_full_dmas": w1, "voxels_per_walk": vox,
+                                   "voxel_ratio_full_over_walk": round(nx * ny * nz / vox, 1),
+                                   "speedup_vs_full_dmas_at_equal_error":
+                                       round(full_ms * n / ms, 1) if w1 >= 1.0 else None}
+    return {"workload": "3D monostatic hemisphere, 64 antennas x 4096 samples, 256^3 grid, window 11",
+            "voxel_antenna_per_scan": va,
+            **{k: round(v, 4) for k, v in t.items()},
+            "das_gvas": round(va / (t["das_ms"] * 1e-3) / 1e9, 2),
+            "dmas_gvas": round(va / (t["dmas_ms"] * 1e-3) / 1e9, 2),
+            "das_dmas_one_launch_gvas_per_image": round(va / (t["das_dmas_one_launch_ms"] * 1e-3) / 1e9, 2),
+            "dmas_roofline_frac_fp32": round(flops_per_va(1, 11) * va / (t["dmas_ms"] * 1e-3) / PEAK_FP32, 4),
+            "full_dmas_scans_per_s": round(1e3 / full_ms, 1),
+            "walk_scans": n, "octree_walks": walks}
 
 
 def _timed(fn, reps=5):

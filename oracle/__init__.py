@@ -20,7 +20,7 @@ import os
 
 import numpy as np
 
-from .build import LIB_PATH, build  # noqa: F401
+from .build import LIB_PATH, build, build_flags  # noqa: F401
 
 _lib = None
 

@@ -13,6 +13,11 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-march=x86-64-v3", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11"]
 
 
+def build_flags() -> list:
+    """The gcc flags the oracle library is built with (reported beside its timing)."""
+    return list(CFLAGS)
+
+
 def build(verbose: bool = False) -> str:
     tmp = LIB_PATH + ".tmp"
     cmd = ["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"]

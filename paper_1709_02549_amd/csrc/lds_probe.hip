@@ -1,12 +1,18 @@
 // LDS read-bandwidth probe: the on-chip resource that bounds the gather of the
 // imaging kernels (each voxel-antenna reads W + 1 staged samples from LDS).
 //
-// Every workgroup (256 lanes) fills a 64 KiB LDS array, then each lane streams
-// `iters` (a multiple of 8) reads of `width` bytes (ds_read_b32 / _b64 / _b128) at addresses that
-// walk the array with a stride of one read per lane, so a wave's 64 reads fall
-// on consecutive dwords (no bank conflicts) and every read is inside the array.
-// The values are folded into one integer per lane and written out, so no read
-// can be dropped.  The first lane records the shader-clock and the constant
+// Every workgroup (256 lanes) fills a 32 KiB LDS array (N elements of `width`
+// bytes), then each lane streams `iters` (a multiple of 8) reads of `width` bytes
+// (ds_read_b32 / _b64 / _b128).  A step issues eight reads, two groups of four: a
+// group reads elements off + lane + 256 u (u = 0..3), so a wave's 64 reads fall on
+// consecutive elements (no bank conflicts) and the four reads differ by immediate
+// address offsets.  off = (step * stride) & (N/2 - 1) with stride a kernel argument
+// (0 in the launches below): with compile-time addresses the compiler sees that the
+// reads repeat and hoists them out of the loop.  Every index is at most
+// N/2 - 1 + 3*256 + 255 < N, inside the array, whatever the stride.
+// The values are folded into one integer per lane (three-input XORs, about two VALU
+// instructions per 16-byte read, far below the read rate) and written out, so no
+// read can be dropped.  The first lane records the shader-clock and the constant
 // 100 MHz counters around its loop; the host derives the clock from them.
 #include <hip/hip_runtime.h>
 
@@ -20,11 +26,16 @@ namespace {
 
 constexpr int kProbeBytes = 32 * 1024;   // a power of two: five workgroups fit a CU's LDS
 
+__device__ __forceinline__ unsigned fold(unsigned a, unsigned b) { return a ^ b; }
+__device__ __forceinline__ unsigned fold(uint2 a, unsigned b) { return a.x ^ a.y ^ b; }
+__device__ __forceinline__ unsigned fold(uint4 a, unsigned b) { return (a.x ^ a.y ^ a.z) ^ (a.w ^ b); }
+
 template <int WIDTH>
-__global__ __launch_bounds__(kBlock) void k_lds_read(int iters, unsigned *sink, long long *clk) {
+__global__ __launch_bounds__(kBlock) void k_lds_read(int iters, int stride, unsigned *sink, long long *clk) {
     using V = typename std::conditional<WIDTH == 4, unsigned,
               typename std::conditional<WIDTH == 8, uint2, uint4>::type>::type;
     constexpr int N = kProbeBytes / WIDTH;          // elements of the array
+    static_assert(N / 2 - 1 + 3 * kBlock + kBlock - 1 < N, "probe reads must stay inside the array");
     __shared__ V buf[N];
     for (int i = threadIdx.x; i < N; i += kBlock) {
         V v;
@@ -35,17 +46,17 @@ __global__ __launch_bounds__(kBlock) void k_lds_read(int iters, unsigned *sink, 
     __syncthreads();
     const long long c0 = clock64(), r0 = wall_clock64();
     unsigned acc = 0;
-    // eight independent reads in flight per lane per step; the addresses depend on the loop counter only
     for (int it = 0; it < iters; it += 8) {
+        const V *p0 = buf + ((it * stride) & (N / 2 - 1)) + threadIdx.x;
+        const V *p1 = buf + (((it + 4) * stride) & (N / 2 - 1)) + threadIdx.x;
         V v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = buf[(threadIdx.x + (it + u) * kBlock) & (N - 1)];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const unsigned *w = reinterpret_cast<const unsigned *>(&v[u]);
-#pragma unroll
-            for (int k = 0; k < WIDTH / 4; ++k) acc ^= w[k];
+        for (int u = 0; u < 4; ++u) {
+            v[u] = p0[u * kBlock];
+            v[4 + u] = p1[u * kBlock];
         }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fold(v[u], acc);
     }
     __syncthreads();
     const long long c1 = clock64(), r1 = wall_clock64();
@@ -78,9 +89,13 @@ extern "C" int uwb_probe_lds_read(int32_t width, int32_t iters, int32_t n_groups
         rc = UWB_EHIP;
     } else {
         auto launch = [&]() {
-            if (width == 4) hipLaunchKernelGGL(k_lds_read<4>, dim3(n_groups), dim3(kBlock), 0, st, iters, sink, clk);
-            else if (width == 8) hipLaunchKernelGGL(k_lds_read<8>, dim3(n_groups), dim3(kBlock), 0, st, iters, sink, clk);
-            else hipLaunchKernelGGL(k_lds_read<16>, dim3(n_groups), dim3(kBlock), 0, st, iters, sink, clk);
+            const int stride = 0;   // runtime value: the reads cannot be hoisted (every stride stays in bounds)
+            if (width == 4)
+                hipLaunchKernelGGL(k_lds_read<4>, dim3(n_groups), dim3(kBlock), 0, st, iters, stride, sink, clk);
+            else if (width == 8)
+                hipLaunchKernelGGL(k_lds_read<8>, dim3(n_groups), dim3(kBlock), 0, st, iters, stride, sink, clk);
+            else
+                hipLaunchKernelGGL(k_lds_read<16>, dim3(n_groups), dim3(kBlock), 0, st, iters, stride, sink, clk);
         };
         launch();   // warm-up
         hipEventRecord(e0, st);
