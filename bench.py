@@ -53,7 +53,8 @@ PEAK_FP32 = 157.3e12
 # sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
 TRAFFIC = {"source_hash": "0f51eae975962d3e", "batch": 256, "bytes": 579537544,
            "valu_per_va": 58.5}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of that launch
-LDS_PEAK = 128 * 256 * 2.4e9        # B/s: 128 B/clk/CU
+# LDS bytes the DMAS kernel reads per voxel·antenna at W = 11: six 16-byte records of (sample, difference)
+LDS_BYTES_DMAS = 96
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2   # wave64 FP32 VALU instructions/s (two cycles each)
 
 
@@ -283,11 +284,13 @@ def main():
                      "avg_launch_ms": round(med["img"], 5),
                      "hbm_gbs": round(traffic / (med["img"] * 1e-3) / 1e9, 1) if traffic else None,
                      "hbm_frac": round(traffic / (med["img"] * 1e-3) / 8e12, 4) if traffic else None,
-                     # the gather's other on-chip bounds: 48 B of LDS reads per voxel·antenna against the LDS
-                     # read bandwidth measured on this device (and against the 128 B/clk/CU prior), and VALU
+                     # the gather's other on-chip bounds: LDS reads against the LDS read bandwidth measured on
+                     # this device -- the kernel reads W + 1 = 12 samples (48 B) of algorithmic data per
+                     # voxel·antenna, as six 16-byte records of (sample, difference) pairs (96 B) -- and VALU
                      # issue (counted instructions, while the sources match the counters)
-                     "lds_frac": round(va_rate * 48 / lds["bytes_per_s"], 4),
-                     "lds_frac_vs_128B_clk_cu_prior": round(va_rate * 48 / LDS_PEAK, 4),
+                     "lds_bytes_per_voxel_antenna": LDS_BYTES_DMAS,
+                     "lds_frac": round(va_rate * LDS_BYTES_DMAS / lds["bytes_per_s"], 4),
+                     "lds_frac_algorithmic_48B": round(va_rate * 48 / lds["bytes_per_s"], 4),
                      "valu_issue_frac": round(va_rate * TRAFFIC["valu_per_va"] / 64 / VALU_ISSUE_PEAK, 4)
                      if counters_valid else None},
         "value_counts": "each full-resolution voxel·antenna once; one gather feeds both the DAS and the DMAS image",

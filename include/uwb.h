@@ -38,7 +38,26 @@ enum uwb_status {
     UWB_EUNSUPPORTED = -5   /* valid request outside what this build handles */
 };
 
-enum uwb_beamformer { UWB_DAS = 0, UWB_DMAS = 1 };
+enum uwb_beamformer { UWB_DAS = 0, UWB_DMAS = 1, UWB_MVDR = 2 };
+
+/*
+ * UWB_MVDR: the Capon (minimum-variance distortionless-response) beamformer that
+ * Section I names among the data-adaptive methods (minimum output power with a
+ * distortionless response toward the focal point); the paper gives no formula
+ * and leaves better beamformers inside its framework to Section V.  At a focal
+ * point r, with x_i(k) the aligned window sample of channel i at offset
+ * k = -h..h (the same gather as DAS / DMAS) and X = [x_i(k)] (M channels x W):
+ *   R   = (1/W) sum_k x(k) x(k)^T          sample covariance over the W offsets
+ *   R_l = R + delta I,  delta = UWB_MVDR_LOADING * trace(R) / M   (diagonal loading)
+ *   w   = R_l^-1 1 / (1^T R_l^-1 1)         steering vector all ones after alignment
+ *   I(r) = sum_k (w^T x(k))^2,   and I = 0 where trace(R) = 0.
+ * Computed through the W x W system of the Woodbury identity (the same weights
+ * up to rounding): with G = X^T X, b = X^T 1 (the DAS window sums) and
+ * A = G + W delta I, c = A^-1 b gives I = (W delta)^2 |c|^2 / (M - b^T c)^2.
+ * Windows up to UWB_MVDR_MAX_WINDOW samples (the W x W system lives in registers).
+ */
+#define UWB_MVDR_LOADING 3.0
+#define UWB_MVDR_MAX_WINDOW 11
 
 /* Largest supported energy window (samples) and trace length. */
 #define UWB_MAX_WINDOW 31
@@ -127,6 +146,21 @@ int uwb_dmas_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t wi
  * ([n_scans][nz][ny][nx] for the batch forms), caller-owned, not overlapping
  * (else UWB_EINVAL); other arguments and errors as uwb_das / uwb_das_batch.
  */
+/*
+ * Capon / MVDR energy image (UWB_MVDR above): the same gather as uwb_das, the
+ * weights adapted per focal point.  window: odd, 1 <= window <= UWB_MVDR_MAX_WINDOW
+ * (UWB_EUNSUPPORTED beyond).  img: device, the uwb_das layout, written entirely.
+ * FP32 arithmetic (the W x W solve too: its system is normalised, see above).
+ * The _batch form images same-shaped scans as uwb_das_batch; the _multistatic
+ * forms take the M^2 channels of uwb_das_multistatic (M counts channels there).
+ * Detection and the segment walk accept UWB_MVDR as their beamformer.
+ */
+int uwb_mvdr(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img, void *stream);
+int uwb_mvdr_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img, void *stream);
+int uwb_mvdr_multistatic(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img, void *stream);
+int uwb_mvdr_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img,
+                               void *stream);
+
 int uwb_das_dmas(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img_das, float *img_dmas,
                  void *stream);
 int uwb_das_dmas_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img_das,
@@ -219,7 +253,7 @@ typedef enum { UWB_TERM_FIXED_DEPTH = 0, UWB_TERM_WB = 1 } uwb_term;
 typedef enum { UWB_WALK_PER_LEVEL = 0, UWB_WALK_PAPER = 1 } uwb_walk;
 
 typedef struct {
-    int32_t beamformer;     /* UWB_DAS or UWB_DMAS */
+    int32_t beamformer;     /* UWB_DAS, UWB_DMAS or UWB_MVDR (window <= UWB_MVDR_MAX_WINDOW) */
     int32_t walk;           /* uwb_walk */
     int32_t coarse;         /* g, even, 2..64 (PER_LEVEL); g^d <= 4096 */
     int32_t decimation;     /* D >= 1 (PAPER); 0 = automatic from min_tumour */

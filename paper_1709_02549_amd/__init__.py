@@ -14,11 +14,11 @@ import numpy as np
 import torch
 
 from . import _abi
-from ._abi import (METRICS, TERMS, UWB_DAS, UWB_DMAS, UWB_MAX_LEVELS, WALKS, UwbBatchConfig,  # noqa: F401
+from ._abi import (METRICS, TERMS, UWB_DAS, UWB_DMAS, UWB_MVDR, UWB_MAX_LEVELS, WALKS, UwbBatchConfig,  # noqa: F401
                    UwbBatchItem, UwbError, UwbGenRecipe, UwbGrid, UwbPeak, UwbScan, UwbScanBatch, UwbSegmentResult,
                    UwbSegmentTree, check, lib)
 
-__all__ = ["BatchPlan", "CNN", "generate_disc_scans", "learned_refine_batch", "cnn_training_inputs", "DeviceScan", "DeviceBatch", "das", "dmas", "das_dmas", "image", "das_batch", "dmas_batch", "das_dmas_batch", "image_batch",
+__all__ = ["BatchPlan", "CNN", "generate_disc_scans", "learned_refine_batch", "cnn_training_inputs", "DeviceScan", "DeviceBatch", "das", "dmas", "mvdr", "das_dmas", "image", "das_batch", "dmas_batch", "das_dmas_batch", "image_batch",
            "argmax", "argmax_batch", "segment_refine", "segment_refine_batch", "auto_decimation",
            "SegmentTree", "UwbError"]
 
@@ -121,15 +121,25 @@ def _nvox(g) -> int:
     return nx * ny * nz
 
 
+_IMAGE_FN = {UWB_DAS: "uwb_das", UWB_DMAS: "uwb_dmas", UWB_MVDR: "uwb_mvdr"}
+
+
+def _bf(beamformer) -> int:
+    b = int(beamformer)
+    if b not in _IMAGE_FN:
+        raise ValueError(f"beamformer must be 0 (DAS), 1 (DMAS) or 2 (MVDR), not {beamformer}")
+    return b
+
+
 def image(scan: DeviceScan, grid, beamformer: int, window: int = 11, out: torch.Tensor | None = None):
-    """Full-resolution DAS (beamformer 0) or DMAS (1) image [nz, ny, nx] fp32."""
+    """Full-resolution DAS (beamformer 0), DMAS (1) or Capon / MVDR (2) image [nz, ny, nx] fp32."""
     if out is None:
         out = torch.empty(_img_shape(grid), dtype=torch.float32, device=scan.traces.device)
     _need_cuda(out, "out", numel=_nvox(grid))
-    fn = lib().uwb_dmas if beamformer == UWB_DMAS else lib().uwb_das
+    name = _IMAGE_FN[_bf(beamformer)]
     sc, gc = scan.c(), grid_c(grid)
-    check(fn(ctypes.byref(sc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)),
-          "uwb_dmas" if beamformer else "uwb_das")
+    check(getattr(lib(), name)(ctypes.byref(sc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)),
+          name)
     return out
 
 
@@ -155,13 +165,17 @@ def dmas(scan, grid, window=11, out=None):
     return image(scan, grid, UWB_DMAS, window, out)
 
 
+def mvdr(scan, grid, window=11, out=None):
+    return image(scan, grid, UWB_MVDR, window, out)
+
+
 def image_batch(batch: DeviceBatch, grid, beamformer: int, window: int = 11, out=None, bc=None):
     """bc: the batch's descriptor (batch.c()), built once by callers that launch repeatedly or capture the call
     in a graph (building it reads the per-scan parameters back to the host)."""
     if out is None:
         out = torch.empty((batch.n_scans,) + _img_shape(grid), dtype=torch.float32, device=batch.traces.device)
     _need_cuda(out, "out", numel=batch.n_scans * _nvox(grid))
-    fn = lib().uwb_dmas_batch if beamformer == UWB_DMAS else lib().uwb_das_batch
+    fn = getattr(lib(), _IMAGE_FN[_bf(beamformer)] + "_batch")
     bc, gc = (bc if bc is not None else batch.c()), grid_c(grid)
     check(fn(ctypes.byref(bc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)), "image_batch")
     return out
@@ -739,7 +753,7 @@ def image_multistatic(scan: DeviceScan, grid, beamformer: int, window: int = 11,
     if out is None:
         out = torch.empty(_img_shape(grid), dtype=torch.float32, device=scan.traces.device)
     _need_cuda(out, "out", numel=_nvox(grid))
-    fn = lib().uwb_dmas_multistatic if beamformer == UWB_DMAS else lib().uwb_das_multistatic
+    fn = getattr(lib(), _IMAGE_FN[_bf(beamformer)] + "_multistatic")
     sc, gc = _ms_scan_c(scan), grid_c(grid)
     check(fn(ctypes.byref(sc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)), "image_multistatic")
     return out
@@ -766,7 +780,7 @@ def image_multistatic_batch(batch: DeviceBatch, grid, beamformer: int, window: i
     if out is None:
         out = torch.empty((batch.n_scans,) + _img_shape(grid), dtype=torch.float32, device=batch.traces.device)
     _need_cuda(out, "out", numel=batch.n_scans * _nvox(grid))
-    fn = lib().uwb_dmas_multistatic_batch if beamformer == UWB_DMAS else lib().uwb_das_multistatic_batch
+    fn = getattr(lib(), _IMAGE_FN[_bf(beamformer)] + "_multistatic_batch")
     bc = bc if bc is not None else _ms_batch_c(batch)
     gc = grid_c(grid)
     check(fn(ctypes.byref(bc), ctypes.byref(gc), window, out.data_ptr(), _stream(out.device)),

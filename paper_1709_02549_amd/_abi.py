@@ -14,7 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libuwb.so")
 
 UWB_OK, UWB_EINVAL, UWB_ERANGE, UWB_ENOMEM, UWB_EHIP, UWB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-UWB_DAS, UWB_DMAS = 0, 1
+UWB_DAS, UWB_DMAS, UWB_MVDR = 0, 1, 2
+MVDR_LOADING = 3.0        # UWB_MVDR_LOADING
+MVDR_MAX_WINDOW = 11      # UWB_MVDR_MAX_WINDOW
 UWB_MAX_WINDOW = 31
 UWB_MAX_SAMPLES = 65536
 UWB_MAX_LEVELS = 16
@@ -77,6 +79,11 @@ PROTOTYPES = {
     "uwb_dmas": (c_i32, [ctypes.POINTER(UwbScan), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp]),
     "uwb_das_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp]),
     "uwb_dmas_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp]),
+    "uwb_mvdr": (c_i32, [ctypes.POINTER(UwbScan), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp]),
+    "uwb_mvdr_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp]),
+    "uwb_mvdr_multistatic": (c_i32, [ctypes.POINTER(UwbScan), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp]),
+    "uwb_mvdr_multistatic_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_vp,
+                                           c_vp]),
     "uwb_das_dmas": (c_i32, [ctypes.POINTER(UwbScan), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp, c_vp]),
     "uwb_das_dmas_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp, c_vp]),
     "uwb_das_dmas_multistatic_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_vp,

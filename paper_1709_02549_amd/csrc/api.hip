@@ -127,7 +127,8 @@ static int argmax_common(const ScanSet &ss, int n, const uwb_grid *grid, int32_t
     int st = check_grid(grid, &g);
     if (st) return st;
     if ((st = check_window(window))) return st;
-    if (bf != UWB_DAS && bf != UWB_DMAS) return UWB_EINVAL;
+    if (bf != UWB_DAS && bf != UWB_DMAS && bf != UWB_MVDR) return UWB_EINVAL;
+    if (bf == UWB_MVDR && window > UWB_MVDR_MAX_WINDOW) return UWB_EUNSUPPORTED;
     if (!img || !out || !ws) return UWB_EINVAL;
     if (ws_bytes < argmax_ws_bytes(g, n)) return UWB_ERANGE;
     return launch_argmax(bf, ss, n, g, window, img, out, ws, (hipStream_t)stream);
@@ -144,6 +145,7 @@ static int walk_common(const ScanSet &ss, int n, const uwb_grid *finest, int32_t
     int64_t bound = 0;
     size_t need = 0;
     if ((st = plan_walk(g, tree, n, &a, &bound, &need))) return st;
+    if (tree->beamformer == UWB_MVDR && window > UWB_MVDR_MAX_WINDOW) return UWB_EUNSUPPORTED;
     if (!out || !ws) return UWB_EINVAL;
     if (roi_img && roi_capacity < bound) return UWB_ERANGE;
     if (!roi_img && roi_capacity != 0 && roi_capacity < bound) return UWB_ERANGE;
@@ -167,6 +169,7 @@ static int learned_plan(const GridView &g, const uwb_segment_tree *t, int n, Wal
     if (!t) return UWB_EINVAL;
     if (t->walk != UWB_WALK_PER_LEVEL || t->coarse != 32 || g.dims[2] != 1 || t->term != UWB_TERM_FIXED_DEPTH)
         return UWB_EUNSUPPORTED;
+    if (t->beamformer == UWB_MVDR) return UWB_EUNSUPPORTED;   // the learned walk ends in DAS or DMAS
     int st = plan_walk(g, t, n, a, bound, need);
     if (st) return st;
     if (a->depth < 1) return UWB_EUNSUPPORTED;
@@ -190,6 +193,31 @@ int uwb_dmas(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *
     ScanSet ss;
     int st = scan_set(scan, &ss);
     return st ? st : image_common(UWB_DMAS, ss, 1, grid, window, img, stream);
+}
+
+int uwb_mvdr(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img, void *stream) {
+    ScanSet ss;
+    int st = scan_set(scan, &ss);
+    return st ? st : image_common(UWB_MVDR, ss, 1, grid, window, img, stream);
+}
+
+int uwb_mvdr_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img, void *stream) {
+    ScanSet ss;
+    int st = batch_set(scans, &ss);
+    return st ? st : image_common(UWB_MVDR, ss, scans->n_scans, grid, window, img, stream);
+}
+
+int uwb_mvdr_multistatic(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img, void *stream) {
+    ScanSet ss;
+    int st = scan_set_ms(scan, &ss);
+    return st ? st : image_common(UWB_MVDR, ss, 1, grid, window, img, stream);
+}
+
+int uwb_mvdr_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img,
+                               void *stream) {
+    ScanSet ss;
+    int st = batch_set_ms(scans, &ss);
+    return st ? st : image_common(UWB_MVDR, ss, scans->n_scans, grid, window, img, stream);
 }
 
 int uwb_das_dmas(const uwb_scan *scan, const uwb_grid *grid, int32_t window, float *img_das, float *img_dmas,
@@ -319,7 +347,8 @@ int uwb_argmax_batch_noalloc(const uwb_scan_batch *scans, const uwb_grid *grid, 
     GridView g;
     if ((st = check_grid(grid, &g))) return st;
     if ((st = check_window(window))) return st;
-    if (beamformer != UWB_DAS && beamformer != UWB_DMAS) return UWB_EINVAL;
+    if (beamformer != UWB_DAS && beamformer != UWB_DMAS && beamformer != UWB_MVDR) return UWB_EINVAL;
+    if (beamformer == UWB_MVDR && window > UWB_MVDR_MAX_WINDOW) return UWB_EUNSUPPORTED;
     if (!img || !out) return UWB_EINVAL;
     if (argmax_ws_bytes(g, scans->n_scans) > (size_t)UWB_ARGMAX_SCRATCH_BYTES) return UWB_ERANGE;
     void *ws = nullptr;

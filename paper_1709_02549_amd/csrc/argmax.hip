@@ -117,6 +117,7 @@ constexpr int kEvalCap = 512;   // candidates of a chunk listed in LDS for stage
 // LDS and the four wavefronts evaluate them four at a time (each candidate on a whole
 // wavefront, so its value does not depend on which one takes it); a chunk with more
 // candidates than the list holds has every wavefront evaluate its own in turn.
+template <bool MV>
 __global__ __launch_bounds__(kBlock) void k_chunk_eval64(const Args a) {
     __shared__ double wmax[kBlock / 64];
     __shared__ int wcnt[kBlock / 64];
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_eval64(const Args a) {
                 const int64_t vv = c0 + cidx[i];
                 double rx, ry, rz;
                 voxel_pos(a.g, vv, rx, ry, rz);
-                const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, lane, 64);
+                const double e = energy64_bf<MV>(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, lane, 64);
                 best = fmax(best, e);
                 if (lane == 0) cval[i] = e;
             }
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_eval64(const Args a) {
                     double rx, ry, rz;
                     voxel_pos(a.g, vv, rx, ry, rz);
                     const double e =
-                        energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, lane, 64);
+                        energy64_bf<MV>(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, lane, 64);
                     best = fmax(best, e);
                     if (lane == 0) {
                         const int slot = atomicAdd(&lcount, 1);
@@ -214,6 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce64(const Args a) {
 }
 
 // Stage E: lowest index within the FP64 tie band, per chunk.
+template <bool MV>
 __global__ __launch_bounds__(kBlock) void k_chunk_select(const Args a) {
     __shared__ long long wbest[kBlock / 64];
     __shared__ double wval[kBlock / 64];
@@ -244,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_chunk_select(const Args a) {
                     if (vv >= best) continue;     // wave-uniform: indices only grow within a wave
                     double rx, ry, rz;
                     voxel_pos(a.g, vv, rx, ry, rz);
-                    const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, lane, 64);
+                    const double e = energy64_bf<MV>(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, lane, 64);
                     if (e >= thr64) { best = vv; bval = e; }
                 }
             }
@@ -336,9 +338,11 @@ int launch_argmax(int bf, const ScanSet &ss, int n_scans, const GridView &g, int
     const dim3 gc((unsigned)nchunks, (unsigned)n_scans), gs((unsigned)n_scans);
     hipLaunchKernelGGL(k_chunk_max32, gc, dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_reduce32, gs, dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_chunk_eval64, gc, dim3(kBlock), 0, st, a);
+    if (bf == UWB_MVDR) hipLaunchKernelGGL(k_chunk_eval64<true>, gc, dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL(k_chunk_eval64<false>, gc, dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_reduce64, gs, dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_chunk_select, gc, dim3(kBlock), 0, st, a);
+    if (bf == UWB_MVDR) hipLaunchKernelGGL(k_chunk_select<true>, gc, dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL(k_chunk_select<false>, gc, dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_final, gs, dim3(kBlock), 0, st, a);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }

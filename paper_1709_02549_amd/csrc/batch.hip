@@ -230,7 +230,7 @@ int materialise(uwb_batch_plan *p) {
         b.n_tiles = b.tiles_x * b.tiles_y * tiles_z;
         b.rs = staged_samples(b.s, (tx - 1) * it.g.pitch[0], (ty - 1) * it.g.pitch[1], (tz - 1) * it.g.pitch[2],
                               p->window, b.T);
-        const int per_ant = b.rs * 4 + 16;
+        const int per_ant = b.rs * 16 + 16;   // staged records of 4 samples + table entry
         if (per_ant > budget) return UWB_EUNSUPPORTED;
         b.chunk = std::min(std::min(budget / per_ant, kBlock), b.M);
         lds = std::max(lds, (size_t)b.chunk * per_ant);

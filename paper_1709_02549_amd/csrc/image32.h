@@ -11,6 +11,8 @@ constexpr int kLdsBudget = 40 * 1024;   // bytes of staged samples per workgroup
 
 // Every odd window 1..31 is compiled.
 #define UWB_WINDOWS(X) X(1) X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) X(27) X(29) X(31)
+// MVDR: windows up to UWB_MVDR_MAX_WINDOW.
+#define UWB_MVDR_WINDOWS(X) X(1) X(3) X(5) X(7) X(9) X(11)
 
 // Staged samples per channel for a tile spanning (ex, ey, ez) metres: the delay
 // range over any box is at most s * |box diagonal| (triangle inequality; for a
@@ -63,6 +65,59 @@ __device__ __forceinline__ void stage_spans(float *stage, int rs, int nch, const
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u)
             if (dst[u] >= 0) stage[dst[u]] = v[u];
+    }
+}
+
+// Staged samples are read as 16-byte records (one ds_read_b128 each): 16-byte LDS reads stream at
+// about twice the bytes per clock of 4- and 8-byte ones.  Record m of a channel holds either
+//   plain (DIFF = false): (y_m, y_m+1, y_m+2, y_m+3), the window of W + 1 samples from sample n
+//       in records n, n + 4, ... (ceil((W + 1) / 4) reads; three for W = 11), or
+//   DIFF: (y_m, y_m+1 - y_m, y_m+1, y_m+2 - y_m+1), the W taps from n in records n, n + 2, ...
+//       ((W + 1) / 2 reads; six for W = 11), so that each tap's linear interpolation
+//       y + f (y' - y) is one FMA.
+// Every record index read stays inside the channel's staged span: the window start n is at most
+// rs - W - 1, and the last record read starts 4 (N - 1) <= W (plain) or W - 1 (DIFF) samples
+// past it.
+template <int W, bool DIFF> struct Rec {
+    static constexpr int N = DIFF ? (W + 1) / 2 : (W + 1 + 3) / 4;   // records per window
+    static constexpr int STEP = DIFF ? 2 : 4;                        // samples per record step
+    static_assert(STEP * (N - 1) <= W, "record reads past the window");
+};
+
+// Copies the records (see Rec) of samples first(j) + m, m = 0 .. rs-1, of channels
+// j = 0 .. nch-1 (trace j at tr + j * T) to rec[j * rs + m], samples outside [0, T) being zero.
+// The workgroup's NW wavefronts take the channels in turn, a row of 64 records per step
+// (overlapping, coalesced loads per lane); each wavefront issues kStageBatch rows' loads before
+// their LDS writes, so that many loads are in flight instead of one.
+template <bool DIFF, int NW = kBlock / 64, typename First>
+__device__ __forceinline__ void stage_records(float4 *rec, int rs, int nch, const float *tr, int T, First first) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nrow = (rs + 63) >> 6;
+    const int total = (nch > wave ? (nch - wave + NW - 1) / NW : 0) * nrow;   // this wavefront's rows
+    int q = 0, row = 0;   // the batch's first row: channel wave + NW q, records 64 row ..
+    for (int r0 = 0; r0 < total; r0 += kStageBatch) {
+        float4 v[kStageBatch];
+        int dst[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int jj = wave + NW * q, m = 64 * row + lane;
+            dst[u] = -1;
+            v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r0 + u < total && m < rs) {
+                dst[u] = jj * rs + m;
+                const int gidx = first(jj) + m;
+                const float *t = tr + (int64_t)jj * T;
+                float y[4];
+#pragma unroll
+                for (int e = 0; e < (DIFF ? 3 : 4); ++e) y[e] = (gidx + e >= 0 && gidx + e < T) ? t[gidx + e] : 0.f;
+                if (DIFF) v[u] = make_float4(y[0], y[1] - y[0], y[1], y[2] - y[1]);
+                else v[u] = make_float4(y[0], y[1], y[2], y[3]);
+            }
+            if (++row == nrow) { row = 0; ++q; }
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u)
+            if (dst[u] >= 0) rec[dst[u]] = v[u];
     }
 }
 
@@ -125,9 +180,14 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
     constexpr int H = (W - 1) / 2;
     constexpr int TX = TS::X, TY = TS::Y, TZ = TS::Z;
     constexpr int TE = MS ? 2 : 1;                            // table entries per channel
+    // DMAS and MVDR interpolate from difference records (one FMA per tap); DAS, bound by the LDS
+    // reads rather than by arithmetic, from plain ones (half the bytes)
+    constexpr bool DIFF = BF != UWB_DAS;
+    constexpr int NR = Rec<W, DIFF>::N;                       // records read per window
+    constexpr int NY = DIFF ? 2 * NR : 4 * NR;                // floats gathered per window
     const int chunk = j.chunk, rs = j.rs;
     float4 *tab = reinterpret_cast<float4 *>(smem);          // [chunk][TE]
-    float *stage = smem + 4 * TE * chunk;                     // [chunk][rs]
+    float4 *recs = tab + TE * chunk;                          // [chunk][rs] records of 4 samples
     const double sc = MS ? 0.5 * j.s : j.s;                   // samples per metre of each leg
     const int tid = threadIdx.x;
     const int nx = j.g.dims[0], ny = j.g.dims[1], nz = j.g.dims[2];
@@ -174,8 +234,16 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
 #pragma unroll
     for (int v = 0; v < VPL; ++v) { fy[v] = (float)vy[v]; fz[v] = (float)vz[v]; }
 
+    // MVDR: one voxel per lane, whose window sums (acc) and Gram matrix (packed lower triangle) feed
+    // the W x W solve of mvdr_energy
+    constexpr bool MV = BF == UWB_MVDR;
+    static_assert(!MV || VPL == 1, "the MVDR statistics of one voxel fill a lane's registers");
+    constexpr int NG = MV ? W * (W + 1) / 2 : 1;
     float acc[VPL][W];
     float pre[BF == UWB_DMAS ? VPL : 1][BF == UWB_DMAS ? W : 1];
+    float gram[NG];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) gram[q] = 0.f;
 #pragma unroll
     for (int v = 0; v < VPL; ++v)
 #pragma unroll
@@ -230,9 +298,9 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
             for (int leg = 0; leg < TE; ++leg) tab[TE * tid + leg] = e[leg];
         }
         __syncthreads();
-        // stage [lo, lo + rs) of every antenna of the chunk
-        stage_spans(stage, rs, nch, j.tr + (int64_t)a0 * T, T,
-                    [&](int jj) { return jj * rs - H - __float_as_int(tab[TE * jj].w); });
+        // stage the records of [lo, lo + rs) of every antenna of the chunk
+        stage_records<DIFF>(recs, rs, nch, j.tr + (int64_t)a0 * T, T,
+                            [&](int jj) { return jj * rs - H - __float_as_int(tab[TE * jj].w); });
         __syncthreads();
 
         // bistatic: receiver of the chunk's first channel (channels run in order, so a
@@ -246,7 +314,7 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
             // [lof, hif] before the floor (same index; a clamped window lies wholly in the
             // staged zero padding, so its fraction does not matter)
             const int base = __builtin_amdgcn_readfirstlane(__float_as_int(e.w));
-            const float *sb = stage + base;
+            const float4 *sb = recs + base;
             const float lof = (float)(jj * rs - base), hif = lof + (float)(rs - (W + 1));
             // squared distance from the lane's voxels to one leg's antenna: leg_d2 forms the part
             // shared by the lane's voxels, leg_v adds voxel v's own coordinate
@@ -274,7 +342,7 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
             }
             // software-pipelined over the lane's voxels: voxel v + 1's delay and window reads are
             // issued before voxel v's taps, so their LDS latency overlaps arithmetic
-            auto locate = [&](int v, float &f, const float *&p) {
+            auto locate = [&](int v, float &f, const float4 *&p) {
                 if constexpr (W < kExactDelayWindow) {
                     // FP64 delay from the positions themselves (Eq. (1) / Eq. (2)); the window start is
                     // clamped to the same integer bounds as below
@@ -304,31 +372,50 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
                     p = sb + floor_to_int(tau);
                 }
             };
-            float fc, yc[W + 1];
-            {
-                const float *p;
-                locate(0, fc, p);
+            // the window from NR records: plain, y[k] = sample n + k (k <= W); DIFF, y[2k] = sample
+            // n + k and y[2k + 1] = its forward difference (k < W)
+            auto gather = [&](const float4 *p, float *y) {
 #pragma unroll
-                for (int k = 0; k <= W; ++k) yc[k] = p[k];
+                for (int r = 0; r < NR; ++r) {
+                    const float4 q = p[Rec<W, DIFF>::STEP * r];
+                    y[4 * r] = q.x; y[4 * r + 1] = q.y; y[4 * r + 2] = q.z; y[4 * r + 3] = q.w;
+                }
+            };
+            float fc, yc[4 * NR];
+            {
+                const float4 *p;
+                locate(0, fc, p);
+                gather(p, yc);
             }
 #pragma unroll
             for (int v = 0; v < VPL; ++v) {
-                float fn = 0.f, yn[W + 1];
+                float fn = 0.f, yn[4 * NR];
+                static_assert(NY <= 4 * NR, "gathered floats");
                 if (v + 1 < VPL) {
-                    const float *p;
+                    const float4 *p;
                     locate(v + 1, fn, p);
-#pragma unroll
-                    for (int k = 0; k <= W; ++k) yn[k] = p[k];
+                    gather(p, yn);
                 }
                 __builtin_amdgcn_sched_barrier(0);   // keep those reads ahead of this voxel's taps
                 const float f = fc, g = 1.f - fc;
                 if (BF == UWB_DAS) {
 #pragma unroll
                     for (int k = 0; k < W; ++k) acc[v][k] = fmaf(f, yc[k + 1], fmaf(g, yc[k], acc[v][k]));
+                } else if (MV) {
+                    float sv[W];
+#pragma unroll
+                    for (int k = 0; k < W; ++k) {
+                        sv[k] = fmaf(f, yc[2 * k + 1], yc[2 * k]);
+                        acc[v][k] += sv[k];
+                    }
+#pragma unroll
+                    for (int k = 0; k < W; ++k)
+#pragma unroll
+                        for (int l = 0; l <= k; ++l) gram[tri(k, l)] = fmaf(sv[k], sv[l], gram[tri(k, l)]);
                 } else {
 #pragma unroll
                     for (int k = 0; k < W; ++k) {
-                        const float s = fmaf(f, yc[k + 1], g * yc[k]);
+                        const float s = fmaf(f, yc[2 * k + 1], yc[2 * k]);
                         pre[v][k] = fmaf(s, acc[v][k], pre[v][k]);
                         acc[v][k] += s;
                     }
@@ -336,7 +423,7 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
                 if (v + 1 < VPL) {
                     fc = fn;
 #pragma unroll
-                    for (int k = 0; k <= W; ++k) yc[k] = yn[k];
+                    for (int k = 0; k < 4 * NR; ++k) yc[k] = yn[k];
                 }
             }
         }
@@ -348,11 +435,15 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
         float en = 0.f, ed = 0.f;
+        if constexpr (MV) {
+            en = mvdr_energy<float, W>(gram, acc[0], M);
+        } else {
 #pragma unroll
-        for (int k = 0; k < W; ++k) {
-            const float q = (BF == UWB_DMAS) ? pre[v][k] : acc[v][k];
-            en = fmaf(q, q, en);
-            if (BF == UWB_DMAS) ed = fmaf(acc[v][k], acc[v][k], ed);
+            for (int k = 0; k < W; ++k) {
+                const float q = (BF == UWB_DMAS) ? pre[v][k] : acc[v][k];
+                en = fmaf(q, q, en);
+                if (BF == UWB_DMAS) ed = fmaf(acc[v][k], acc[v][k], ed);
+            }
         }
         if (!fits) en = ed = __builtin_nanf("");
         if (live && vx < nx && vy[v] < ny && vz[v] < nz) {

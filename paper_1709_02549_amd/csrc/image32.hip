@@ -1,5 +1,6 @@
 // Full-resolution FP32 DAS / DMAS imaging (Eq. (1) delay, Eq. (3) DAS, the
-// pairwise DMAS of Section II-B) for gfx950.
+// pairwise DMAS of Section II-B) for gfx950, and the Capon / MVDR beamformer
+// named in Section I on the same gather.
 //
 // A workgroup (256 lanes = 4 wave64) owns a tile of voxels; every lane owns
 // VPL voxels.  For a chunk of antennas the workgroup first derives, per
@@ -13,7 +14,9 @@
 //   DAS : S_k += s_k
 //   DMAS: P_k += s_k * A_k ; A_k += s_k   (A_k = sum of earlier antennas), which
 //         regroups sum_{i<j} s_i s_j exactly and keeps the direct sum's error bound.
-// The energy sum_k S_k^2 (or P_k^2) is written once per voxel.  No atomics,
+//   MVDR: S_k += s_k and the Gram matrix G_kl += s_k s_l (one voxel per lane),
+//         solved per voxel through a W x W Cholesky factorisation (mvdr_energy).
+// The energy sum_k S_k^2 (or P_k^2, or the MVDR output energy) is written once per voxel.  No atomics,
 // fixed summation order: results are bitwise reproducible and independent of
 // the tile shape.
 //
@@ -49,9 +52,13 @@ struct Args {
     int chunk;              // antennas staged per pass
 };
 
+// Voxels per lane of a beamformer: MVDR keeps a W x W Gram matrix per voxel, one voxel per lane.
+template <int BF> constexpr int image_vpl() { return BF == UWB_MVDR ? 1 : kImageVpl; }
+
 template <int BF, int W, bool D3, bool MS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_image32(const Args a) {
-    constexpr int VPL = kImageVpl;
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BF == UWB_MVDR ? 2 : 3)))
+void k_image32(const Args a) {
+    constexpr int VPL = image_vpl<BF>();
     extern __shared__ float smem[];
     const int scan = blockIdx.y;
     const ScanConst sc = scan_const(a.ss, scan);
@@ -99,14 +106,25 @@ hipError_t launch_bf(int window, bool d3, dim3 grid, size_t lds, hipStream_t st,
     return hipErrorInvalidValue;
 }
 
+template <>
+hipError_t launch_bf<UWB_MVDR>(int window, bool d3, dim3 grid, size_t lds, hipStream_t st, const Args &a) {
+    switch (window) {
+#define UWB_W(w) case w: return launch_w<UWB_MVDR, w>(d3, grid, lds, st, a);
+        UWB_MVDR_WINDOWS(UWB_W)
+#undef UWB_W
+    }
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
 
 int launch_image32(int bf, const ScanSet &ss, int n_scans, const GridView &g, int window, float *img,
                    hipStream_t stream, float *img_das) {
     if (img_das && bf != UWB_DMAS) return UWB_EINVAL;
+    if (bf == UWB_MVDR && window > UWB_MVDR_MAX_WINDOW) return UWB_EUNSUPPORTED;
     const bool d3 = g.dims[2] > 1;
     int tx, ty, tz;
-    tile_shape(d3, kImageVpl, &tx, &ty, &tz);
+    tile_shape(d3, bf == UWB_MVDR ? image_vpl<UWB_MVDR>() : kImageVpl, &tx, &ty, &tz);
     Args a;
     a.ss = ss;
     a.g = g;
@@ -121,7 +139,7 @@ int launch_image32(int bf, const ScanSet &ss, int n_scans, const GridView &g, in
     const double s_max = 2.0 / (ss.v * ss.dt);
     a.rs = staged_samples(s_max, (tx - 1) * g.pitch[0], (ty - 1) * g.pitch[1], (tz - 1) * g.pitch[2], window,
                           ss.n_samp);
-    const int per_ant = a.rs * 4 + (ss.ms ? 32 : 16);   // staged samples + table entries
+    const int per_ant = a.rs * 16 + (ss.ms ? 32 : 16);   // staged records of 4 samples + table entries
     if (per_ant > kLdsBudget) return UWB_EUNSUPPORTED;
     a.chunk = kLdsBudget / per_ant;
     if (a.chunk > kBlock) a.chunk = kBlock;
@@ -130,8 +148,9 @@ int launch_image32(int bf, const ScanSet &ss, int n_scans, const GridView &g, in
     const int64_t tiles = (int64_t)a.tiles_x * a.tiles_y * tiles_z;
     if (tiles > 0x7fffffff || n_scans > 65535) return UWB_EUNSUPPORTED;
     dim3 grid((unsigned)tiles, (unsigned)n_scans);
-    hipError_t e = bf == UWB_DMAS ? launch_bf<UWB_DMAS>(window, d3, grid, lds, stream, a)
-                                  : launch_bf<UWB_DAS>(window, d3, grid, lds, stream, a);
+    hipError_t e = bf == UWB_DMAS   ? launch_bf<UWB_DMAS>(window, d3, grid, lds, stream, a)
+                   : bf == UWB_MVDR ? launch_bf<UWB_MVDR>(window, d3, grid, lds, stream, a)
+                                    : launch_bf<UWB_DAS>(window, d3, grid, lds, stream, a);
     return e == hipSuccess ? UWB_OK : UWB_EHIP;
 }
 

@@ -179,6 +179,72 @@ __device__ bool stage_box(const Stage &st, int *tmp, const ScanConst &sc, int M,
 }
 
 // ------------------------------------------------------------------------------
+// Capon / MVDR energy of one focal point from its window statistics (header: the
+// beamformer's definition).  gram: the packed lower triangle of G = X^T X,
+// entry (k, l <= k) at k (k + 1) / 2 + l; b: X^T 1; M: channels.  Through the
+// Woodbury identity, R_l^-1 1 = (1/delta) (1 - X c) with c = A^-1 b and
+// A = G + W delta I, so the output samples are y = W delta c / (M - b^T c).  The
+// statistics are first divided by tr = trace(G) = |X|^2 (the energy scales as
+// |X|^2), which leaves A' = G / tr + (loading / M) I, whose eigenvalues lie in
+// [loading / M, 1 + loading / M]: the system is well conditioned at any signal
+// level.  Cholesky A' = L L^T (in place), L z = b / sqrt(tr), L^T c = z; then
+// b^T c = |z|^2 and I = tr (loading / M)^2 |c|^2 / (M - |z|^2)^2.
+// tr = 0 (no signal) gives 0; a non-finite tr gives NaN.
+// ------------------------------------------------------------------------------
+constexpr int tri(int k, int l) { return k * (k + 1) / 2 + l; }
+
+template <typename Real, int W>
+__device__ __forceinline__ Real mvdr_energy(Real (&gram)[W * (W + 1) / 2], const Real (&b)[W], int M) {
+    Real tr = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) tr += gram[tri(k, k)];
+    if (!(tr > Real(0))) return tr == Real(0) ? Real(0) : static_cast<Real>(__builtin_nan(""));
+    const Real inv = Real(1) / tr, load = Real(UWB_MVDR_LOADING) / Real(M);
+#pragma unroll
+    for (int q = 0; q < W * (W + 1) / 2; ++q) gram[q] *= inv;
+#pragma unroll
+    for (int k = 0; k < W; ++k) gram[tri(k, k)] += load;
+    Real rd[W];   // 1 / L_jj
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        Real d = gram[tri(j, j)];
+#pragma unroll
+        for (int p = 0; p < j; ++p) d -= gram[tri(j, p)] * gram[tri(j, p)];
+        const Real ljj = sqrt(d);
+        gram[tri(j, j)] = ljj;
+        rd[j] = Real(1) / ljj;
+#pragma unroll
+        for (int i = j + 1; i < W; ++i) {
+            Real t = gram[tri(i, j)];
+#pragma unroll
+            for (int p = 0; p < j; ++p) t -= gram[tri(i, p)] * gram[tri(j, p)];
+            gram[tri(i, j)] = t * rd[j];
+        }
+    }
+    const Real sb = sqrt(inv);
+    Real z[W], zz = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        Real t = b[i] * sb;
+#pragma unroll
+        for (int p = 0; p < i; ++p) t -= gram[tri(i, p)] * z[p];
+        z[i] = t * rd[i];
+        zz += z[i] * z[i];
+    }
+    Real c[W], cc = 0;
+#pragma unroll
+    for (int i = W - 1; i >= 0; --i) {
+        Real t = z[i];
+#pragma unroll
+        for (int p = i + 1; p < W; ++p) t -= gram[tri(p, i)] * c[p];
+        c[i] = t * rd[i];
+        cc += c[i] * c[i];
+    }
+    const Real den = Real(M) - zz;
+    return tr * load * load * cc / (den * den);
+}
+
+// ------------------------------------------------------------------------------
 // FP64 energy of one focal point, evaluated cooperatively by a group of G lanes
 // (G a power of two <= 64, lanes of one group contiguous in the wave).  Lane
 // `gl` of the group takes antennas gl, gl+G, ...  The window is processed in
@@ -280,11 +346,85 @@ __device__ double energy64_group(const ScanConst &sc, int M, int T, int window, 
     return energy;
 }
 
+// The Capon / MVDR energy of one focal point in FP64 by a group of G lanes: every lane
+// accumulates the window sums and the Gram matrix of its channels (gl, gl + G, ...), the
+// group adds them up with a butterfly (each pair of lanes forms the same sums, so every
+// lane ends with identical values), and every lane solves the W x W system.
+template <int W>
+__device__ double energy64_mvdr(const ScanConst &sc, int M, int T, double rx, double ry, double rz, int gl, int G,
+                                const Stage *st) {
+    constexpr int H = (W - 1) / 2, NG = W * (W + 1) / 2;
+    double gram[NG], b[W];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) gram[q] = 0.0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) b[k] = 0.0;
+    for (int i = gl; i < M; i += G) {
+        const double tau = delay64(sc, i, rx, ry, rz);
+        const double fl = floor(tau);
+        const double f = tau - fl;
+        double y[W + 1];
+        if (st) {
+            // window [n-h, n+h+1] lies inside the staged span by construction; the clamp only
+            // guards non-finite inputs
+            const int l0 = st->lo[i], ln = st->len[i];
+            const double nc = fmin(fmax(fl, (double)(l0 + H)), (double)(l0 + ln - H - 2));
+            const float *p = st->buf + st->off[i] + ((int)nc - l0);
+#pragma unroll
+            for (int k = 0; k <= W; ++k) y[k] = (double)p[k - H];
+        } else {
+            const long long n = (long long)fmin(fmax(fl, -1.0e9), 1.0e9);
+            const float *tr = sc.tr + (int64_t)i * T;
+#pragma unroll
+            for (int k = 0; k <= W; ++k) y[k] = trace64(tr, T, n + k - H);
+        }
+        double sv[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            sv[k] = (1.0 - f) * y[k] + f * y[k + 1];
+            b[k] += sv[k];
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+#pragma unroll
+            for (int l = 0; l <= k; ++l) gram[tri(k, l)] += sv[k] * sv[l];
+    }
+    for (int o = 1; o < G; o <<= 1) {
+#pragma unroll
+        for (int q = 0; q < NG; ++q) gram[q] += __shfl_xor(gram[q], o, 64);
+#pragma unroll
+        for (int k = 0; k < W; ++k) b[k] += __shfl_xor(b[k], o, 64);
+    }
+    return mvdr_energy<double, W>(gram, b, M);
+}
+
+// DAS or DMAS.
 __device__ __forceinline__ double energy64_dispatch(int bf, const ScanConst &sc, int M, int T, int window,
                                                     double rx, double ry, double rz, int gl, int G,
                                                     const Stage *st = nullptr) {
     return bf == UWB_DMAS ? energy64_group<UWB_DMAS>(sc, M, T, window, rx, ry, rz, gl, G, st)
                           : energy64_group<UWB_DAS>(sc, M, T, window, rx, ry, rz, gl, G, st);
+}
+
+// Any beamformer: MV selects the MVDR energy, whose W x W statistics take about 160 more VGPRs than
+// DAS / DMAS, so the kernels that evaluate candidates are instantiated once for MVDR and once for the
+// others, and the DAS / DMAS instantiation keeps its occupancy.
+template <bool MV>
+__device__ __forceinline__ double energy64_bf(int bf, const ScanConst &sc, int M, int T, int window, double rx,
+                                             double ry, double rz, int gl, int G, const Stage *st = nullptr) {
+    if constexpr (MV) {
+        switch (window) {
+            case 1: return energy64_mvdr<1>(sc, M, T, rx, ry, rz, gl, G, st);
+            case 3: return energy64_mvdr<3>(sc, M, T, rx, ry, rz, gl, G, st);
+            case 5: return energy64_mvdr<5>(sc, M, T, rx, ry, rz, gl, G, st);
+            case 7: return energy64_mvdr<7>(sc, M, T, rx, ry, rz, gl, G, st);
+            case 9: return energy64_mvdr<9>(sc, M, T, rx, ry, rz, gl, G, st);
+            case 11: return energy64_mvdr<11>(sc, M, T, rx, ry, rz, gl, G, st);
+        }
+        return __builtin_nan("");   // rejected on the host
+    } else {
+        return energy64_dispatch(bf, sc, M, T, window, rx, ry, rz, gl, G, st);
+    }
 }
 
 }  // namespace uwb

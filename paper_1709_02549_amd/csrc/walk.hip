@@ -418,7 +418,7 @@ static int64_t lattice_in(int lo, int hi, int step) {  // lattice coordinates in
 int plan_walk(const GridView &g, const uwb_segment_tree *t, int n_scans, WalkArgs *a, int64_t *roi_bound,
               size_t *ws_bytes) {
     if (!t) return UWB_EINVAL;
-    if (t->beamformer != UWB_DAS && t->beamformer != UWB_DMAS) return UWB_EINVAL;
+    if (t->beamformer != UWB_DAS && t->beamformer != UWB_DMAS && t->beamformer != UWB_MVDR) return UWB_EINVAL;
     if (t->walk != UWB_WALK_PER_LEVEL && t->walk != UWB_WALK_PAPER) return UWB_EINVAL;
     if (t->metric < UWB_MEAN || t->metric > UWB_EQ5_CLAMPED) return UWB_EINVAL;
     if (t->term != UWB_TERM_FIXED_DEPTH && t->term != UWB_TERM_WB) return UWB_EINVAL;

@@ -14,7 +14,9 @@
 // transmitter distance is kept while consecutive channels share the
 // transmitter), reads the W+1 staged samples around it and accumulates the
 // linearly interpolated window into W FP64 accumulators (Eq. (3) DAS, or the
-// prefix form P_k += s_k S_k, S_k += s_k of the Section II-B pairwise DMAS sum).
+// prefix form P_k += s_k S_k, S_k += s_k of the Section II-B pairwise DMAS sum, or
+// for the Capon / MVDR beamformer the window sums and their W x W Gram matrix,
+// solved per point).
 // Positions are formed exactly as the rest of the walk forms them (origin +
 // index * pitch on the finest grid), channels are taken in order, and every
 // point's energy is written once: the values depend neither on the tiling nor on
@@ -209,6 +211,25 @@ __device__ __forceinline__ void taps64(const float *p, double f, double (&S)[W],
     }
 }
 
+// MVDR: the window sums and the Gram matrix (packed lower triangle) of the same samples.
+template <int W>
+__device__ __forceinline__ void taps64_mvdr(const float *p, double f, double (&S)[W], double (&gram)[W * (W + 1) / 2]) {
+    float y[W + 1];
+#pragma unroll
+    for (int k = 0; k <= W; ++k) y[k] = p[k];
+    const double g = 1.0 - f;
+    double sv[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        sv[k] = fma(f, (double)y[k + 1], g * (double)y[k]);
+        S[k] += sv[k];
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k)
+#pragma unroll
+        for (int l = 0; l <= k; ++l) gram[tri(k, l)] = fma(sv[k], sv[l], gram[tri(k, l)]);
+}
+
 template <int BF, int W, bool MS>
 __device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const Group &G, unsigned char *dsm,
                              int64_t out_offset) {
@@ -236,11 +257,14 @@ __device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const 
     const int chunk = __builtin_amdgcn_readfirstlane(min(a.lds_bytes / (kTabBytes + 4 * rs), min(M, kBlock)));
     float *stage = reinterpret_cast<float *>(dsm + (size_t)kTabBytes * chunk);   // [chunk][rs]
 
-    double S[W], P[BF == UWB_DMAS ? W : 1];
+    constexpr int NG = BF == UWB_MVDR ? W * (W + 1) / 2 : 1;
+    double S[W], P[BF == UWB_DMAS ? W : 1], gram[NG];
 #pragma unroll
     for (int k = 0; k < W; ++k) S[k] = 0.0;
 #pragma unroll
     for (int k = 0; k < (BF == UWB_DMAS ? W : 1); ++k) P[k] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) gram[q] = 0.0;
 
     double dtx = 0.0;   // bistatic: the current transmitter's distance
     for (int a0 = 0; chunk > 0 && a0 < M; a0 += chunk) {
@@ -303,14 +327,19 @@ __device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const 
             // guards non-finite inputs (every span fits by construction)
             const double off = fmin(fmax(fl - H - tab[8 * jj + 6], 0.0), (double)(rs - (W + 1)));
             const float *p = stage + jj * rs + (int)off;
-            taps64<BF, W, 0, W>(p, f, S, P);
+            if constexpr (BF == UWB_MVDR) taps64_mvdr<W>(p, f, S, gram);
+            else taps64<BF, W, 0, W>(p, f, S, P);
         }
     }
     double e = 0.0;
+    if constexpr (BF == UWB_MVDR) {
+        e = mvdr_energy<double, W>(gram, S, M);
+    } else {
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        const double q = BF == UWB_DMAS ? P[k] : S[k];
-        e = fma(q, q, e);
+        for (int k = 0; k < W; ++k) {
+            const double q = BF == UWB_DMAS ? P[k] : S[k];
+            e = fma(q, q, e);
+        }
     }
     if (chunk < 1) e = __builtin_nan("");   // a span longer than the staging space (rejected on the host)
     if (G.valid) {
@@ -367,6 +396,24 @@ int launch_bf(int window, bool d3, dim3 grid, const Grid64Args &a, int rs_max, c
     return UWB_EINVAL;
 }
 
+template <>
+int launch_bf<UWB_MVDR>(int window, bool d3, dim3 grid, const Grid64Args &a, int rs_max, const WalkArgs *w,
+                        int levels, hipStream_t st) {
+    switch (window) {
+#define UWB_W(w_) case w_: return launch_w<UWB_MVDR, w_>(d3, grid, a, rs_max, w, levels, st);
+        UWB_MVDR_WINDOWS(UWB_W)
+#undef UWB_W
+    }
+    return UWB_EUNSUPPORTED;
+}
+
+template <typename... A>
+int launch_any(int bf, int window, A... args) {
+    return bf == UWB_DMAS   ? launch_bf<UWB_DMAS>(window, args...)
+           : bf == UWB_MVDR ? launch_bf<UWB_MVDR>(window, args...)
+                            : launch_bf<UWB_DAS>(window, args...);
+}
+
 // Largest bounding box (lattice steps per axis) of the groups the kernel forms on a
 // cnt[0] x cnt[1] x cnt[2] lattice: a tile, or the bands of 256 consecutive points.
 void group_extent(const int *cnt, bool d3, int64_t ext[3]) {
@@ -407,8 +454,7 @@ int launch_grid64(Grid64Args a, const int *max_cnt, int max_step, int n_scans, h
                                       (double)ext[1] * max_step * a.g.pitch[1],
                                       (double)ext[2] * max_step * a.g.pitch[2], a.window, a.ss.n_samp);
     const dim3 grid((unsigned)wgs, (unsigned)n_scans);
-    return a.bf == UWB_DMAS ? launch_bf<UWB_DMAS>(a.window, d3, grid, a, rs_max, nullptr, 0, st)
-                            : launch_bf<UWB_DAS>(a.window, d3, grid, a, rs_max, nullptr, 0, st);
+    return launch_any(a.bf, a.window, d3, grid, a, rs_max, (const WalkArgs *)nullptr, 0, st);
 }
 
 // The per-level walk's levels in one launch (a: the kGridBox arguments of its lattices).
@@ -424,8 +470,7 @@ int launch_pl_fused(Grid64Args a, const WalkArgs &w, int levels, int n_scans, hi
     const int rs_max = staged_samples(s_max, (double)ext[0] * step0 * a.g.pitch[0], (double)ext[1] * step0 * a.g.pitch[1],
                                       (double)ext[2] * step0 * a.g.pitch[2], a.window, a.ss.n_samp);
     const dim3 grid((unsigned)n_scans);
-    return a.bf == UWB_DMAS ? launch_bf<UWB_DMAS>(a.window, d3, grid, a, rs_max, &w, levels, st)
-                            : launch_bf<UWB_DAS>(a.window, d3, grid, a, rs_max, &w, levels, st);
+    return launch_any(a.bf, a.window, d3, grid, a, rs_max, &w, levels, st);
 }
 
 }  // namespace uwb

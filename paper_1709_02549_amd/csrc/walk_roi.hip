@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_roi32(const RoiArgs a) {
         // staging stride and channels per pass for this group (uniform: kept in scalar registers)
         j.rs = __builtin_amdgcn_readfirstlane(staged_samples(sc.s, (x1 - x0) * a.g.pitch[0], (y1 - y0) * a.g.pitch[1],
                                                              (z1 - z0) * a.g.pitch[2], W, a.ss.n_samp));
-        j.chunk = __builtin_amdgcn_readfirstlane(min(a.lds_bytes / (j.rs * 4 + (MS ? 32 : 16)), min(j.M, kBlock)));
+        j.chunk = __builtin_amdgcn_readfirstlane(min(a.lds_bytes / (j.rs * 16 + (MS ? 32 : 16)), min(j.M, kBlock)));
         if (j.chunk < 1) continue;   // never: the host sizes the LDS for the widest group
         if (tiled) image_tile<BF, W, D3, 1, MS, false>(j, smem);
         else image_tile<BF, W, D3, 1, MS, true>(j, smem);
@@ -109,6 +109,7 @@ __device__ __forceinline__ void roi_pos(const RoiArgs &a, const int *roi, int rn
 // The winner among a ROI's FP32 candidates, on one wavefront: candidates evaluated in
 // index order, lane l remembering the l-th, so the tie band needs no second evaluation
 // unless there are more than 64.  Every lane returns the same (index, value).
+template <bool MV>
 __device__ void pick_serial(const RoiArgs &a, const ScanConst &sc, const int *roi, int rnx, int rny, int64_t n,
                             const float *v, float thr32, int lane, long long &b, double &pv) {
     const int M = a.ss.n_ant, T = a.ss.n_samp;
@@ -125,7 +126,7 @@ __device__ void pick_serial(const RoiArgs &a, const ScanConst &sc, const int *ro
             const int64_t pp = p0 + l;
             double rx, ry, rz;
             roi_pos(a, roi, rnx, rny, pp, rx, ry, rz);
-            const double e = energy64_dispatch(a.bf, sc, M, T, a.window, rx, ry, rz, lane, 64);   // on every lane
+            const double e = energy64_bf<MV>(a.bf, sc, M, T, a.window, rx, ry, rz, lane, 64);   // on every lane
             best = fmax(best, e);
             if (lane == count) { my_idx = pp; my_val = e; }
             ++count;
@@ -149,7 +150,7 @@ __device__ void pick_serial(const RoiArgs &a, const ScanConst &sc, const int *ro
                 const int64_t pp = p0 + l;
                 double rx, ry, rz;
                 roi_pos(a, roi, rnx, rny, pp, rx, ry, rz);
-                const double e = energy64_dispatch(a.bf, sc, M, T, a.window, rx, ry, rz, lane, 64);
+                const double e = energy64_bf<MV>(a.bf, sc, M, T, a.window, rx, ry, rz, lane, 64);
                 if (e >= thr64) { b = pp; pv = e; break; }
             }
         }
@@ -163,6 +164,7 @@ constexpr int kPickCap = 512;   // candidates listed in LDS per scan
 // whole wavefront, channels over the lanes, so a candidate's FP64 value does not depend
 // on which wavefront takes it); the winner is the lowest listed candidate within the tie
 // band.  More candidates than the list holds (a flat image) go to the serial pick.
+template <bool MV>
 __global__ __launch_bounds__(kBlock) void k_roi_pick(const RoiArgs a) {
     __shared__ int cand[kPickCap];
     __shared__ double cval[kPickCap];
@@ -211,12 +213,12 @@ __global__ __launch_bounds__(kBlock) void k_roi_pick(const RoiArgs a) {
     long long b = LLONG_MAX;
     double pv = __builtin_nan("");
     if (count > kPickCap || n > INT_MAX) {   // uniform over the workgroup
-        if (wave == 0) pick_serial(a, sc, roi, rnx, rny, n, v, thr32, lane, b, pv);
+        if (wave == 0) pick_serial<MV>(a, sc, roi, rnx, rny, n, v, thr32, lane, b, pv);
     } else {
         for (int c = wave; c < count; c += kRoiWaves) {   // uniform per wavefront
             double rx, ry, rz;
             roi_pos(a, roi, rnx, rny, cand[c], rx, ry, rz);
-            const double e = energy64_dispatch(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, lane, 64);
+            const double e = energy64_bf<MV>(a.bf, sc, a.ss.n_ant, a.ss.n_samp, a.window, rx, ry, rz, lane, 64);
             if (lane == 0) cval[c] = e;
         }
         __syncthreads();
@@ -269,6 +271,16 @@ bool launch_bf(int window, bool d3, dim3 grid, size_t lds, hipStream_t st, const
     return false;
 }
 
+template <>
+bool launch_bf<UWB_MVDR>(int window, bool d3, dim3 grid, size_t lds, hipStream_t st, const RoiArgs &a) {
+    switch (window) {
+#define UWB_W(w) case w: launch_w<UWB_MVDR, w>(d3, grid, lds, st, a); return true;
+        UWB_MVDR_WINDOWS(UWB_W)
+#undef UWB_W
+    }
+    return false;
+}
+
 }  // namespace
 
 int launch_roi(const WalkArgs &w, int bf, int n_scans, hipStream_t st) {
@@ -291,16 +303,18 @@ int launch_roi(const WalkArgs &w, int bf, int n_scans, hipStream_t st) {
     const double s_max = 2.0 / (w.ss.v * w.ss.dt);
     const int rs_max = staged_samples(s_max, (w.roi_side[0] - 1) * w.g.pitch[0], (w.roi_side[1] - 1) * w.g.pitch[1],
                                       (w.roi_side[2] - 1) * w.g.pitch[2], w.window, w.ss.n_samp);
-    const int per_ch = rs_max * 4 + (w.ss.ms ? 32 : 16);   // staged samples + table entries
+    const int per_ch = rs_max * 16 + (w.ss.ms ? 32 : 16);   // staged records of 4 samples + table entries
     if (per_ch > kLdsBudget) return UWB_EUNSUPPORTED;
     a.lds_bytes = (int)std::min<int64_t>((int64_t)per_ch * std::min(w.ss.n_ant, kBlock), kLdsBudget);
     const size_t lds = (size_t)a.lds_bytes;
     const dim3 grid((unsigned)n_scans, (unsigned)(bands < 65535 ? bands : 65535));
-    const bool ok = bf == UWB_DMAS ? launch_bf<UWB_DMAS>(w.window, d3, grid, lds, st, a)
-                                   : launch_bf<UWB_DAS>(w.window, d3, grid, lds, st, a);
+    const bool ok = bf == UWB_DMAS   ? launch_bf<UWB_DMAS>(w.window, d3, grid, lds, st, a)
+                    : bf == UWB_MVDR ? launch_bf<UWB_MVDR>(w.window, d3, grid, lds, st, a)
+                                     : launch_bf<UWB_DAS>(w.window, d3, grid, lds, st, a);
     if (!ok) return UWB_EINVAL;
     if (hipGetLastError() != hipSuccess) return UWB_EHIP;
-    hipLaunchKernelGGL(k_roi_pick, dim3((unsigned)n_scans), dim3(kBlock), 0, st, a);
+    if (bf == UWB_MVDR) hipLaunchKernelGGL(k_roi_pick<true>, dim3((unsigned)n_scans), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL(k_roi_pick<false>, dim3((unsigned)n_scans), dim3(kBlock), 0, st, a);
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;
 }
 

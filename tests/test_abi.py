@@ -145,7 +145,7 @@ def test_argmax_argument_errors():
     need = L.uwb_argmax_workspace_bytes(ctypes.byref(g), 1)
     assert need > 0
     s = _scan()
-    assert L.uwb_argmax(ctypes.byref(s), ctypes.byref(g), 11, 2, FAKE, FAKE, FAKE, need, None) == a.UWB_EINVAL
+    assert L.uwb_argmax(ctypes.byref(s), ctypes.byref(g), 11, 3, FAKE, FAKE, FAKE, need, None) == a.UWB_EINVAL
     assert L.uwb_argmax(ctypes.byref(s), ctypes.byref(g), 11, 0, None, FAKE, FAKE, need, None) == a.UWB_EINVAL
     assert L.uwb_argmax(ctypes.byref(s), ctypes.byref(g), 11, 0, FAKE, FAKE, FAKE, need - 1, None) == a.UWB_ERANGE
     assert L.uwb_argmax_workspace_bytes(None, 1) == 0
@@ -167,7 +167,7 @@ def test_argmax_noalloc_limit_and_errors():
                          dt_min=2e-11)
     assert L.uwb_argmax_workspace_bytes(ctypes.byref(g512), 512) > limit
     assert f(ctypes.byref(big), ctypes.byref(g512), 11, 1, FAKE, FAKE, None) == a.UWB_ERANGE
-    assert f(ctypes.byref(ok), ctypes.byref(g512), 11, 2, FAKE, FAKE, None) == a.UWB_EINVAL
+    assert f(ctypes.byref(ok), ctypes.byref(g512), 11, 3, FAKE, FAKE, None) == a.UWB_EINVAL
     assert f(ctypes.byref(ok), ctypes.byref(g512), 11, 1, None, FAKE, None) == a.UWB_EINVAL
     assert f(ctypes.byref(ok), ctypes.byref(g512), 11, 1, FAKE, None, None) == a.UWB_EINVAL
     assert f(ctypes.byref(ok), ctypes.byref(g512), 4, 1, FAKE, FAKE, None) == a.UWB_EINVAL
@@ -221,6 +221,40 @@ def test_segment_sizes_and_errors():
                                 None) == a.UWB_ERANGE
     assert L.uwb_segment_refine(ctypes.byref(s), ctypes.byref(g512), 11, None, FAKE, FAKE, cap, FAKE, ws,
                                 None) == E
+
+
+def test_mvdr_argument_errors():
+    """MVDR windows beyond UWB_MVDR_MAX_WINDOW are refused by the images, the detection and the walk before
+    anything is launched; the batch plan and the learned walk do not take MVDR; beamformer 3 does not exist."""
+    a = _abi()
+    L = a.lib()
+    g = _grid()
+    s = ctypes.byref(_scan())
+    U, E = a.UWB_EUNSUPPORTED, a.UWB_EINVAL
+    assert a.UWB_MVDR == 2
+    for fn in ("uwb_mvdr", "uwb_mvdr_multistatic"):
+        assert getattr(L, fn)(s, ctypes.byref(g), 13, FAKE, None) == U
+        assert getattr(L, fn)(s, ctypes.byref(g), 12, FAKE, None) == E
+        assert getattr(L, fn)(s, ctypes.byref(g), 11, None, None) == E
+    bb = a.UwbScanBatch(n_scans=2, n_ant=4, n_samp=64, ant_pos=FAKE, traces=FAKE, params=FAKE, v_min=1e8,
+                        dt_min=2e-11)
+    for fn in ("uwb_mvdr_batch", "uwb_mvdr_multistatic_batch"):
+        assert getattr(L, fn)(ctypes.byref(bb), ctypes.byref(g), 13, FAKE, None) == U
+    need = L.uwb_argmax_workspace_bytes(ctypes.byref(g), 1)
+    assert L.uwb_argmax(s, ctypes.byref(g), 13, 2, FAKE, FAKE, FAKE, need, None) == U
+    assert L.uwb_argmax(s, ctypes.byref(g), 11, 3, FAKE, FAKE, FAKE, need, None) == E
+    g512 = _grid(dims=(512, 512, 1), pitch=(0.1 / 512,) * 3)
+    t = _tree(beamformer=2)
+    ws = L.uwb_segment_workspace_bytes(ctypes.byref(g512), ctypes.byref(t), 1)
+    cap = L.uwb_segment_roi_capacity(ctypes.byref(g512), ctypes.byref(t))
+    assert ws > 0 and cap > 0
+    assert L.uwb_segment_refine(s, ctypes.byref(g512), 13, ctypes.byref(t), FAKE, FAKE, cap, FAKE, ws, None) == U
+    assert L.uwb_segment_roi_capacity(ctypes.byref(g512), ctypes.byref(_tree(beamformer=3))) == E
+    lt = _tree(beamformer=2, coarse=32)
+    assert L.uwb_learned_workspace_bytes(ctypes.byref(g512), ctypes.byref(lt), 1) == 0
+    plan = ctypes.c_void_p()
+    item = a.UwbBatchItem()
+    assert L.uwb_batch_plan_create(ctypes.byref(plan), ctypes.byref(item), 1, 2, 11, None) == E
 
 
 def test_paper_walk_roi_bound_covers_oracle_walks():
