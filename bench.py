@@ -120,9 +120,14 @@ def main():
     img_dmas = torch.empty_like(img_das)
     pk_das = torch.empty(24 * B, dtype=torch.uint8, device=dev)
     pk_dmas = torch.empty_like(pk_das)
+    # the imaging launch writes every tile's maximum of both images; the detections read those instead of
+    # making a pass of their own over the images
+    n_tiles = uwb.image_tiles(grid)
+    tm_das = torch.empty((B, n_tiles), dtype=torch.float32, device=dev)
+    tm_dmas = torch.empty_like(tm_das)
     trees = {bf: uwb.SegmentTree(beamformer=bf, coarse=args.coarse, metric="max", frame_final=0.25) for bf in (0, 1)}
     walk_out = {}
-    ws_argmax = {bf: torch.empty(int(uwb.lib().uwb_argmax_workspace_bytes(
+    ws_argmax = {bf: torch.empty(int(uwb.lib().uwb_argmax_tilemax_workspace_bytes(
         __import__("ctypes").byref(uwb.grid_c(grid)), B)), dtype=torch.uint8, device=dev) for bf in (0, 1)}
     # the DAS and DMAS detections, and the two walks, are independent and latency-bound: each pair runs
     # on two streams (default priority), the DMAS one on `side`, forked from and joined to the main stream
@@ -143,16 +148,17 @@ def main():
         def mark(k, i):
             if record:
                 ev[k][i].record()
-        # both full-resolution images from one launch: the DMAS kernel's running sums are the DAS sums
+        # both full-resolution images from one launch (the DMAS kernel's running sums are the DAS sums),
+        # with every tile's maximum of each
         mark("img", 0)
-        uwb.das_dmas_batch(batch, grid, W, img_das, img_dmas, bc=bc)
+        uwb.das_dmas_batch_tilemax(batch, grid, W, img_das, img_dmas, tm_das, tm_dmas, bc=bc)
         mark("img", 1)
         main = torch.cuda.current_stream(dev)
         mark("arg", 0)
         side.wait_stream(main)
         with torch.cuda.stream(side):
-            uwb.argmax_batch_async(batch, grid, img_dmas, 1, W, pk_dmas, ws_argmax[1], bc=bc)
-        uwb.argmax_batch_async(batch, grid, img_das, 0, W, pk_das, ws_argmax[0], bc=bc)
+            uwb.argmax_batch_tilemax_async(batch, grid, img_dmas, tm_dmas, 1, W, pk_dmas, ws_argmax[1], bc=bc)
+        uwb.argmax_batch_tilemax_async(batch, grid, img_das, tm_das, 0, W, pk_das, ws_argmax[0], bc=bc)
         main.wait_stream(side)
         mark("arg", 1)
         mark("walk", 0)
@@ -214,9 +220,11 @@ def main():
         uwb.segment_refine_batch_async(batch, grid, trees[bf], W, out=out, workspace=ws, bc=bc)
 
     walk_alone = {bf: launch_ms(lambda bf=bf: walk_once(bf), reps=21) for bf in (0, 1)}
-    arg_alone = {bf: launch_ms(lambda bf=bf: uwb.argmax_batch_async(
-        batch, grid, img_dmas if bf else img_das, bf, W, pk_dmas if bf else pk_das, ws_argmax[bf], bc=bc), reps=21)
-        for bf in (0, 1)}
+    arg_alone = {bf: launch_ms(lambda bf=bf: uwb.argmax_batch_tilemax_async(
+        batch, grid, img_dmas if bf else img_das, tm_dmas if bf else tm_das, bf, W, pk_dmas if bf else pk_das,
+        ws_argmax[bf], bc=bc), reps=21) for bf in (0, 1)}
+    # the same detection making its own pass over the image (uwb_argmax_batch), for comparison
+    arg_pass = launch_ms(lambda: uwb.argmax_batch_async(batch, grid, img_dmas, 1, W, bc=bc), reps=21)
     # the last launches above leave the step's detections and walk results in place for the accuracy checks
 
     # the two walks of a step are launch-bound at this batch (about a dozen small kernels each): the
@@ -274,8 +282,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "2D monostatic ring, 32 antennas x 2048 samples, 512x512 grid, window 11, "
-                               f"full-res DAS+DMAS (one launch) + argmax + quadtree walks (g={args.coarse}, "
-                               "max metric)",
+                               f"full-res DAS+DMAS (one launch, tile maxima) + FP64-decided detection of each + "
+                               f"quadtree walks (g={args.coarse}, max metric)",
                    "batch_scans": B, "distinct_scans": len(distinct), "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": "k_image32 DMAS writing DAS too (W=11, 2D)",
                      "achieved": round(achieved / 1e12, 3), "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
@@ -295,6 +303,8 @@ def main():
                      if counters_valid else None},
         "value_counts": "each full-resolution voxel·antenna once; one gather feeds both the DAS and the DMAS image",
         "components_ms": {k: round(v, 5) for k, v in med.items()},
+        "detection_ms": {"dmas_from_tile_maxima": round(arg_alone[1], 5), "das_from_tile_maxima": round(arg_alone[0], 5),
+                         "dmas_with_its_own_image_pass": round(arg_pass, 5)},
         "das_dmas_one_launch_gvas_per_image": round(va / (med["img"] * 1e-3) / 1e9, 2),
         "das_dmas_one_launch_gvas_two_image_sum": round(2 * va / (med["img"] * 1e-3) / 1e9, 2),
         "separate_launch_ms": {k: round(v, 5) for k, v in sep.items()},

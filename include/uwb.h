@@ -192,6 +192,36 @@ int uwb_argmax_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t 
                      size_t workspace_bytes, void *stream);
 
 /*
+ * Imaging and detection without a second pass over the images (Section II-A
+ * detection fused with the Eq. (3) / Section II-B images).  The full-resolution
+ * DAS / DMAS launch works in tiles of voxels (16 x 64 in 2D, 8 x 8 x 16 in 3D);
+ * uwb_das_dmas_batch_tilemax is uwb_das_dmas_batch that also writes every
+ * tile's FP32 maximum of each image, and uwb_argmax_batch_tilemax is
+ * uwb_argmax_batch that takes the maxima from those instead of reading the
+ * whole image for them: it reads the image only in the tiles whose maximum
+ * comes within 1e-3 of the scan's.  The uwb_peak records are identical to
+ * uwb_argmax_batch's on the same image (same candidates, same FP64 decision).
+ *   uwb_image_tiles(grid)   tiles per scan (the length of one scan's maxima);
+ *                           negative status for an invalid grid
+ *   tmax_das, tmax_dmas     device [n_scans][uwb_image_tiles(grid)] fp32,
+ *                           caller-owned, overlapping neither each other nor
+ *                           the images (else UWB_EINVAL)
+ *   tmax (detection)        the maxima written for img by the imaging call on
+ *                           the same scans, grid and window; beamformer
+ *                           UWB_DAS or UWB_DMAS only (else UWB_EINVAL)
+ *   workspace               device, >= uwb_argmax_tilemax_workspace_bytes(grid,
+ *                           n_scans) bytes (else UWB_ERANGE)
+ * Other arguments and errors as uwb_das_dmas_batch / uwb_argmax_batch.
+ */
+int64_t uwb_image_tiles(const uwb_grid *grid);
+int uwb_das_dmas_batch_tilemax(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img_das,
+                               float *img_dmas, float *tmax_das, float *tmax_dmas, void *stream);
+size_t uwb_argmax_tilemax_workspace_bytes(const uwb_grid *grid, int32_t n_scans);
+int uwb_argmax_batch_tilemax(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, int32_t beamformer,
+                             const float *img, const float *tmax, uwb_peak *out, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
+/*
  * Allocation-free detection, for callers that cannot allocate device memory
  * while they run: code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc.  The same computation and result as uwb_argmax_batch

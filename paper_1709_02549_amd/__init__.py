@@ -274,6 +274,58 @@ def argmax_batch_async(batch: DeviceBatch, grid, img: torch.Tensor, beamformer: 
     return out
 
 
+def image_tiles(grid) -> int:
+    """Tiles per scan of the full-resolution DAS / DMAS launch (length of one scan's tile maxima)."""
+    gc = grid_c(grid)
+    n = int(lib().uwb_image_tiles(ctypes.byref(gc)))
+    check(min(n, 0), "uwb_image_tiles")
+    return n
+
+
+def das_dmas_batch_tilemax(batch: DeviceBatch, grid, window: int = 11, out_das=None, out_dmas=None, tmax_das=None,
+                           tmax_dmas=None, bc=None):
+    """das_dmas_batch that also writes every tile's FP32 maximum of each image.
+    Returns (das, dmas, tmax_das, tmax_dmas)."""
+    shape = (batch.n_scans,) + _img_shape(grid)
+    dev = batch.traces.device
+    nt = image_tiles(grid)
+    if out_das is None:
+        out_das = torch.empty(shape, dtype=torch.float32, device=dev)
+    if out_dmas is None:
+        out_dmas = torch.empty(shape, dtype=torch.float32, device=dev)
+    if tmax_das is None:
+        tmax_das = torch.empty((batch.n_scans, nt), dtype=torch.float32, device=dev)
+    if tmax_dmas is None:
+        tmax_dmas = torch.empty((batch.n_scans, nt), dtype=torch.float32, device=dev)
+    for t, name, n in ((out_das, "out_das", _nvox(grid)), (out_dmas, "out_dmas", _nvox(grid)),
+                       (tmax_das, "tmax_das", nt), (tmax_dmas, "tmax_dmas", nt)):
+        _need_cuda(t, name, numel=batch.n_scans * n)
+    bc, gc = (bc if bc is not None else batch.c()), grid_c(grid)
+    check(lib().uwb_das_dmas_batch_tilemax(ctypes.byref(bc), ctypes.byref(gc), window, out_das.data_ptr(),
+                                           out_dmas.data_ptr(), tmax_das.data_ptr(), tmax_dmas.data_ptr(),
+                                           _stream(out_das.device)), "uwb_das_dmas_batch_tilemax")
+    return out_das, out_dmas, tmax_das, tmax_dmas
+
+
+def argmax_batch_tilemax_async(batch: DeviceBatch, grid, img: torch.Tensor, tmax: torch.Tensor, beamformer: int,
+                               window: int = 11, out=None, workspace=None, bc=None) -> torch.Tensor:
+    """argmax_batch_async taking the image's tile maxima (das_dmas_batch_tilemax) instead of a pass over it."""
+    gc = grid_c(grid)
+    bc = bc if bc is not None else batch.c()
+    need = lib().uwb_argmax_tilemax_workspace_bytes(ctypes.byref(gc), batch.n_scans)
+    ws = workspace if workspace is not None else _ws.get(need, img.device)
+    if out is None:
+        out = torch.empty(ctypes.sizeof(UwbPeak) * batch.n_scans, dtype=torch.uint8, device=img.device)
+    _need_cuda(img, "img", numel=batch.n_scans * _nvox(grid))
+    _need_cuda(tmax, "tmax", numel=batch.n_scans * image_tiles(grid))
+    _need_bytes(out, "out", ctypes.sizeof(UwbPeak) * batch.n_scans)
+    _need_bytes(ws, "workspace", need)
+    check(lib().uwb_argmax_batch_tilemax(ctypes.byref(bc), ctypes.byref(gc), window, beamformer, img.data_ptr(),
+                                         tmax.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                         _stream(img.device)), "uwb_argmax_batch_tilemax")
+    return out
+
+
 ARGMAX_SCRATCH_BYTES = 4 << 20   # UWB_ARGMAX_SCRATCH_BYTES: the allocation-free detection's scratch limit
 
 

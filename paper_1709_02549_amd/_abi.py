@@ -108,6 +108,12 @@ PROTOTYPES = {
                            ctypes.c_size_t, c_vp]),
     "uwb_argmax_batch": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_i32, c_vp, c_vp,
                                  c_vp, ctypes.c_size_t, c_vp]),
+    "uwb_image_tiles": (c_i64, [ctypes.POINTER(UwbGrid)]),
+    "uwb_das_dmas_batch_tilemax": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_vp, c_vp,
+                                           c_vp, c_vp, c_vp]),
+    "uwb_argmax_tilemax_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(UwbGrid), c_i32]),
+    "uwb_argmax_batch_tilemax": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_i32, c_vp,
+                                         c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
     "uwb_argmax_batch_noalloc": (c_i32, [ctypes.POINTER(UwbScanBatch), ctypes.POINTER(UwbGrid), c_i32, c_i32,
                                          c_vp, c_vp, c_vp]),
     "uwb_segment_roi_capacity": (c_i64, [ctypes.POINTER(UwbGrid), ctypes.POINTER(UwbSegmentTree)]),

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/uwb.h: argument validation and
 // dispatch to the kernels.  Validation runs before any HIP call, so an invalid
 // request returns its status without touching the device.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -107,22 +108,36 @@ static int image_common(int bf, const ScanSet &ss, int n, const uwb_grid *grid, 
     return launch_image32(bf, ss, n, g, window, img, (hipStream_t)stream);
 }
 
-// Both images from one DMAS launch; the two outputs must not overlap.
+static bool overlap(const void *p, const void *q, uintptr_t bytes) {
+    const uintptr_t a = (uintptr_t)p, b = (uintptr_t)q;
+    return a < b + bytes && b < a + bytes;
+}
+
+// Both images from one DMAS launch; the two outputs must not overlap (nor, when given, the tile maxima).
 static int image_both_common(const ScanSet &ss, int n, const uwb_grid *grid, int32_t window, float *img_das,
-                             float *img_dmas, void *stream) {
+                             float *img_dmas, void *stream, float *tmax_das = nullptr, float *tmax_dmas = nullptr) {
     GridView g;
     int st = check_grid(grid, &g);
     if (st) return st;
     if ((st = check_window(window))) return st;
     if (!img_das || !img_dmas) return UWB_EINVAL;
     const uintptr_t bytes = (uintptr_t)n * (uintptr_t)g.dims[0] * g.dims[1] * g.dims[2] * sizeof(float);
-    const uintptr_t a = (uintptr_t)img_das, b = (uintptr_t)img_dmas;
-    if (a < b + bytes && b < a + bytes) return UWB_EINVAL;
-    return launch_image32(UWB_DMAS, ss, n, g, window, img_dmas, (hipStream_t)stream, img_das);
+    if (overlap(img_das, img_dmas, bytes)) return UWB_EINVAL;
+    if (tmax_das || tmax_dmas) {
+        if (!tmax_das || !tmax_dmas) return UWB_EINVAL;
+        const uintptr_t tb = (uintptr_t)n * (uintptr_t)full_tile_count(g) * sizeof(float);
+        if (overlap(tmax_das, tmax_dmas, tb) || overlap(tmax_das, img_das, std::max(tb, bytes)) ||
+            overlap(tmax_das, img_dmas, std::max(tb, bytes)) || overlap(tmax_dmas, img_das, std::max(tb, bytes)) ||
+            overlap(tmax_dmas, img_dmas, std::max(tb, bytes)))
+            return UWB_EINVAL;
+    }
+    return launch_image32(UWB_DMAS, ss, n, g, window, img_dmas, (hipStream_t)stream, img_das, tmax_dmas, tmax_das);
 }
 
+// tmax (tile mode): the tile maxima of img from uwb_das_dmas_batch_tilemax.
 static int argmax_common(const ScanSet &ss, int n, const uwb_grid *grid, int32_t window, int32_t bf,
-                         const float *img, uwb_peak *out, void *ws, size_t ws_bytes, void *stream) {
+                         const float *img, uwb_peak *out, void *ws, size_t ws_bytes, void *stream,
+                         const float *tmax = nullptr) {
     GridView g;
     int st = check_grid(grid, &g);
     if (st) return st;
@@ -130,8 +145,8 @@ static int argmax_common(const ScanSet &ss, int n, const uwb_grid *grid, int32_t
     if (bf != UWB_DAS && bf != UWB_DMAS && bf != UWB_MVDR) return UWB_EINVAL;
     if (bf == UWB_MVDR && window > UWB_MVDR_MAX_WINDOW) return UWB_EUNSUPPORTED;
     if (!img || !out || !ws) return UWB_EINVAL;
-    if (ws_bytes < argmax_ws_bytes(g, n)) return UWB_ERANGE;
-    return launch_argmax(bf, ss, n, g, window, img, out, ws, (hipStream_t)stream);
+    if (ws_bytes < argmax_ws_bytes(g, n, tmax != nullptr)) return UWB_ERANGE;
+    return launch_argmax(bf, ss, n, g, window, img, out, ws, (hipStream_t)stream, tmax);
 }
 
 static int walk_common(const ScanSet &ss, int n, const uwb_grid *finest, int32_t window,
@@ -232,6 +247,39 @@ int uwb_das_dmas_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_
     ScanSet ss;
     int st = batch_set(scans, &ss);
     return st ? st : image_both_common(ss, scans->n_scans, grid, window, img_das, img_dmas, stream);
+}
+
+int64_t uwb_image_tiles(const uwb_grid *grid) {
+    GridView g;
+    int st = check_grid(grid, &g);
+    return st ? st : full_tile_count(g);
+}
+
+int uwb_das_dmas_batch_tilemax(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, float *img_das,
+                               float *img_dmas, float *tmax_das, float *tmax_dmas, void *stream) {
+    ScanSet ss;
+    int st = batch_set(scans, &ss);
+    if (st) return st;
+    if (!tmax_das || !tmax_dmas) return UWB_EINVAL;
+    return image_both_common(ss, scans->n_scans, grid, window, img_das, img_dmas, stream, tmax_das, tmax_dmas);
+}
+
+size_t uwb_argmax_tilemax_workspace_bytes(const uwb_grid *grid, int32_t n_scans) {
+    GridView g;
+    if (check_grid(grid, &g) || n_scans < 1) return 0;
+    return argmax_ws_bytes(g, n_scans, true);
+}
+
+int uwb_argmax_batch_tilemax(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window, int32_t beamformer,
+                             const float *img, const float *tmax, uwb_peak *out, void *workspace,
+                             size_t workspace_bytes, void *stream) {
+    ScanSet ss;
+    int st = batch_set(scans, &ss);
+    if (st) return st;
+    if (beamformer != UWB_DAS && beamformer != UWB_DMAS) return UWB_EINVAL;
+    if (!tmax) return UWB_EINVAL;
+    return argmax_common(ss, scans->n_scans, grid, window, beamformer, img, out, workspace, workspace_bytes, stream,
+                         tmax);
 }
 
 int uwb_das_dmas_multistatic_batch(const uwb_scan_batch *scans, const uwb_grid *grid, int32_t window,

@@ -135,6 +135,8 @@ struct TileJob {
     int ms;               // multistatic: antennas per side (channel i*ms + j), 0: monostatic
     int64_t p0;           // band form: first voxel (linear, x fastest) of the band
     float *img_das = nullptr;   // DMAS only, optional: the DAS image of the same voxels
+    float *tmax = nullptr;      // optional: the tile's FP32 maximum of img (of img_das: tmax_das)
+    float *tmax_das = nullptr;
 };
 
 // Tile geometry.  2D: 16 (x) by 16*VPL (y); lane (tx, ty) owns y = ty + 16 v.
@@ -264,8 +266,15 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
         __syncthreads();   // previous chunk (or previous tile) fully consumed
         if (tid < nch) {
             const int i = a0 + tid;
-            const double dqx = sc * j.g.pitch[0], dqy = sc * j.g.pitch[1], dqz = sc * j.g.pitch[2];
-            double tmin = -j.t0s;
+            // The box products below are the same in every chunk; hoisted out of the chunk loop they would
+            // stay live (six doubles) across the voxel loop and be spilled to scratch memory, once per lane.
+            // An empty asm statement on copies of the bounds (and of a zero the scale is offset by) keeps them
+            // inside this branch.
+            int b0x = bx0, b1x = bx1, b0y = by0, b1y = by1, b0z = bz0, b1z = bz1, zero = 0;
+            asm volatile("" : "+v"(b0x), "+v"(b1x), "+v"(b0y), "+v"(b1y), "+v"(b0z), "+v"(b1z), "+v"(zero));
+            const double scl = sc + (double)zero, t0s_d = j.t0s + (double)zero;
+            const double dqx = scl * j.g.pitch[0], dqy = scl * j.g.pitch[1], dqz = scl * j.g.pitch[2];
+            double tmin = -t0s_d;
             float4 e[TE];
 #pragma unroll
             for (int leg = 0; leg < TE; ++leg) {
@@ -274,12 +283,12 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
                 const double ay = (double)j.pos[3 * ant + 1];
                 const double az = (double)j.pos[3 * ant + 2];
                 // antenna-relative offsets in sample units: c + idx * q
-                const double cx = sc * (j.g.origin[0] - ax);
-                const double cy = sc * (j.g.origin[1] - ay);
-                const double cz = sc * (j.g.origin[2] - az);
-                const double lx = cx + bx0 * dqx, hx = cx + bx1 * dqx;
-                const double ly = cy + by0 * dqy, hy = cy + by1 * dqy;
-                const double lz = cz + bz0 * dqz, hz = cz + bz1 * dqz;
+                const double cx = scl * (j.g.origin[0] - ax);
+                const double cy = scl * (j.g.origin[1] - ay);
+                const double cz = scl * (j.g.origin[2] - az);
+                const double lx = cx + b0x * dqx, hx = cx + b1x * dqx;
+                const double ly = cy + b0y * dqy, hy = cy + b1y * dqy;
+                const double lz = cz + b0z * dqz, hz = cz + b1z * dqz;
                 // nearest point of the tile's box to the antenna (the antenna is at 0 here)
                 const double mx = fmin(fmax(0.0, lx), hx), my = fmin(fmax(0.0, ly), hy), mz = fmin(fmax(0.0, lz), hz);
                 tmin += sqrt(mx * mx + my * my + mz * mz);
@@ -432,6 +441,7 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
     // the DMAS running sums acc_k = sum of s_k over every antenna are the DAS window sums
     // (Eq. (3)): a DMAS tile writes the DAS image too when asked, at no extra reads
     float *const das = BF == UWB_DMAS ? j.img_das : nullptr;
+    float tm = -INFINITY, tmd = -INFINITY;   // this lane's maxima of its voxels (NaN ignored, as fmaxf does)
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
         float en = 0.f, ed = 0.f;
@@ -450,6 +460,24 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
             const int64_t o = ((int64_t)vz[v] * ny + vy[v]) * nx + vx;
             j.img[o] = en;
             if (das) das[o] = ed;
+            tm = fmaxf(tm, en);
+            tmd = fmaxf(tmd, ed);
+        }
+    }
+    // the tile's maxima, for a detection that reads them instead of the image (uniform branch)
+    if (!MV && j.tmax) {
+        tm = wave_maxf(tm);
+        tmd = wave_maxf(tmd);
+        __syncthreads();   // every wave is done with the staged records: reuse their LDS
+        constexpr int NW = kBlock / 64;
+        float *red = smem;   // [NW] image maxima, then [NW] DAS-image maxima
+        if ((tid & 63) == 0) { red[tid >> 6] = tm; red[NW + (tid >> 6)] = tmd; }
+        __syncthreads();
+        if (tid == 0) {
+            float m = red[0], md = red[NW];
+            for (int w = 1; w < NW; ++w) { m = fmaxf(m, red[w]); md = fmaxf(md, red[NW + w]); }
+            *j.tmax = m;
+            if (j.tmax_das) *j.tmax_das = md;
         }
     }
 }

@@ -41,12 +41,20 @@ namespace {
 // measured a few per cent faster than 2 for DAS and DMAS on the 512 x 512 batch.
 constexpr int kImageVpl = 4;
 
+}  // namespace
+
+void full_tile_shape(bool d3, int *tx, int *ty, int *tz) { tile_shape(d3, kImageVpl, tx, ty, tz); }
+
+namespace {
+
 struct Args {
     ScanSet ss;
     GridView g;
     float *img;
     float *img_das;         // DMAS launch, optional: the DAS images too (same layout)
     int64_t img_stride;     // elements between scans
+    float *tmax, *tmax_das; // optional: each tile's FP32 maximum of img / img_das, [scan][tiles]
+    int tiles;              // tiles per scan
     int tiles_x, tiles_y;   // tiles along x and y (z = rest)
     int rs;                 // staged samples per antenna (stride in LDS)
     int chunk;              // antennas staged per pass
@@ -69,6 +77,9 @@ void k_image32(const Args a) {
     j.tr = sc.tr;
     j.img = a.img + (int64_t)scan * a.img_stride;
     j.img_das = a.img_das ? a.img_das + (int64_t)scan * a.img_stride : nullptr;
+    const int64_t slot = (int64_t)scan * a.tiles + blockIdx.x;
+    j.tmax = a.tmax ? a.tmax + slot : nullptr;
+    j.tmax_das = a.tmax_das ? a.tmax_das + slot : nullptr;
     j.M = a.ss.n_ant;
     j.T = a.ss.n_samp;
     j.s = sc.s;
@@ -119,8 +130,10 @@ hipError_t launch_bf<UWB_MVDR>(int window, bool d3, dim3 grid, size_t lds, hipSt
 }  // namespace
 
 int launch_image32(int bf, const ScanSet &ss, int n_scans, const GridView &g, int window, float *img,
-                   hipStream_t stream, float *img_das) {
+                   hipStream_t stream, float *img_das, float *tmax, float *tmax_das) {
     if (img_das && bf != UWB_DMAS) return UWB_EINVAL;
+    if ((tmax || tmax_das) && bf == UWB_MVDR) return UWB_EINVAL;
+    if (tmax_das && !img_das) return UWB_EINVAL;
     if (bf == UWB_MVDR && window > UWB_MVDR_MAX_WINDOW) return UWB_EUNSUPPORTED;
     const bool d3 = g.dims[2] > 1;
     int tx, ty, tz;
@@ -147,6 +160,9 @@ int launch_image32(int bf, const ScanSet &ss, int n_scans, const GridView &g, in
     const size_t lds = (size_t)a.chunk * per_ant;
     const int64_t tiles = (int64_t)a.tiles_x * a.tiles_y * tiles_z;
     if (tiles > 0x7fffffff || n_scans > 65535) return UWB_EUNSUPPORTED;
+    a.tiles = (int)tiles;
+    a.tmax = tmax;
+    a.tmax_das = tmax_das;
     dim3 grid((unsigned)tiles, (unsigned)n_scans);
     hipError_t e = bf == UWB_DMAS   ? launch_bf<UWB_DMAS>(window, d3, grid, lds, stream, a)
                    : bf == UWB_MVDR ? launch_bf<UWB_MVDR>(window, d3, grid, lds, stream, a)

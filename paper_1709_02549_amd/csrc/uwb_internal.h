@@ -432,11 +432,18 @@ __device__ __forceinline__ double energy64_bf(int bf, const ScanConst &sc, int M
 // Host-side launchers implemented in the .hip files.
 namespace uwb {
 // img_das (DMAS only, optional): the DAS images of the same scans, from the same launch.
+// tmax, tmax_das (DAS / DMAS only, optional): each workgroup tile's FP32 maximum of img (and of img_das),
+// [n_scans][full_tile_count(g)], for the detection's tile mode.
 int launch_image32(int bf, const ScanSet &ss, int n_scans, const GridView &g, int window, float *img,
-                   hipStream_t stream, float *img_das = nullptr);
+                   hipStream_t stream, float *img_das = nullptr, float *tmax = nullptr, float *tmax_das = nullptr);
+// tmax (optional): the FP32 tile maxima the full-resolution DAS / DMAS launch wrote for img; the detection
+// then skips its own pass over the image (tile mode, whose workspace is argmax_ws_bytes(g, n, true)).
 int launch_argmax(int bf, const ScanSet &ss, int n_scans, const GridView &g, int window, const float *img,
-                  uwb_peak *out, void *ws, hipStream_t stream);
-size_t argmax_ws_bytes(const GridView &g, int n_scans);
+                  uwb_peak *out, void *ws, hipStream_t stream, const float *tmax = nullptr);
+size_t argmax_ws_bytes(const GridView &g, int n_scans, bool tiles = false);
+// Tiles per scan of the full-resolution DAS / DMAS launch, and their shape.
+int64_t full_tile_count(const GridView &g);
+void full_tile_shape(bool d3, int *tx, int *ty, int *tz);
 // This device's scratch of the allocation-free detection (UWB_ARGMAX_SCRATCH_BYTES bytes), its address
 // taken once per device; UWB_EHIP if the runtime cannot give it.
 int argmax_scratch(void **ptr);

@@ -223,6 +223,34 @@ def test_segment_sizes_and_errors():
                                 None) == E
 
 
+def test_tilemax_sizes_and_errors():
+    """Tiles per scan of the full-resolution launch (16 x 64 in 2D, 8 x 8 x 16 in 3D) and the argument checks
+    of the tile-maximum imaging and detection, before anything is launched."""
+    a = _abi()
+    L = a.lib()
+    g512 = _grid(dims=(512, 512, 1))
+    assert L.uwb_image_tiles(ctypes.byref(g512)) == 32 * 8
+    assert L.uwb_image_tiles(ctypes.byref(_grid(dims=(256, 256, 256)))) == 32 * 32 * 16
+    assert L.uwb_image_tiles(ctypes.byref(_grid(dims=(100, 76, 1)))) == 7 * 2
+    assert L.uwb_image_tiles(ctypes.byref(_grid(dims=(0, 8, 1)))) == a.UWB_EINVAL
+    E = a.UWB_EINVAL
+    bb = a.UwbScanBatch(n_scans=2, n_ant=4, n_samp=64, ant_pos=FAKE, traces=FAKE, params=FAKE, v_min=1e8,
+                        dt_min=2e-11)
+    g = _grid()   # 8 x 8: one tile; images of 2 x 256 bytes
+    v = ctypes.c_void_p
+    f = L.uwb_das_dmas_batch_tilemax
+    P = 0x10000000
+    assert f(ctypes.byref(bb), ctypes.byref(g), 11, v(P), v(P + 512), None, v(P + 4096), None) == E
+    assert f(ctypes.byref(bb), ctypes.byref(g), 11, v(P), v(P + 512), v(P + 4096), v(P + 4096), None) == E
+    assert f(ctypes.byref(bb), ctypes.byref(g), 11, v(P), v(P + 512), v(P + 256), v(P + 4096), None) == E
+    need = L.uwb_argmax_tilemax_workspace_bytes(ctypes.byref(g), 2)
+    assert need > 0 and L.uwb_argmax_tilemax_workspace_bytes(None, 2) == 0
+    d = L.uwb_argmax_batch_tilemax
+    assert d(ctypes.byref(bb), ctypes.byref(g), 11, 2, FAKE, FAKE, FAKE, FAKE, need, None) == E
+    assert d(ctypes.byref(bb), ctypes.byref(g), 11, 1, FAKE, None, FAKE, FAKE, need, None) == E
+    assert d(ctypes.byref(bb), ctypes.byref(g), 11, 1, FAKE, FAKE, FAKE, FAKE, need - 1, None) == a.UWB_ERANGE
+
+
 def test_mvdr_argument_errors():
     """MVDR windows beyond UWB_MVDR_MAX_WINDOW are refused by the images, the detection and the walk before
     anything is launched; the batch plan and the learned walk do not take MVDR; beamformer 3 does not exist."""

@@ -238,3 +238,62 @@ def test_das_dmas_batch_and_errors():
     u.das_dmas_batch(b, scans[0].grid, out_das=buf[0:4], out_dmas=buf[4:8])   # adjacent is fine
     torch.cuda.synchronize()
     assert torch.equal(buf[4:8], dmas) and torch.equal(buf[0:4], das)
+
+
+# ----------------------------------------------------------------------------------
+# detection from the imaging launch's tile maxima (no second pass over the images)
+# ----------------------------------------------------------------------------------
+
+def _tile_max_reference(img, grid):
+    """Every 16 x 64 (2D) or 8 x 8 x 16 (3D) tile's maximum of img [n][nz][ny][nx], tiles in launch order."""
+    nx, ny, nz = grid.dims
+    tx, ty, tz = (8, 8, 16) if nz > 1 else (16, 64, 1)
+    n = img.shape[0]
+    px, py, pz = -nx % tx, -ny % ty, -nz % tz
+    x = torch.nn.functional.pad(img, (0, px, 0, py, 0, pz), value=float("-inf"))
+    x = x.reshape(n, (nz + pz) // tz, tz, (ny + py) // ty, ty, (nx + px) // tx, tx)
+    return x.amax(dim=(2, 4, 6)).reshape(n, -1)
+
+
+@pytest.mark.parametrize("case", ["c2", "ragged-3d", "ragged-2d"])
+def test_tilemax_detection_equals_argmax(case):
+    """uwb_das_dmas_batch_tilemax writes the same images as uwb_das_dmas_batch plus every tile's maximum; the
+    detection from those maxima returns the uwb_peak records of uwb_argmax_batch byte for byte, which are the
+    oracle's argmax."""
+    u = uwb()
+    if case == "c2":
+        scans = [synth.c2_scan(k) for k in range(6)]
+    elif case == "ragged-3d":
+        scans = [_ragged_scan((19, 21, 11), 20 + k) for k in range(3)]
+    else:
+        scans = [_ragged_scan((100, 76, 1), 30 + k) for k in range(3)]
+    g = scans[0].grid
+    b = u.DeviceBatch.from_host(scans)
+    das, dmas, tdas, tdmas = u.das_dmas_batch_tilemax(b, g)
+    das2, dmas2 = u.das_dmas_batch(b, g)
+    torch.cuda.synchronize()
+    assert torch.equal(das, das2) and torch.equal(dmas, dmas2)
+    assert tdas.shape[1] == u.image_tiles(g)
+    assert torch.equal(tdas, _tile_max_reference(das, g)) and torch.equal(tdmas, _tile_max_reference(dmas, g))
+    for bf, img, tm in ((0, das, tdas), (1, dmas, tdmas)):
+        p_tile = u.argmax_batch_tilemax_async(b, g, img, tm, bf)
+        p_ref = u.argmax_batch_async(b, g, img, bf)
+        torch.cuda.synchronize()
+        assert torch.equal(p_tile, p_ref)
+        for k, s in enumerate(scans[:2]):
+            assert u._peaks(p_tile, len(scans))[k].index == oracle.argmax_grid(oracle.image_grid(s, bf))[0]
+
+
+def test_flat_images_overflow_the_chunk_list():
+    """All-equal energies: every chunk (16 of 4096 voxels) and every tile (64) holds candidates, more than the
+    detection lists per scan, so its candidate passes take every chunk in turn; the lowest index wins."""
+    u = uwb()
+    g = Grid((0.0, 0.0, 0.0), (1e-4, 1e-4, 1e-4), (256, 256, 1))
+    ant = np.array([[-0.1, 0.0, 0.0]], np.float32)
+    s = synth.Scan(ant, np.ones((1, 4096), np.float32), 2e-11, 0.0, 1e8, g)
+    b = u.DeviceBatch.from_host([s, s])
+    das, dmas, tdas, tdmas = u.das_dmas_batch_tilemax(b, g)
+    for p in (u.argmax_batch_async(b, g, das, 0), u.argmax_batch_tilemax_async(b, g, das, tdas, 0)):
+        pk = u._peaks(p, 2)
+        assert [q.index for q in pk] == [0, 0]
+        assert [q.candidates for q in pk] == [256 * 256] * 2
