@@ -51,8 +51,8 @@ PEAK_FP32 = 157.3e12
 # batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a 256 MiB copy); valid only for the kernel
 # sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
-TRAFFIC = {"source_hash": "0f51eae975962d3e", "batch": 256, "bytes": 579537544,
-           "valu_per_va": 58.5}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of that launch
+TRAFFIC = {"source_hash": "8f0e282e9ed73d21", "batch": 256, "bytes": 583800000,
+           "valu_per_va": 48.30}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of that launch
 # LDS bytes the DMAS kernel reads per voxel·antenna at W = 11: six 16-byte records of (sample, difference)
 LDS_BYTES_DMAS = 96
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2   # wave64 FP32 VALU instructions/s (two cycles each)
@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--c3-scans", type=int, default=32, help="3D scans for the octree walks against full DMAS")
     ap.add_argument("--no-c3", action="store_true", help="skip the 3D (256^3) measurements")
     ap.add_argument("--no-c1", action="store_true", help="skip the single-scan latency measurements")
+    ap.add_argument("--mvdr-scans", type=int, default=64, help="2D scans of the Capon (MVDR) block")
+    ap.add_argument("--no-mvdr", action="store_true", help="skip the Capon (MVDR) measurements")
     ap.add_argument("--no-separate", action="store_true",
                     help="skip timing the DAS and DMAS kernels as separate launches (profiling runs)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
@@ -331,6 +333,8 @@ def main():
         },
         "input_generation_s": round(gen_s, 2),
     }
+    if not args.no_mvdr:
+        out["mvdr"] = mvdr_block(args, uwb, synth, dev)
     if not args.no_c1:
         out["c1_latency"] = c1_block(uwb, synth, dev)
     if not args.no_c3:
@@ -391,6 +395,61 @@ def _event_ms(fn, reps=50):
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1))
     return float(np.median(ts))
+
+
+def mvdr_flops_per_va(window: int, n_ant: int) -> float:
+    """Algorithmic FP32 work of the Capon (MVDR) image per voxel·antenna: the delay (11 flops), per window offset
+    the interpolation (3) and the window sum (1), the W (W + 1) / 2 Gram products (2 each), and per voxel the W x W
+    Cholesky factorisation and two triangular solves (W^3 / 3 + 2 W^2 flops) spread over the voxel's antennas."""
+    w = window
+    return FLOPS_DELAY + 4 * w + w * (w + 1) + (w ** 3 / 3 + 2 * w * w) / n_ant
+
+
+def mvdr_block(args, uwb, synth, dev):
+    """The framework over the Capon (MVDR) beamformer on the 2D hierarchical configuration (32 antennas, 2048
+    samples, 512 x 512, 200 clutter scatterers, 20 dB): full-resolution MVDR images and their detection, and the
+    per-level walk over MVDR (g = 16) against the full-resolution MVDR detection."""
+    import ctypes
+    import numpy as np
+    import torch
+    n = args.mvdr_scans
+    scans = [synth.c2_scan(5000 + k) for k in range(n)]
+    g = scans[0].grid
+    nx, ny, nz = g.dims
+    M = scans[0].n_ant
+    b = uwb.DeviceBatch.from_host(scans, dev)
+    bc = b.c()
+    img = torch.empty((n, nz, ny, nx), dtype=torch.float32, device=dev)
+    t_img = _event_ms(lambda: uwb.image_batch(b, g, 2, out=img, bc=bc), reps=11)
+    pk = uwb.argmax_batch_async(b, g, img, 2, bc=bc)
+    t_arg = _event_ms(lambda: uwb.argmax_batch_async(b, g, img, 2, out=pk, bc=bc), reps=11)
+    full = uwb._peaks(pk, n)
+    va = n * nx * ny * nz * M
+    res = {}
+    for m in ("max", "mean"):
+        tree = uwb.SegmentTree(beamformer=2, coarse=16, metric=m, frame_final=0.25)
+        gc, tc = uwb.grid_c(g), tree.c()
+        ws = torch.empty(uwb.lib().uwb_segment_workspace_bytes(ctypes.byref(gc), ctypes.byref(tc), n),
+                         dtype=torch.uint8, device=dev)
+        rb = torch.empty(ctypes.sizeof(uwb.UwbSegmentResult) * n, dtype=torch.uint8, device=dev)
+        t_w = _event_ms(lambda tree=tree, ws=ws, rb=rb: uwb.segment_refine_batch_async(
+            b, g, tree, out=rb, workspace=ws, bc=bc), reps=11)
+        rr = uwb._results(rb, n, 4)
+        w1 = float(np.mean([abs(r.argmax % nx - f.index % nx) <= 1 and abs(r.argmax // nx - f.index // nx) <= 1
+                            for r, f in zip(rr, full)]))
+        res[f"walk_g16_{m}"] = {"scans_per_s": round(n / (t_w * 1e-3), 1), "ms_per_batch": round(t_w, 4),
+                                "within_1_voxel_of_full_mvdr": w1,
+                                "speedup_vs_full_mvdr_at_equal_error":
+                                    round((t_img + t_arg) / t_w, 1) if w1 >= 1.0 else None}
+    fpva = mvdr_flops_per_va(11, M)
+    return {"workload": "2D monostatic ring, 32 antennas x 2048 samples, 512x512 grid, window 11, Capon weights "
+                        "(diagonal loading 3 x mean channel power) per voxel",
+            "scans": n, "image_ms": round(t_img, 4), "gvas": round(va / (t_img * 1e-3) / 1e9, 2),
+            "flops_per_voxel_antenna": round(fpva, 1),
+            "tflops": round(fpva * va / (t_img * 1e-3) / 1e12, 2),
+            "roofline_frac_fp32": round(fpva * va / (t_img * 1e-3) / PEAK_FP32, 4),
+            "detection_ms": round(t_arg, 4), "full_mvdr_scans_per_s": round(n / ((t_img + t_arg) * 1e-3), 1),
+            **res}
 
 
 def c1_block(uwb, synth, dev):
