@@ -408,7 +408,7 @@ def mvdr_flops_per_va(window: int, n_ant: int) -> float:
 def mvdr_block(args, uwb, synth, dev):
     """The framework over the Capon (MVDR) beamformer on the 2D hierarchical configuration (32 antennas, 2048
     samples, 512 x 512, 200 clutter scatterers, 20 dB): full-resolution MVDR images and their detection, and the
-    per-level walk over MVDR (g = 16) against the full-resolution MVDR detection."""
+    per-level walk over MVDR (g = 16 and 32) against the full-resolution MVDR detection."""
     import ctypes
     import numpy as np
     import torch
@@ -426,8 +426,8 @@ def mvdr_block(args, uwb, synth, dev):
     full = uwb._peaks(pk, n)
     va = n * nx * ny * nz * M
     res = {}
-    for m in ("max", "mean"):
-        tree = uwb.SegmentTree(beamformer=2, coarse=16, metric=m, frame_final=0.25)
+    for gg, m in ((16, "max"), (16, "mean"), (32, "max"), (32, "mean")):
+        tree = uwb.SegmentTree(beamformer=2, coarse=gg, metric=m, frame_final=0.25)
         gc, tc = uwb.grid_c(g), tree.c()
         ws = torch.empty(uwb.lib().uwb_segment_workspace_bytes(ctypes.byref(gc), ctypes.byref(tc), n),
                          dtype=torch.uint8, device=dev)
@@ -437,7 +437,7 @@ def mvdr_block(args, uwb, synth, dev):
         rr = uwb._results(rb, n, 4)
         w1 = float(np.mean([abs(r.argmax % nx - f.index % nx) <= 1 and abs(r.argmax // nx - f.index // nx) <= 1
                             for r, f in zip(rr, full)]))
-        res[f"walk_g16_{m}"] = {"scans_per_s": round(n / (t_w * 1e-3), 1), "ms_per_batch": round(t_w, 4),
+        res[f"walk_g{gg}_{m}"] = {"scans_per_s": round(n / (t_w * 1e-3), 1), "ms_per_batch": round(t_w, 4),
                                 "within_1_voxel_of_full_mvdr": w1,
                                 "speedup_vs_full_mvdr_at_equal_error":
                                     round((t_img + t_arg) / t_w, 1) if w1 >= 1.0 else None}

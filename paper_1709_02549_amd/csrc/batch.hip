@@ -101,7 +101,8 @@ __global__ __launch_bounds__(kBlock) void k_batch32(const BatchArgs a) {
             j.rs = d.rs;
             j.chunk = d.chunk;
             j.ms = 0;
-            image_tile<BF, W, D3, VPL>(j, smem);
+            if (j.t0s == 0.0) image_tile<BF, W, D3, VPL, false, false, true>(j, smem);   // uniform per workgroup
+            else image_tile<BF, W, D3, VPL>(j, smem);
             __syncthreads();   // every lane's image stores are issued before the stamp
             if (threadIdx.x == 0) atomicMax(&a.t_done[scan], __builtin_amdgcn_s_memrealtime());
         }

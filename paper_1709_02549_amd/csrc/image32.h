@@ -175,7 +175,10 @@ __host__ __device__ inline void band_box(int64_t p0, int64_t p1, int nx, int ny,
 // BAND (one voxel per lane only): the workgroup images the 256 consecutive voxels
 // from j.p0 (x fastest) instead of a tile -- for small, ragged grids, whose tiles
 // would idle many lanes; j.rs must cover the band's bounding box (band_box).
-template <int BF, int W, bool D3, int VPL, bool MS = false, bool BAND = false>
+// T0Z: the scan's t0 is zero (sample 0 at the excitation peak, as in the workloads), so the monostatic delay
+// is the scaled distance itself and its subtraction of t0 / dt, one instruction per voxel·antenna, is left
+// out; subtracting zero is exact, so the energies are those of the general form bit for bit.
+template <int BF, int W, bool D3, int VPL, bool MS = false, bool BAND = false, bool T0Z = false>
 __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
     static_assert(!BAND || VPL == 1, "a band holds one voxel per lane");
     using TS = TileShape<D3, VPL>;
@@ -375,6 +378,7 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
                 } else {
                     float tau;
                     if (MS) tau = dtx[v] + __builtin_amdgcn_sqrtf(leg_v(er, partr, v));
+                    else if constexpr (T0Z) tau = __builtin_amdgcn_sqrtf(leg_v(e, part, v));
                     else tau = __builtin_amdgcn_sqrtf(leg_v(e, part, v)) - t0s;
                     tau = __builtin_amdgcn_fmed3f(tau, lof, hif);
                     f = __builtin_amdgcn_fractf(tau);

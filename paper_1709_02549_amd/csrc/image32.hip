@@ -92,7 +92,8 @@ void k_image32(const Args a) {
     j.rs = a.rs;
     j.chunk = a.chunk;
     j.ms = a.ss.ms;
-    image_tile<BF, W, D3, VPL, MS>(j, smem);
+    if (!MS && j.t0s == 0.0) image_tile<BF, W, D3, VPL, MS, false, true>(j, smem);   // uniform per workgroup
+    else image_tile<BF, W, D3, VPL, MS>(j, smem);
 }
 
 template <int BF, int W>

@@ -148,19 +148,29 @@ def test_window_limit():
 # the framework (Section III) over the MVDR beamformer
 # ----------------------------------------------------------------------------------
 
+# largest relative GPU - oracle difference of the MVDR walk's FP64 scores (printed by the test below)
+MVDR_DIFF = {"score": 0.0}
+
+
 def _walk_compare(g, o):
+    """Decisions exact; FP64 values to 1e-11 relative: the GPU solves the Woodbury W x W system and the oracle
+    the M x M one, and the normalised system's condition number (<= 1 + M / 3, 12 for M = 32) scales their
+    ~1e-15 rounding differences."""
     assert g.child == o.child
     assert g.n_levels == o.n_levels and g.term_level == o.term_level
     assert [tuple(b) for b in g.boxes] == [tuple(b) for b in o.boxes]
     assert tuple(g.roi) == tuple(o.roi)
     assert g.argmax == o.argmax
-    assert g.peak == pytest.approx(o.peak, rel=1e-9)
+    assert g.peak == pytest.approx(o.peak, rel=1e-11)
     assert g.voxels_evaluated == o.voxels_evaluated
     for a, b in zip(g.scores, o.scores):
-        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-300)
+        np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-300)
+        a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+        d = np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+        MVDR_DIFF["score"] = max(MVDR_DIFF["score"], float(np.max(np.where(a == b, 0.0, d))))
     assert len(g.wb) == len(o.wb)
     for a, b in zip(g.wb, o.wb):
-        np.testing.assert_allclose(a, b, rtol=1e-9)
+        np.testing.assert_allclose(a, b, rtol=1e-11)
 
 
 @pytest.mark.parametrize("metric", ["max", "mean", "eq5", "var"])
@@ -200,3 +210,8 @@ def test_c3_octree_walk():
     o = oracle.walk(s, oracle.TreeParams(**kw))
     g = uwb().segment_refine(uwb().DeviceScan.from_host(s), s.grid, uwb().SegmentTree(**kw))
     _walk_compare(g, o)
+
+
+def test_zz_report_mvdr_walk_difference():
+    """Prints the largest relative GPU - oracle difference of the MVDR walks' FP64 scores seen above."""
+    print(f"MVDR walk FP64 GPU-oracle max relative score difference: {MVDR_DIFF['score']:.3e}")
