@@ -28,6 +28,7 @@ __host__ __device__ inline int staged_samples(double s, double ex, double ey, do
 void tile_shape(bool d3, int vpl, int *tx, int *ty, int *tz);
 
 constexpr int kStageBatch = 8;   // rows of 64 samples a wavefront loads before writing them
+constexpr int kMaxSubtiles = 4;  // tiles a workgroup may image from one staging (TileJob::subtiles)
 
 // Windows shorter than this take the delay in FP64.  The FP32 delay carries an absolute error of about
 // 2e-5 samples (an ulp of a delay of ~200 samples); an energy summed over 5 or more taps spans a good part
@@ -137,6 +138,7 @@ struct TileJob {
     float *img_das = nullptr;   // DMAS only, optional: the DAS image of the same voxels
     float *tmax = nullptr;      // optional: the tile's FP32 maximum of img (of img_das: tmax_das)
     float *tmax_das = nullptr;
+    int subtiles = 1;           // tiles along x imaged from one staging (then every channel fits one chunk)
 };
 
 // Tile geometry.  2D: 16 (x) by 16*VPL (y); lane (tx, ty) owns y = ty + 16 v.
@@ -198,6 +200,11 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
     const int nx = j.g.dims[0], ny = j.g.dims[1], nz = j.g.dims[2];
     const int T = j.T, M = j.M;
     const int tx0 = j.tx0, ty0 = j.ty0, tz0 = j.tz0;
+    // S tiles side by side along x share one staging of the traces: the staged span covers their union,
+    // which is only a few samples longer than one tile's, and the table and the staging pass (global-memory
+    // latency between two barriers) are paid once for S tiles.  The host sets S > 1 when every channel fits
+    // one chunk; with several chunks each sub-tile stages them again.
+    const int S = BAND ? 1 : j.subtiles;
 
     const float qx = (float)(sc * j.g.pitch[0]);
     const float qy = (float)(sc * j.g.pitch[1]);
@@ -205,7 +212,8 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
     const float t0s = (float)j.t0s;
 
     // lane -> voxels, and the bounding box of the workgroup's voxels (inclusive finest indices)
-    int vx, vy[VPL], vz[VPL];
+    // a lane's voxels differ only in y (2D) or z (3D), by a constant stride: one base each
+    int vx, vy0, vz0;
     int bx0, by0, bz0, bx1, by1, bz1;
     bool live = true;   // band form: the lane's voxel exists
     if (BAND) {
@@ -213,31 +221,37 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
         const int64_t p = j.p0 + tid, p1 = min(j.p0 + kBlock, n) - 1, pc = min(p, p1);
         live = p <= p1;
         vx = (int)(pc % nx);
-        vy[0] = (int)((pc / nx) % ny);
-        vz[0] = (int)(pc / sxy);
+        vy0 = (int)((pc / nx) % ny);
+        vz0 = (int)(pc / sxy);
         band_box(j.p0, p1, nx, ny, bx0, bx1, by0, by1, bz0, bz1);
     } else if (!D3) {
         vx = tx0 + (tid & 15);
-#pragma unroll
-        for (int v = 0; v < VPL; ++v) { vy[v] = ty0 + (tid >> 4) + 16 * v; vz[v] = 0; }
+        vy0 = ty0 + (tid >> 4);
+        vz0 = 0;
     } else {
         vx = tx0 + (tid & 7);
-#pragma unroll
-        for (int v = 0; v < VPL; ++v) { vy[v] = ty0 + ((tid >> 3) & 7); vz[v] = tz0 + (tid >> 6) + 4 * v; }
+        vy0 = ty0 + ((tid >> 3) & 7);
+        vz0 = tz0 + (tid >> 6);
     }
     if (!BAND) {
         bx0 = tx0; by0 = ty0; bz0 = tz0;
-        bx1 = min(tx0 + TX, nx) - 1; by1 = min(ty0 + TY, ny) - 1; bz1 = min(tz0 + TZ, nz) - 1;
+        bx1 = min(tx0 + S * TX, nx) - 1; by1 = min(ty0 + TY, ny) - 1; bz1 = min(tz0 + TZ, nz) - 1;
     }
     // this scan's own staging need must fit the launch's (a batch is sized for its bound)
-    const double ex = (BAND ? bx1 - bx0 : TX - 1) * j.g.pitch[0], ey = (BAND ? by1 - by0 : TY - 1) * j.g.pitch[1],
+    const double ex = (BAND ? bx1 - bx0 : S * TX - 1) * j.g.pitch[0], ey = (BAND ? by1 - by0 : TY - 1) * j.g.pitch[1],
                  ez = (BAND ? bz1 - bz0 : TZ - 1) * j.g.pitch[2];
     const double need = ceil(j.s * sqrt(ex * ex + ey * ey + ez * ez)) + W + 6;
     const bool fits = need <= (double)rs || rs >= T + 2 * W + 2;
+    // voxel v of the lane: y = vy0 + 16 v (2D) or z = vz0 + 4 v (3D)
+    auto VY = [&](int v) { return D3 ? vy0 : vy0 + 16 * v; };
+    auto VZ = [&](int v) { return D3 ? vz0 + 4 * v : vz0; };
+
+    // per sub-tile and wavefront: the maxima of the image and of the DAS image (tile maxima)
+    __shared__ float tile_red[kMaxSubtiles][2][kBlock / 64];
+    int n_sub = 0;   // sub-tiles imaged (those inside the grid)
+    for (int st = 0; st < S; ++st, vx += TX) {
+    if (!BAND && vx - (tid & (TX - 1)) >= nx) break;   // uniform: this sub-tile lies past the grid
     const float fx = (float)vx;
-    float fy[VPL], fz[VPL];
-#pragma unroll
-    for (int v = 0; v < VPL; ++v) { fy[v] = (float)vy[v]; fz[v] = (float)vz[v]; }
 
     // MVDR: one voxel per lane, whose window sums (acc) and Gram matrix (packed lower triangle) feed
     // the W x W solve of mvdr_energy
@@ -266,6 +280,7 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
 
     for (int a0 = 0; a0 < M; a0 += chunk) {
         const int nch = min(chunk, M - a0);
+        if (st == 0 || chunk < M) {   // one chunk: its table and records serve every sub-tile
         __syncthreads();   // previous chunk (or previous tile) fully consumed
         if (tid < nch) {
             const int i = a0 + tid;
@@ -314,6 +329,7 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
         stage_records<DIFF>(recs, rs, nch, j.tr + (int64_t)a0 * T, T,
                             [&](int jj) { return jj * rs - H - __float_as_int(tab[TE * jj].w); });
         __syncthreads();
+        }
 
         // bistatic: receiver of the chunk's first channel (channels run in order, so a
         // transmitter's distances carry over a chunk boundary)
@@ -333,11 +349,11 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
             auto leg_d2 = [&](const float4 &t, float &part) {
                 const float dx = fmaf(fx, qx, t.x);
                 if (!D3) part = fmaf(dx, dx, t.z);
-                else { const float dy = fmaf(fy[0], qy, t.y); part = fmaf(dy, dy, dx * dx); }
+                else { const float dy = fmaf((float)vy0, qy, t.y); part = fmaf(dy, dy, dx * dx); }
             };
             auto leg_v = [&](const float4 &t, float part, int v) {
-                if (!D3) { const float dy = fmaf(fy[v], qy, t.y); return fmaf(dy, dy, part); }
-                const float dz = fmaf(fz[v], qz, t.z);
+                if (!D3) { const float dy = fmaf((float)VY(v), qy, t.y); return fmaf(dy, dy, part); }
+                const float dz = fmaf((float)VZ(v), qz, t.z);
                 return fmaf(dz, dz, part);
             };
             float part, partr = 0.f;
@@ -361,8 +377,8 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
                     const int ch = a0 + jj;
                     const float *at = j.pos + 3 * (MS ? ch / j.ms : ch), *ar = j.pos + 3 * (MS ? ch % j.ms : ch);
                     const double rx = j.g.origin[0] + (double)vx * j.g.pitch[0];
-                    const double ry = j.g.origin[1] + (double)vy[v] * j.g.pitch[1];
-                    const double rz = j.g.origin[2] + (double)vz[v] * j.g.pitch[2];
+                    const double ry = j.g.origin[1] + (double)VY(v) * j.g.pitch[1];
+                    const double rz = j.g.origin[2] + (double)VZ(v) * j.g.pitch[2];
                     double dist = 0.0;
 #pragma unroll
                     for (int leg = 0; leg < TE; ++leg) {
@@ -446,6 +462,10 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
     // (Eq. (3)): a DMAS tile writes the DAS image too when asked, at no extra reads
     float *const das = BF == UWB_DMAS ? j.img_das : nullptr;
     float tm = -INFINITY, tmd = -INFINITY;   // this lane's maxima of its voxels (NaN ignored, as fmaxf does)
+    // the voxels' row offsets are the same in every sub-tile; computed here from a laundered zero, they are
+    // not hoisted out of the sub-tile loop (kept live across it they would be spilled to scratch memory)
+    int zrow = 0;
+    asm volatile("" : "+v"(zrow));
 #pragma unroll
     for (int v = 0; v < VPL; ++v) {
         float en = 0.f, ed = 0.f;
@@ -460,28 +480,30 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
             }
         }
         if (!fits) en = ed = __builtin_nanf("");
-        if (live && vx < nx && vy[v] < ny && vz[v] < nz) {
-            const int64_t o = ((int64_t)vz[v] * ny + vy[v]) * nx + vx;
+        if (live && vx < nx && VY(v) < ny && VZ(v) < nz) {
+            const int64_t o = ((int64_t)(VZ(v) + zrow) * ny + (VY(v) + zrow)) * nx + (vx + zrow);
             j.img[o] = en;
             if (das) das[o] = ed;
             tm = fmaxf(tm, en);
             tmd = fmaxf(tmd, ed);
         }
     }
-    // the tile's maxima, for a detection that reads them instead of the image (uniform branch)
+    // the tile's maxima, for a detection that reads them instead of the image (uniform branch): each
+    // wavefront's maxima per sub-tile go to LDS, combined once after the last sub-tile
     if (!MV && j.tmax) {
         tm = wave_maxf(tm);
         tmd = wave_maxf(tmd);
-        __syncthreads();   // every wave is done with the staged records: reuse their LDS
-        constexpr int NW = kBlock / 64;
-        float *red = smem;   // [NW] image maxima, then [NW] DAS-image maxima
-        if ((tid & 63) == 0) { red[tid >> 6] = tm; red[NW + (tid >> 6)] = tmd; }
+        if ((tid & 63) == 0) { tile_red[st][0][tid >> 6] = tm; tile_red[st][1][tid >> 6] = tmd; }
+    }
+    ++n_sub;
+    }   // sub-tiles
+    if (BF != UWB_MVDR && j.tmax) {
         __syncthreads();
-        if (tid == 0) {
-            float m = red[0], md = red[NW];
-            for (int w = 1; w < NW; ++w) { m = fmaxf(m, red[w]); md = fmaxf(md, red[NW + w]); }
-            *j.tmax = m;
-            if (j.tmax_das) *j.tmax_das = md;
+        if (tid < n_sub) {   // the sub-tiles' tiles are consecutive in tile order
+            float m = tile_red[tid][0][0], md = tile_red[tid][1][0];
+            for (int w = 1; w < kBlock / 64; ++w) { m = fmaxf(m, tile_red[tid][0][w]); md = fmaxf(md, tile_red[tid][1][w]); }
+            j.tmax[tid] = m;
+            if (j.tmax_das) j.tmax_das[tid] = md;
         }
     }
 }

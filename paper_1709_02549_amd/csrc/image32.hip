@@ -26,6 +26,8 @@
 // The tile body is shared by two kernels: k_image32 maps blockIdx to (tile,
 // scan) for same-shaped batches; k_batch32 is a persistent kernel that pulls
 // (scan, tile) items of uneven scans from a work list (see batch.hip).
+#include <algorithm>
+
 #include "image32.h"
 
 namespace uwb {
@@ -40,6 +42,12 @@ namespace {
 // Voxels per lane of the grid-mapped kernel: 4 (tiles of 16 x 64 in 2D, 8 x 8 x 16 in 3D)
 // measured a few per cent faster than 2 for DAS and DMAS on the 512 x 512 batch.
 constexpr int kImageVpl = 4;
+
+// Tiles along x a workgroup images from one staging of the traces, when every channel fits one chunk and
+// the launch keeps at least kGroupMinWorkgroups workgroups (a few per CU slot): the staging pass, about
+// 7 % of a 512 x 512 DMAS launch with one tile per workgroup, is then paid once per four tiles.
+constexpr int kGroupTiles = kMaxSubtiles;
+constexpr int64_t kGroupMinWorkgroups = 4096;
 
 }  // namespace
 
@@ -58,6 +66,8 @@ struct Args {
     int tiles_x, tiles_y;   // tiles along x and y (z = rest)
     int rs;                 // staged samples per antenna (stride in LDS)
     int chunk;              // antennas staged per pass
+    int subtiles;           // tiles along x per workgroup, imaged from one staging
+    int groups_x;           // workgroups along x: ceil(tiles_x / subtiles)
 };
 
 // Voxels per lane of a beamformer: MVDR keeps a W x W Gram matrix per voxel, one voxel per lane.
@@ -67,7 +77,7 @@ template <int BF, int W, bool D3, bool MS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BF == UWB_MVDR ? 2 : 3)))
 void k_image32(const Args a) {
     constexpr int VPL = image_vpl<BF>();
-    extern __shared__ float smem[];
+    extern __shared__ __align__(16) float smem[];
     const int scan = blockIdx.y;
     const ScanConst sc = scan_const(a.ss, scan);
     int tx, ty, tz;
@@ -77,7 +87,8 @@ void k_image32(const Args a) {
     j.tr = sc.tr;
     j.img = a.img + (int64_t)scan * a.img_stride;
     j.img_das = a.img_das ? a.img_das + (int64_t)scan * a.img_stride : nullptr;
-    const int64_t slot = (int64_t)scan * a.tiles + blockIdx.x;
+    const int g = blockIdx.x, gx = g % a.groups_x, gyz = g / a.groups_x;   // gyz = tile row (y, z)
+    const int64_t slot = (int64_t)scan * a.tiles + (int64_t)gyz * a.tiles_x + gx * a.subtiles;   // first sub-tile's
     j.tmax = a.tmax ? a.tmax + slot : nullptr;
     j.tmax_das = a.tmax_das ? a.tmax_das + slot : nullptr;
     j.M = a.ss.n_ant;
@@ -85,10 +96,10 @@ void k_image32(const Args a) {
     j.s = sc.s;
     j.t0s = sc.t0s;
     j.g = a.g;
-    const int tile = blockIdx.x;
-    j.tx0 = (tile % a.tiles_x) * tx;
-    j.ty0 = ((tile / a.tiles_x) % a.tiles_y) * ty;
-    j.tz0 = (tile / (a.tiles_x * a.tiles_y)) * tz;
+    j.tx0 = gx * a.subtiles * tx;
+    j.ty0 = (gyz % a.tiles_y) * ty;
+    j.tz0 = (gyz / a.tiles_y) * tz;
+    j.subtiles = a.subtiles;
     j.rs = a.rs;
     j.chunk = a.chunk;
     j.ms = a.ss.ms;
@@ -151,20 +162,32 @@ int launch_image32(int bf, const ScanSet &ss, int n_scans, const GridView &g, in
     // inside a batch the speed may vary per scan: ss.v and ss.dt hold lower bounds
     // over the batch, so this sizes the staging for the largest samples-per-metre
     const double s_max = 2.0 / (ss.v * ss.dt);
-    a.rs = staged_samples(s_max, (tx - 1) * g.pitch[0], (ty - 1) * g.pitch[1], (tz - 1) * g.pitch[2], window,
-                          ss.n_samp);
-    const int per_ant = a.rs * 16 + (ss.ms ? 32 : 16);   // staged records of 4 samples + table entries
-    if (per_ant > kLdsBudget) return UWB_EUNSUPPORTED;
-    a.chunk = kLdsBudget / per_ant;
-    if (a.chunk > kBlock) a.chunk = kBlock;
-    if (a.chunk > ss.n_ant) a.chunk = ss.n_ant;
-    const size_t lds = (size_t)a.chunk * per_ant;
     const int64_t tiles = (int64_t)a.tiles_x * a.tiles_y * tiles_z;
     if (tiles > 0x7fffffff || n_scans > 65535) return UWB_EUNSUPPORTED;
+    // staging for S tiles side by side along x: S = kGroupTiles when every channel then fits one chunk and
+    // the launch still holds enough workgroups to fill the device several times over, else S = 1
+    auto plan = [&](int S, int &rs, int &chunk) {
+        rs = staged_samples(s_max, (S * tx - 1) * g.pitch[0], (ty - 1) * g.pitch[1], (tz - 1) * g.pitch[2], window,
+                            ss.n_samp);
+        const int per_ant = rs * 16 + (ss.ms ? 32 : 16);   // staged records of 4 samples + table entries
+        if (per_ant > kLdsBudget) return false;
+        chunk = std::min(std::min(kLdsBudget / per_ant, kBlock), ss.n_ant);
+        return true;
+    };
+    int S = 1;
+    if (a.tiles_x >= kGroupTiles && (tiles / kGroupTiles) * n_scans >= kGroupMinWorkgroups &&
+        plan(kGroupTiles, a.rs, a.chunk) && a.chunk >= ss.n_ant)
+        S = kGroupTiles;
+    else if (!plan(1, a.rs, a.chunk))
+        return UWB_EUNSUPPORTED;
+    a.subtiles = S;
+    a.groups_x = (a.tiles_x + S - 1) / S;
+    const size_t lds = (size_t)a.chunk * (a.rs * 16 + (ss.ms ? 32 : 16));
     a.tiles = (int)tiles;
     a.tmax = tmax;
     a.tmax_das = tmax_das;
-    dim3 grid((unsigned)tiles, (unsigned)n_scans);
+    const int64_t groups = (int64_t)a.groups_x * a.tiles_y * tiles_z;
+    dim3 grid((unsigned)groups, (unsigned)n_scans);
     hipError_t e = bf == UWB_DMAS   ? launch_bf<UWB_DMAS>(window, d3, grid, lds, stream, a)
                    : bf == UWB_MVDR ? launch_bf<UWB_MVDR>(window, d3, grid, lds, stream, a)
                                     : launch_bf<UWB_DAS>(window, d3, grid, lds, stream, a);

@@ -297,3 +297,37 @@ def test_flat_images_overflow_the_chunk_list():
         pk = u._peaks(p, 2)
         assert [q.index for q in pk] == [0, 0]
         assert [q.candidates for q in pk] == [256 * 256] * 2
+
+
+def test_grouped_tiles_match_single_tiles():
+    """A large launch images four tiles per workgroup from one staging of the traces (the launch holds enough
+    workgroups); on a grid whose tiles do not fill the last group of a row (200 x 200: 13 tiles of 16 along x,
+    four rows of 64, ragged in both) every image equals the one-scan launch's (one tile per workgroup) bit for
+    bit, the tile maxima are the images' own, the detections those of uwb_argmax_batch, and two scans meet the
+    oracle's bar."""
+    u = uwb()
+    g = Grid((-0.05, -0.05, 0.0), (0.1 / 199, 0.1 / 199, 1e-3), (200, 200, 1))
+    ant = synth.ring_antennas(4)
+    scans = []
+    for k in range(320):
+        rng = np.random.default_rng(7000 + k)
+        tum = np.array([*rng.uniform(-0.03, 0.03, 2), 0.0])
+        s = synth.point_scan(ant, g, tum[None, :], [1.0], 512, synth.C0 / 3)
+        s.traces = (s.traces + 0.01 * rng.standard_normal(s.traces.shape)).astype(np.float32)
+        scans.append(s)
+    b = u.DeviceBatch.from_host(scans)
+    das, dmas, tdas, tdmas = u.das_dmas_batch_tilemax(b, g)
+    torch.cuda.synchronize()
+    assert torch.equal(tdas, _tile_max_reference(das, g)) and torch.equal(tdmas, _tile_max_reference(dmas, g))
+    for k in (0, 1, 157, 319):
+        d1, m1 = u.das_dmas(u.DeviceScan.from_host(scans[k]), g)
+        torch.cuda.synchronize()
+        assert torch.equal(d1, das[k]) and torch.equal(m1, dmas[k]), k
+    for bf, img, tm in ((0, das, tdas), (1, dmas, tdmas)):
+        p_tile = u.argmax_batch_tilemax_async(b, g, img, tm, bf)
+        p_ref = u.argmax_batch_async(b, g, img, bf)
+        torch.cuda.synchronize()
+        assert torch.equal(p_tile, p_ref)
+    for k in (0, 319):
+        _check_image(das[k].cpu().numpy(), oracle.image_grid(scans[k], 0))
+        _check_image(dmas[k].cpu().numpy(), oracle.image_grid(scans[k], 1))
