@@ -51,8 +51,8 @@ PEAK_FP32 = 157.3e12
 # batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a 256 MiB copy); valid only for the kernel
 # sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
-TRAFFIC = {"source_hash": "8f0e282e9ed73d21", "batch": 256, "bytes": 583800000,
-           "valu_per_va": 48.30}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of that launch
+TRAFFIC = {"source_hash": "5de47146d8ba55e0", "batch": 256, "bytes": 590500000,
+           "valu_per_va": 45.56}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of that launch
 # LDS bytes the DMAS kernel reads per voxel·antenna at W = 11: six 16-byte records of (sample, difference)
 LDS_BYTES_DMAS = 96
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2   # wave64 FP32 VALU instructions/s (two cycles each)
