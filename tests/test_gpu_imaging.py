@@ -331,3 +331,24 @@ def test_grouped_tiles_match_single_tiles():
     for k in (0, 319):
         _check_image(das[k].cpu().numpy(), oracle.image_grid(scans[k], 0))
         _check_image(dmas[k].cpu().numpy(), oracle.image_grid(scans[k], 1))
+
+
+def test_nan_trace_detection_is_reported_not_found():
+    """A NaN sample propagates into every voxel that reads it (traces are not scanned for NaN); where the whole
+    image is NaN both detection forms report no finite candidate: index 0 and a NaN value, identically."""
+    u = uwb()
+    scans = [synth.c1_scan(k, n_grid=64) for k in range(2)]
+    scans[1].traces = np.full_like(scans[1].traces, np.nan)
+    g = scans[0].grid
+    b = u.DeviceBatch.from_host(scans)
+    das, dmas, tdas, tdmas = u.das_dmas_batch_tilemax(b, g)
+    torch.cuda.synchronize()
+    assert torch.isnan(dmas[1]).all() and torch.isfinite(dmas[0]).all()
+    for bf, img, tm in ((0, das, tdas), (1, dmas, tdmas)):
+        p_tile = u.argmax_batch_tilemax_async(b, g, img, tm, bf)
+        p_ref = u.argmax_batch_async(b, g, img, bf)
+        torch.cuda.synchronize()
+        assert torch.equal(p_tile, p_ref)
+        pk = u._peaks(p_ref, 2)
+        assert pk[1].index == 0 and np.isnan(pk[1].value)
+        assert pk[0].index == oracle.argmax_grid(oracle.image_grid(scans[0], bf))[0]
