@@ -72,12 +72,40 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 
 // Wave-level reductions (wave64).
+// Wave-wide FP64 sum and maximum, the same value in every lane: a butterfly whose
+// first four stages stay inside rows of 16 lanes and run as data-parallel-primitive
+// moves (lanes paired at distance 1 and 2 by quad permutations, then quads by the
+// half-row mirror and half-rows by the row mirror) instead of LDS-crossbar permutations;
+// the last two stages pair rows 16 and 32 lanes apart.  Every stage adds two values
+// that are the same in both lanes of a pair, so all lanes hold the same bits throughout,
+// which are those of the xor butterfly over 1, 2, 4, 8, 16, 32.
+template <int CTRL>
+__device__ __forceinline__ double dpp_row64(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror: lane i <-> 7 - i within each 8
+constexpr int kDppMirror = 0x140;      // row_mirror: lane i <-> 15 - i within each row
 __device__ __forceinline__ double wave_sum(double x) {
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    x += dpp_row64<kDppXor1>(x);
+    x += dpp_row64<kDppXor2>(x);
+    x += dpp_row64<kDppHalfMirror>(x);
+    x += dpp_row64<kDppMirror>(x);
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
     return x;
 }
 __device__ __forceinline__ double wave_max(double x) {
-    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+    x = fmax(x, dpp_row64<kDppXor1>(x));
+    x = fmax(x, dpp_row64<kDppXor2>(x));
+    x = fmax(x, dpp_row64<kDppHalfMirror>(x));
+    x = fmax(x, dpp_row64<kDppMirror>(x));
+    x = fmax(x, __shfl_xor(x, 16, 64));
+    x = fmax(x, __shfl_xor(x, 32, 64));
     return x;
 }
 __device__ __forceinline__ float wave_maxf(float x) {

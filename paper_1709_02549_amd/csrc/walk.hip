@@ -135,14 +135,20 @@ __global__ __launch_bounds__(kBlock) void k_walk_paper(const WalkArgs a, int n_s
         if (cmin < kMinChildSamples) { n_kept = lev; break; }
         // select the child (lowest index within the tie band)
         double best = -INFINITY;
-        for (int c = 0; c < nchild; ++c) best = fmax(best, sc8[c]);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (c < nchild) best = fmax(best, sc8[c]);
         const double thr = best - kTieRel * fabs(best);
         int sel = 0;
-        for (int c = nchild - 1; c >= 0; --c)
-            if (sc8[c] >= thr) sel = c;
-        expand_box(cbox[sel], a.frame_level, nact, dims, box);
+#pragma unroll
+        for (int c = 7; c >= 0; --c)
+            if (c < nchild && sc8[c] >= thr) sel = c;
+        int sbox[6];   // the chosen child's box formed again (a runtime index into cbox would place it in scratch)
+        split_box(box, sel, nact, sbox);
+        expand_box(sbox, a.frame_level, nact, dims, box);
         if (tid == 0) {
             R.child[made] = sel;
+#pragma unroll
             for (int c = 0; c < 8; ++c) R.score[made][c] = c < nchild ? sc8[c] : 0.0;
             for (int i = 0; i < 6; ++i) R.box[lev + 1][i] = box[i];
         }
@@ -175,13 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_walk_paper(const WalkArgs a, int n_s
 __global__ void k_pl_init(const WalkArgs a, int n_scans) {
     const int scan = blockIdx.x * blockDim.x + threadIdx.x;
     if (scan >= n_scans) return;
-    PLState &S = a.state[scan];
-    S.prev_n = S.prev_mean = S.prev_m2 = S.prev_w = S.prev_b = 0.0;
-    S.nvox = 0;
-    S.active = 1;
-    S.n_kept = a.depth;
-    S.made = 0;
-    S.n_wb = 0;
+    pl_init_state(a, a.state[scan]);
     uwb_segment_result &R = a.out[scan];
     const int full[6] = {0, a.g.dims[0], 0, a.g.dims[1], 0, a.g.dims[2]};
     for (int i = 0; i < 6; ++i) R.box[0][i] = full[i];
@@ -197,24 +197,7 @@ __global__ __launch_bounds__(kBlock) void k_pl_level(const WalkArgs a, int lev, 
 __global__ void k_pl_finish(const WalkArgs a, int n_scans) {
     const int scan = blockIdx.x * blockDim.x + threadIdx.x;
     if (scan >= n_scans) return;
-    const int nact = a.g.dims[2] > 1 ? 3 : 2;
-    const int dims[3] = {a.g.dims[0], a.g.dims[1], a.g.dims[2]};
-    const PLState st = a.state[scan];
-    uwb_segment_result &R = a.out[scan];
-    int roi[6];
-    expand_box(R.box[st.n_kept], a.frame_final, nact, dims, roi);
-    R.n_levels = st.n_kept;
-    R.term_level = st.made;
-    R.decimation = 0;
-    R.n_samples_level0 = (int)(nact == 3 ? a.coarse * a.coarse * a.coarse : a.coarse * a.coarse);
-    R.n_wb = st.n_wb;
-    for (int i = 0; i < 6; ++i) R.roi[i] = roi[i];
-    const int64_t rv = (int64_t)(roi[1] - roi[0]) * (roi[3] - roi[2]) * (roi[5] - roi[4]);
-    R.voxels_evaluated = st.nvox + rv;
-    R.argmax = -1;
-    R.peak = 0.0;
-    R.learned_mask = 0;
-    R.guard_hits = 0;
+    pl_finish_record(a, a.state[scan], a.out[scan]);
 }
 
 // ----------------------------------------------------------------------------
@@ -300,13 +283,16 @@ __global__ __launch_bounds__(kBlock) void k_learn_level(const WalkArgs a, int le
     double sc8[8];
     wave_level_stats<2>(a, L, lv, box, side, false, cbox, sc8);
     double best = -INFINITY;
+#pragma unroll
     for (int c = 0; c < 4; ++c) best = fmax(best, sc8[c]);
     const double thr = best - kTieRel * fabs(best);
     int sel = 0;
+#pragma unroll
     for (int c = 3; c >= 0; --c)
         if (sc8[c] >= thr) sel = c;
     if (lane == 0) {
         fb_child[scan] = sel;
+#pragma unroll
         for (int c = 0; c < 8; ++c) R.score[lev][c] = c < 4 ? sc8[c] : 0.0;
     }
     // the CNN input: the lattice divided by its maximum, BF16, [y][x]
@@ -620,11 +606,12 @@ int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st) {
         else hipLaunchKernelGGL(k_walk_paper<2>, gw, dim3(kBlock), 0, st, a, n_scans);
     } else {
         const unsigned nb = (unsigned)((n_scans + 255) / 256);
-        hipLaunchKernelGGL(k_pl_init, dim3(nb), dim3(256), 0, st, a, n_scans);
         const int levels = a.term == UWB_TERM_WB ? a.depth + 1 : a.depth;
         const int nact = a.g.dims[2] > 1 ? 3 : 2;
         const int cnt[3] = {a.coarse, a.coarse, nact == 3 ? a.coarse : 1};
-        const bool fused = fuse_levels(a, n_scans);
+        // the fused kernel sets up and finishes the walk itself
+        const bool fused = levels >= 1 && fuse_levels(a, n_scans);
+        if (!fused) hipLaunchKernelGGL(k_pl_init, dim3(nb), dim3(256), 0, st, a, n_scans);
         if (fused) {
             Grid64Args g = grid_args(a, kGridBox);
             g.state = a.state;
@@ -645,7 +632,7 @@ int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st) {
             if (nact == 3) hipLaunchKernelGGL(k_pl_level<3>, gw, dim3(kBlock), 0, st, a, lev, n_scans);
             else hipLaunchKernelGGL(k_pl_level<2>, gw, dim3(kBlock), 0, st, a, lev, n_scans);
         }
-        hipLaunchKernelGGL(k_pl_finish, dim3(nb), dim3(256), 0, st, a, n_scans);
+        if (!fused) hipLaunchKernelGGL(k_pl_finish, dim3(nb), dim3(256), 0, st, a, n_scans);
     }
     if ((rc = launch_roi(a, a.bf, n_scans, st))) return rc;
     return hipGetLastError() == hipSuccess ? UWB_OK : UWB_EHIP;

@@ -73,8 +73,8 @@ struct Group {
 };
 
 template <int BF, int W, bool MS>
-__device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const Group &G, unsigned char *dsm,
-                             int64_t out_offset);
+__device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const ScanConst &sc, const Group &G,
+                             unsigned char *dsm, int64_t out_offset, double *lat_lds);
 
 // Group t of a c0 x c1 x c2 lattice as lane tid sees it: a tile when the lattice is a whole
 // number of tiles (tiled), else the band of points t * 256 .. in lattice order.
@@ -153,42 +153,61 @@ void k_grid64(const Grid64Args a) {
     const int64_t t = blockIdx.x;   // the launch holds enough workgroups for the largest lattice
     if (t >= ngroups) return;       // uniform per workgroup
     const Group G = make_group<D3>(c0, c1, c2, tiled, t, tid);
-    grid64_group<BF, W, MS>(a, L, scan, G, dsm, a.out_offset);
+    grid64_group<BF, W, MS>(a, L, scan, scan_const(a.ss, scan), G, dsm, a.out_offset, nullptr);
 }
 
-// The per-level walk in one launch, one workgroup per scan: at every level the workgroup
-// images the coarse^d lattice of the scan's box group by group (as k_grid64 does), then
-// its first wavefront takes the level's statistics and decision; the barriers between
-// the phases publish the lattice values and the next box (global memory) to the whole
-// workgroup.  Values and decisions are those of the level-synchronous kernels.
+// The per-level walk in one launch, one workgroup per scan: the workgroup sets up the
+// walk, then at every level images the coarse^d lattice of the scan's box (as k_grid64
+// does, the energies also kept in LDS), and its first wavefront takes the level's
+// statistics and decision; finally it writes the walk's record for the ROI phase.  The
+// walk's state stays in the first wavefront's registers and the box and the lattice in
+// LDS (barriers publish them), so a level reads nothing back from global memory.  Values
+// and decisions are those of the level-synchronous kernels.
 template <int BF, int W, bool D3, bool MS>
 __global__ __launch_bounds__(kBlock) void k_pl_fused(const Grid64Args a, const WalkArgs w, int levels) {
     using TS = Tile64<D3>;
     extern __shared__ __align__(16) unsigned char dsm[];
+    __shared__ double lat[kBlock];   // this level's lattice energies (at most kBlock points)
+    __shared__ int sbox[6], sactive;
     const int scan = blockIdx.x;
     const int c0 = w.coarse, c1 = w.coarse, c2 = D3 ? w.coarse : 1;
     const int64_t n = (int64_t)c0 * c1 * c2;
     const bool tiled = c0 % TS::X == 0 && c1 % TS::Y == 0 && c2 % TS::Z == 0;
-    const int64_t ngroups = (n + kBlock - 1) / kBlock;
+    const ScanConst sc = scan_const(a.ss, scan);
+    uwb_segment_result &R = w.out[scan];
+    PLState st;                                                          // first wavefront
+    int box[6] = {0, w.g.dims[0], 0, w.g.dims[1], 0, w.g.dims[2]};      // first wavefront
+    if (threadIdx.x < 64) pl_init_state(w, st);
+    if (threadIdx.x < 6) {
+        sbox[threadIdx.x] = box[threadIdx.x];
+        R.box[0][threadIdx.x] = box[threadIdx.x];
+    }
+    if (threadIdx.x == 0) sactive = 1;
+    __syncthreads();
     for (int lev = 0; lev < levels; ++lev) {
-        if (!w.state[scan].active) break;   // uniform: published by the barrier closing the previous level
-        const int *box = w.out[scan].box[lev];
+        if (!sactive) break;   // uniform: published by the barrier closing the previous level
         const int step = (w.g.dims[0] >> lev) / w.coarse;
         Lat L;
         for (int d = 0; d < 3; ++d) {
             const bool act = d < 2 || D3;
-            L.x0[d] = act ? box[2 * d] + step / 2 : 0;
+            L.x0[d] = act ? sbox[2 * d] + step / 2 : 0;
             L.cnt[d] = act ? w.coarse : 1;
         }
         L.step = step;
         const int64_t off = (int64_t)lev * n;
-        if (n + off <= a.out_stride) {   // always, for a planned walk
-            for (int64_t t = 0; t < ngroups; ++t)
-                grid64_group<BF, W, MS>(a, L, scan, make_group<D3>(c0, c1, c2, tiled, t, threadIdx.x), dsm, off);
+        if (n <= kBlock && n + off <= a.out_stride)   // always, for a planned walk
+            grid64_group<BF, W, MS>(a, L, scan, sc, make_group<D3>(c0, c1, c2, tiled, 0, threadIdx.x), dsm, off, lat);
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            pl_level_core<D3 ? 3 : 2>(w, lev, scan, st, lat, box);
+            if (threadIdx.x < 6) sbox[threadIdx.x] = box[threadIdx.x];
+            if (threadIdx.x == 0) sactive = st.active;
         }
         __syncthreads();
-        if (threadIdx.x < 64) pl_level_step<D3 ? 3 : 2>(w, lev, scan);
-        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        w.state[scan] = st;
+        pl_finish_record(w, st, R);
     }
 }
 
@@ -230,12 +249,12 @@ __device__ __forceinline__ void taps64_mvdr(const float *p, double f, double (&S
         for (int l = 0; l <= k; ++l) gram[tri(k, l)] = fma(sv[k], sv[l], gram[tri(k, l)]);
 }
 
+// lat_lds (optional): the energies written to LDS as well, at the points' lattice offsets.
 template <int BF, int W, bool MS>
-__device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const Group &G, unsigned char *dsm,
-                             int64_t out_offset) {
+__device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const ScanConst &sc, const Group &G,
+                             unsigned char *dsm, int64_t out_offset, double *lat_lds) {
     constexpr int H = (W - 1) / 2;
     const int tid = threadIdx.x;
-    const ScanConst sc = scan_const(a.ss, scan);
     const int M = a.ss.n_ant, T = a.ss.n_samp;
     double *tab = reinterpret_cast<double *>(dsm);   // [chunk][8]
 
@@ -344,18 +363,22 @@ __device__ void grid64_group(const Grid64Args &a, const Lat &L, int scan, const 
     if (chunk < 1) e = __builtin_nan("");   // a span longer than the staging space (rejected on the host)
     if (G.valid) {
         a.out64[(int64_t)scan * a.out_stride + out_offset + G.p] = e;
+        if (lat_lds) lat_lds[G.p] = e;
         if (a.out32) a.out32[(int64_t)scan * a.out32_stride + G.p] = (float)e;
     }
 }
 
 // Staging budget per workgroup: the CU's LDS shared by as many workgroups as the
-// kernel's registers let run at once (queried once per instantiation), at most kGridLdsMax.
+// kernel's registers let run at once (queried once per instantiation), less the kernel's
+// own static LDS, at most kGridLdsMax in all.
 int lds_budget(const void *kern, int block, std::atomic<int> &cache) {
     int b = cache.load(std::memory_order_relaxed);
     if (b > 0) return b;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, block, 0) != hipSuccess || nb < 1) nb = 5;
-    b = std::min(kGridLdsMax, (kLdsPerCu / nb) & ~255);
+    hipFuncAttributes fa;
+    const int stat = hipFuncGetAttributes(&fa, kern) == hipSuccess ? (int)fa.sharedSizeBytes : 4096;
+    b = (std::min(kGridLdsMax, kLdsPerCu / nb) - stat) & ~255;
     cache.store(b, std::memory_order_relaxed);
     return b;
 }

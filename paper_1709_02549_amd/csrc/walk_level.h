@@ -185,17 +185,16 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
 
 
 // One level of the per-level walk for one scan, on one whole wavefront: the level's
-// statistics over its lattice values (lat64), the W/B test of Eqs. (6)-(7), and the
-// choice of the child (the first of the children within the tie band of the best score),
-// carrying the previous level's figures in PLState.  Writes the result record and state.
+// statistics over its lattice values (src), the W/B test of Eqs. (6)-(7), and the choice
+// of the child (the first of the children within the tie band of the best score),
+// carrying the previous level's figures in st.  box holds the level's box and receives
+// the chosen child's.  Every lane computes the same state; lane 0 writes the result
+// record (child, scores, W/B, next box), which nothing in the walk reads back.
 template <int NACT>
-__device__ void pl_level_step(const WalkArgs &a, int lev, int scan) {
+__device__ void pl_level_core(const WalkArgs &a, int lev, int scan, PLState &st, const double *src, int (&box)[6]) {
     constexpr int NCH = 1 << NACT;
-    PLState &S = a.state[scan];
-    if (!S.active) return;                     // uniform per wavefront; no workgroup barriers below
     uwb_segment_result &R = a.out[scan];
-    int box[6];
-    for (int i = 0; i < 6; ++i) box[i] = R.box[lev][i];
+    const bool writer = (threadIdx.x & 63) == 0;
     const int side = a.g.dims[0] >> lev;
     const int step = side / a.coarse;
     Lattice L;
@@ -205,12 +204,9 @@ __device__ void pl_level_step(const WalkArgs &a, int lev, int scan) {
     }
     L.step = step;
     const int P = L.count();
-    const double *src = a.lat64 + (int64_t)scan * a.lat_stride + (int64_t)lev * P;
     int cbox[8][6];
     double sc8[8];
     const LevelStats ls = wave_level_stats<NACT>(a, L, src, box, side, false, cbox, sc8);
-    if ((threadIdx.x & 63) != 0) return;       // the rest is one lane's bookkeeping
-    PLState st = S;
     st.nvox += P;
     bool stop = false;
     if (a.term == UWB_TERM_WB && lev >= 1) {
@@ -218,8 +214,10 @@ __device__ void pl_level_step(const WalkArgs &a, int lev, int scan) {
         const double W = st.prev_m2 + ls.pm2;
         const double B = st.prev_n * (st.prev_mean - pooled) * (st.prev_mean - pooled) +
                          ls.pn * (ls.pmean - pooled) * (ls.pmean - pooled);
-        R.wb[st.n_wb][0] = W;
-        R.wb[st.n_wb][1] = B;
+        if (writer) {
+            R.wb[st.n_wb][0] = W;
+            R.wb[st.n_wb][1] = B;
+        }
         ++st.n_wb;
         if (lev >= 2 && (B <= st.prev_b || W >= st.prev_w)) { st.n_kept = lev - 1; stop = true; }
         st.prev_w = W;
@@ -234,19 +232,73 @@ __device__ void pl_level_step(const WalkArgs &a, int lev, int scan) {
             stop = true;
         } else {
             double best = -INFINITY;
+#pragma unroll
             for (int c = 0; c < NCH; ++c) best = fmax(best, sc8[c]);
             const double thr = best - kTieRel * fabs(best);
             int sel = 0;
+#pragma unroll
             for (int c = NCH - 1; c >= 0; --c)
                 if (sc8[c] >= thr) sel = c;
-            R.child[st.made] = sel;
-            for (int c = 0; c < 8; ++c) R.score[st.made][c] = c < NCH ? sc8[c] : 0.0;
+            // the chosen child's box formed again rather than read from cbox[sel]: a runtime index into the
+            // child arrays would place them in scratch memory
+            int nb[6];
+            split_box(box, sel, NACT, nb);
+            if (writer) {
+                R.child[st.made] = sel;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) R.score[st.made][c] = c < NCH ? sc8[c] : 0.0;
+                for (int i = 0; i < 6; ++i) R.box[lev + 1][i] = nb[i];
+            }
             ++st.made;
-            for (int i = 0; i < 6; ++i) R.box[lev + 1][i] = cbox[sel][i];
+            for (int i = 0; i < 6; ++i) box[i] = nb[i];
         }
     }
     if (stop) st.active = 0;
-    S = st;
+}
+
+// The same level with the state, the box and the lattice values in global memory (the
+// level-synchronous walk: one wavefront per scan, after the level's lattice kernel).
+template <int NACT>
+__device__ void pl_level_step(const WalkArgs &a, int lev, int scan) {
+    PLState st = a.state[scan];
+    if (!st.active) return;                    // uniform per wavefront; no workgroup barriers below
+    int box[6];
+    for (int i = 0; i < 6; ++i) box[i] = a.out[scan].box[lev][i];
+    const int P = NACT == 3 ? a.coarse * a.coarse * a.coarse : a.coarse * a.coarse;
+    const double *src = a.lat64 + (int64_t)scan * a.lat_stride + (int64_t)lev * P;
+    pl_level_core<NACT>(a, lev, scan, st, src, box);
+    if ((threadIdx.x & 63) == 0) a.state[scan] = st;
+}
+
+// Initial state of a scan's per-level walk: level 0's box is the whole grid.
+__device__ inline void pl_init_state(const WalkArgs &a, PLState &S) {
+    S.prev_n = S.prev_mean = S.prev_m2 = S.prev_w = S.prev_b = 0.0;
+    S.nvox = 0;
+    S.active = 1;
+    S.n_kept = a.depth;
+    S.made = 0;
+    S.n_wb = 0;
+}
+
+// A finished per-level walk's record: the ROI (the last kept box widened by the final
+// frame), the counts, and the detection fields cleared for the ROI phase.
+__device__ inline void pl_finish_record(const WalkArgs &a, const PLState &st, uwb_segment_result &R) {
+    const int nact = a.g.dims[2] > 1 ? 3 : 2;
+    const int dims[3] = {a.g.dims[0], a.g.dims[1], a.g.dims[2]};
+    int roi[6];
+    expand_box(R.box[st.n_kept], a.frame_final, nact, dims, roi);
+    R.n_levels = st.n_kept;
+    R.term_level = st.made;
+    R.decimation = 0;
+    R.n_samples_level0 = (int)(nact == 3 ? a.coarse * a.coarse * a.coarse : a.coarse * a.coarse);
+    R.n_wb = st.n_wb;
+    for (int i = 0; i < 6; ++i) R.roi[i] = roi[i];
+    const int64_t rv = (int64_t)(roi[1] - roi[0]) * (roi[3] - roi[2]) * (roi[5] - roi[4]);
+    R.voxels_evaluated = st.nvox + rv;
+    R.argmax = -1;
+    R.peak = 0.0;
+    R.learned_mask = 0;
+    R.guard_hits = 0;
 }
 
 }  // namespace uwb
