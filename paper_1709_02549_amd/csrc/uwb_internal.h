@@ -2,6 +2,8 @@
 // launch helpers).  Not part of the public ABI.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -90,6 +92,19 @@ constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
 constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
 constexpr int kDppHalfMirror = 0x141;  // row_half_mirror: lane i <-> 7 - i within each 8
 constexpr int kDppMirror = 0x140;      // row_mirror: lane i <-> 15 - i within each row
+// One stage of a butterfly over aligned groups of lanes that starts at distance 1: the
+// value of the partner o lanes away (lane ^ o).  For o < 16 the partner sits in the same
+// row, and once the previous stages have made every aligned group of o lanes agree, the
+// quad permutations and the (half-)row mirrors pair the same values as the xor does, so
+// those stages run as DPP moves; o >= 16 goes through the LDS crossbar.
+template <int O>
+__device__ __forceinline__ double bfly64(double x) {
+    if constexpr (O == 1) return dpp_row64<kDppXor1>(x);
+    else if constexpr (O == 2) return dpp_row64<kDppXor2>(x);
+    else if constexpr (O == 4) return dpp_row64<kDppHalfMirror>(x);
+    else if constexpr (O == 8) return dpp_row64<kDppMirror>(x);
+    else return __shfl_xor(x, O, 64);
+}
 __device__ __forceinline__ double wave_sum(double x) {
     x += dpp_row64<kDppXor1>(x);
     x += dpp_row64<kDppXor2>(x);
@@ -352,17 +367,27 @@ __device__ double energy64_group(const ScanConst &sc, int M, int T, int window, 
                 }
             }
         }
-        for (int o = 1; o < G; o <<= 1) {
+        // the group's butterfly over 1, 2, 4, ... < G: both lanes of a pair form the same sums
+        auto stage = [&](auto oc) {
+            constexpr int O = decltype(oc)::value;
+            if (O < G) {   // uniform
 #pragma unroll
-            for (int j = 0; j < kChunk; ++j) {
-                const double So = __shfl_xor(S[j], o, 64);
-                if (BF == UWB_DMAS) {
-                    const double Po = __shfl_xor(P[j], o, 64);
-                    P[j] = P[j] + Po + S[j] * So;
+                for (int j = 0; j < kChunk; ++j) {
+                    const double So = bfly64<O>(S[j]);
+                    if (BF == UWB_DMAS) {
+                        const double Po = bfly64<O>(P[j]);
+                        P[j] = P[j] + Po + S[j] * So;
+                    }
+                    S[j] += So;
                 }
-                S[j] += So;
             }
-        }
+        };
+        stage(std::integral_constant<int, 1>{});
+        stage(std::integral_constant<int, 2>{});
+        stage(std::integral_constant<int, 4>{});
+        stage(std::integral_constant<int, 8>{});
+        stage(std::integral_constant<int, 16>{});
+        stage(std::integral_constant<int, 32>{});
 #pragma unroll
         for (int j = 0; j < kChunk; ++j) {
             if (k0 + j <= h) {
@@ -417,12 +442,21 @@ __device__ double energy64_mvdr(const ScanConst &sc, int M, int T, double rx, do
 #pragma unroll
             for (int l = 0; l <= k; ++l) gram[tri(k, l)] += sv[k] * sv[l];
     }
-    for (int o = 1; o < G; o <<= 1) {
+    auto stage = [&](auto oc) {
+        constexpr int O = decltype(oc)::value;
+        if (O < G) {   // uniform
 #pragma unroll
-        for (int q = 0; q < NG; ++q) gram[q] += __shfl_xor(gram[q], o, 64);
+            for (int q = 0; q < NG; ++q) gram[q] += bfly64<O>(gram[q]);
 #pragma unroll
-        for (int k = 0; k < W; ++k) b[k] += __shfl_xor(b[k], o, 64);
-    }
+            for (int k = 0; k < W; ++k) b[k] += bfly64<O>(b[k]);
+        }
+    };
+    stage(std::integral_constant<int, 1>{});
+    stage(std::integral_constant<int, 2>{});
+    stage(std::integral_constant<int, 4>{});
+    stage(std::integral_constant<int, 8>{});
+    stage(std::integral_constant<int, 16>{});
+    stage(std::integral_constant<int, 32>{});
     return mvdr_energy<double, W>(gram, b, M);
 }
 
