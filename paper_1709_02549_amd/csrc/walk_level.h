@@ -24,6 +24,33 @@ struct Lattice {
     }
 };
 
+// The points p, p + stride, p + 2 stride, ... of a lattice in order, their finest indices
+// formed by carries instead of a division per point (the divisions are done once).
+struct LatticeCursor {
+    int kx, ky, kz, dx, dy, dz, cx, cy;
+    __device__ LatticeCursor(const Lattice &L, int p, int stride) {
+        cx = L.cnt[0];
+        cy = L.cnt[1];
+        kx = p % cx; ky = (p / cx) % cy; kz = p / (cx * cy);
+        dx = stride % cx; dy = (stride / cx) % cy; dz = stride / (cx * cy);
+    }
+    __device__ void coord(const Lattice &L, int &x, int &y, int &z) const {
+        x = L.x0[0] + L.step * kx;
+        y = L.x0[1] + L.step * ky;
+        z = L.x0[2] + L.step * kz;
+    }
+    // dx < cx and dy < cy: at most one carry into each next index
+    __device__ void advance() {
+        kx += dx;
+        const int c0 = kx >= cx;
+        kx -= c0 ? cx : 0;
+        ky += dy + c0;
+        const int c1 = ky >= cy;
+        ky -= c1 ? cy : 0;
+        kz += dz + c1;
+    }
+};
+
 __device__ __forceinline__ bool in_box(const int *b, int x, int y, int z) {
     return x >= b[0] && x < b[1] && y >= b[2] && y < b[3] && z >= b[4] && z < b[5];
 }
@@ -83,7 +110,6 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
                                        int side, bool paper, int cbox[8][6], double sc8[8]) {
     constexpr int NCH = 1 << NACT;
     const int lane = threadIdx.x & 63;
-    const int P = L.count();
     int sbx[NCH][6];
     const int half = side / 2;
     // the per-level walk scores each child on its box widened by the level frame; the
@@ -106,9 +132,10 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
     double cn[NCH], csum[NCH], cmx[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) { cn[c] = 0.0; csum[c] = 0.0; cmx[c] = -INFINITY; }
-    for (int p = lane; p < P; p += 64) {
+    for (LatticeCursor cur(L, lane, 64); cur.kz < L.cnt[2]; cur.advance()) {
+        const int p = (cur.kz * L.cnt[1] + cur.ky) * L.cnt[0] + cur.kx;
         int x, y, z;
-        L.coord(p, x, y, z);
+        cur.coord(L, x, y, z);
         if (!in_box(box, x, y, z)) continue;
         const double v = src[p];
         pn += 1.0; psum += v; pmax = fmax(pmax, v);
@@ -123,17 +150,20 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
     for (int c = 0; c < NCH; ++c) { cn[c] = wave_sum(cn[c]); csum[c] = wave_sum(csum[c]); cmx[c] = wave_max(cmx[c]); }
     const double pmean = psum / pn;
     const double scale = pmax > 0.0 ? pmax : 1.0;    // Eq. (5) normalisation
+    // (the divisions below are taken only where the metric or a later pass uses them)
+    const bool need_mean = need2 || a.metric == UWB_MEAN || a.metric == UWB_MAX_OVER_MEAN;
     double cmean[NCH];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) cmean[c] = csum[c] / cn[c];
+    for (int c = 0; c < NCH; ++c) cmean[c] = need_mean ? csum[c] / cn[c] : 0.0;
     // pass 2: raw squared deviations and normalised sums
     double pm2 = 0.0, pnsum = 0.0, cm2[NCH], cnsum[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) { cm2[c] = 0.0; cnsum[c] = 0.0; }
     if (need2) {
-        for (int p = lane; p < P; p += 64) {
+        for (LatticeCursor cur(L, lane, 64); cur.kz < L.cnt[2]; cur.advance()) {
+            const int p = (cur.kz * L.cnt[1] + cur.ky) * L.cnt[0] + cur.kx;
             int x, y, z;
-            L.coord(p, x, y, z);
+            cur.coord(L, x, y, z);
             if (!in_box(box, x, y, z)) continue;
             const double v = src[p];
             const double vn = pmax > 0.0 ? v / scale : v;
@@ -148,18 +178,19 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
 #pragma unroll
         for (int c = 0; c < NCH; ++c) { cm2[c] = wave_sum(cm2[c]); cnsum[c] = wave_sum(cnsum[c]); }
     }
-    const double pnmean = pnsum / pn;
+    const double pnmean = need2 ? pnsum / pn : 0.0;
     double cnmean[NCH];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) cnmean[c] = cnsum[c] / cn[c];
+    for (int c = 0; c < NCH; ++c) cnmean[c] = need2 ? cnsum[c] / cn[c] : 0.0;
     // pass 3: normalised squared deviations (Eq. 5 variances)
     double pv = 0.0, cv[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) cv[c] = 0.0;
     if (need3) {
-        for (int p = lane; p < P; p += 64) {
+        for (LatticeCursor cur(L, lane, 64); cur.kz < L.cnt[2]; cur.advance()) {
+            const int p = (cur.kz * L.cnt[1] + cur.ky) * L.cnt[0] + cur.kx;
             int x, y, z;
-            L.coord(p, x, y, z);
+            cur.coord(L, x, y, z);
             if (!in_box(box, x, y, z)) continue;
             const double vn = pmax > 0.0 ? src[p] / scale : src[p];
             pv += (vn - pnmean) * (vn - pnmean);
@@ -175,10 +206,12 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
     out.pn = pn;
     out.pmean = pmean;
     out.pm2 = pm2;
+    const double pnvar = need3 ? pv / pn : 0.0;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         out.count[c] = cn[c];
-        sc8[c] = metric_value(a.metric, cn[c], cmean[c], cm2[c], cmx[c], cnmean[c], cv[c] / cn[c], pv / pn);
+        sc8[c] = metric_value(a.metric, cn[c], cmean[c], cm2[c], cmx[c], cnmean[c], need3 ? cv[c] / cn[c] : 0.0,
+                              pnvar);
     }
     return out;
 }
