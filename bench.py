@@ -143,13 +143,17 @@ def main():
         walk_bufs[bf] = (torch.empty(ctypes.sizeof(uwb.UwbSegmentResult) * B, dtype=torch.uint8, device=dev),
                          torch.empty(need, dtype=torch.uint8, device=dev))
 
-    ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2)] for k in ("img", "arg", "walk")}
+    # one pair of events per component and timed step, read back after the last step: the steps run back to
+    # back, with no host synchronisation between them
+    ev = {k: [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+          for k in ("img", "arg", "walk")}
     times = {k: [] for k in ev}
+    cur = [0]
 
     def step(record: bool):
         def mark(k, i):
             if record:
-                ev[k][i].record()
+                ev[k][cur[0]][i].record()
         # both full-resolution images from one launch (the DMAS kernel's running sums are the DAS sums),
         # with every tile's maximum of each
         mark("img", 0)
@@ -182,12 +186,13 @@ def main():
         step(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        cur[0] = i
         step(True)
-        torch.cuda.synchronize()       # per-step sync so every event pair is read back
-        for k in ev:
-            times[k].append(ev[k][0].elapsed_time(ev[k][1]))
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
+    for k in ev:
+        times[k] = [e0.elapsed_time(e1) for e0, e1 in ev[k]]
     ms_step = (t1 - t0) * 1e3 / args.steps
     va = B * nx * ny * nz * M
     # Gvoxel*antenna/s over the whole step; each pair is counted once, although its gathered samples feed both
