@@ -194,6 +194,22 @@ __global__ __launch_bounds__(kBlock) void k_pl_level(const WalkArgs a, int lev, 
     pl_level_step<NACT>(a, lev, scan);
 }
 
+// The same level step with a workgroup per scan, for octree lattices of more than
+// kWaveStatsPoints points: the four wavefronts take the statistics together.
+template <int NACT>
+__global__ __launch_bounds__(kBlock) void k_pl_level_wg(const WalkArgs a, int lev) {
+    __shared__ double red[kWaves * (3 * 8 + 3)];
+    const int scan = blockIdx.x;
+    PLState st = a.state[scan];
+    if (!st.active) return;   // uniform per workgroup
+    int box[6];
+    for (int i = 0; i < 6; ++i) box[i] = a.out[scan].box[lev][i];
+    const int P = NACT == 3 ? a.coarse * a.coarse * a.coarse : a.coarse * a.coarse;
+    const double *src = a.lat64 + (int64_t)scan * a.lat_stride + (int64_t)lev * P;
+    pl_level_core<NACT, kWaves>(a, lev, scan, st, src, box, red);
+    if (threadIdx.x == 0) a.state[scan] = st;
+}
+
 __global__ void k_pl_finish(const WalkArgs a, int n_scans) {
     const int scan = blockIdx.x * blockDim.x + threadIdx.x;
     if (scan >= n_scans) return;
@@ -628,9 +644,16 @@ int launch_walk(const WalkArgs &a, int n_scans, hipStream_t st) {
             g.out_stride = a.lat_stride;
             g.out_offset = (int64_t)lev * cnt[0] * cnt[1] * cnt[2];
             if ((rc = launch_grid64(g, cnt, g.step, n_scans, st))) return rc;
-            const dim3 gw((unsigned)((n_scans + kWaves - 1) / kWaves));
-            if (nact == 3) hipLaunchKernelGGL(k_pl_level<3>, gw, dim3(kBlock), 0, st, a, lev, n_scans);
-            else hipLaunchKernelGGL(k_pl_level<2>, gw, dim3(kBlock), 0, st, a, lev, n_scans);
+            // octree lattices of more than kWaveStatsPoints points: a workgroup per scan (chosen by the lattice
+            // alone, so that a scan's walk does not depend on its batch; planar lattices keep one wavefront per
+            // scan, as the learned walk's metric fallback does, whose scores equal the metric walk's bit for bit)
+            if (nact == 3 && (int64_t)cnt[0] * cnt[1] * cnt[2] > kWaveStatsPoints) {
+                hipLaunchKernelGGL(k_pl_level_wg<3>, dim3((unsigned)n_scans), dim3(kBlock), 0, st, a, lev);
+            } else {
+                const dim3 gw((unsigned)((n_scans + kWaves - 1) / kWaves));
+                if (nact == 3) hipLaunchKernelGGL(k_pl_level<3>, gw, dim3(kBlock), 0, st, a, lev, n_scans);
+                else hipLaunchKernelGGL(k_pl_level<2>, gw, dim3(kBlock), 0, st, a, lev, n_scans);
+            }
         }
         if (!fused) hipLaunchKernelGGL(k_pl_finish, dim3(nb), dim3(256), 0, st, a, n_scans);
     }

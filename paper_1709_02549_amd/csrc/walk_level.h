@@ -100,16 +100,42 @@ struct LevelStats {
     double count[8];
 };
 
-// The same statistics for one scan on one wavefront (no workgroup barriers): for
-// the per-level walk, whose every level's lattice lies inside its box, and for the
+// Largest octree lattice whose level statistics one wavefront takes; larger ones are split
+// over the workgroup's four wavefronts (k_pl_level_wg).
+constexpr int kWaveStatsPoints = 256;
+
+// Combines each wavefront's reduced values v[0..n) over the WAVES wavefronts of the
+// workgroup through LDS (red: WAVES x n doubles), in wavefront order: sums for the first
+// nsum values, maxima for the rest.  Every thread of the workgroup calls it.
+template <int WAVES>
+__device__ __forceinline__ void combine_waves(double *v, int n, int nsum, double *red) {
+    if constexpr (WAVES > 1) {
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0)
+            for (int i = 0; i < n; ++i) red[w * n + i] = v[i];
+        __syncthreads();
+        for (int i = 0; i < n; ++i) {
+            double t = red[i];
+            for (int k = 1; k < WAVES; ++k) t = i < nsum ? t + red[k * n + i] : fmax(t, red[k * n + i]);
+            v[i] = t;
+        }
+        __syncthreads();   // red is free for the next combine
+    }
+}
+
+// The same statistics for one scan on one wavefront (WAVES = 1, no workgroup barriers),
+// or on a whole workgroup (WAVES = 4: wavefront w takes the points p with (p / 64) % 4 = w,
+// and the wavefronts' sums are combined in wavefront order; red: LDS for the combine):
+// for the per-level walk, whose every level's lattice lies inside its box, and for the
 // paper walk (paper = true), whose samples are the decimated lattice points inside
 // the current box.  Passes 2 and 3 run only when the metric or the W/B stop needs
 // them.  Every lane returns the result.
-template <int NACT>
+template <int NACT, int WAVES = 1>
 __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, const double *src, const int *box,
-                                       int side, bool paper, int cbox[8][6], double sc8[8]) {
+                                       int side, bool paper, int cbox[8][6], double sc8[8], double *red = nullptr) {
     constexpr int NCH = 1 << NACT;
     const int lane = threadIdx.x & 63;
+    const int first = lane + 64 * (WAVES > 1 ? (int)(threadIdx.x >> 6) : 0), stride = 64 * WAVES;
     int sbx[NCH][6];
     const int half = side / 2;
     // the per-level walk scores each child on its box widened by the level frame; the
@@ -132,7 +158,7 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
     double cn[NCH], csum[NCH], cmx[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) { cn[c] = 0.0; csum[c] = 0.0; cmx[c] = -INFINITY; }
-    for (LatticeCursor cur(L, lane, 64); cur.kz < L.cnt[2]; cur.advance()) {
+    for (LatticeCursor cur(L, first, stride); cur.kz < L.cnt[2]; cur.advance()) {
         const int p = (cur.kz * L.cnt[1] + cur.ky) * L.cnt[0] + cur.kx;
         int x, y, z;
         cur.coord(L, x, y, z);
@@ -148,6 +174,21 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
     pmax = wave_max(pmax);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) { cn[c] = wave_sum(cn[c]); csum[c] = wave_sum(csum[c]); cmx[c] = wave_max(cmx[c]); }
+    if constexpr (WAVES > 1) {
+        // the sums (counts, sums) lead, the maxima follow
+        double w[3 * NCH + 3];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) { w[c] = cn[c]; w[NCH + c] = csum[c]; w[2 * NCH + 2 + c] = cmx[c]; }
+        w[2 * NCH] = pn;
+        w[2 * NCH + 1] = psum;
+        w[3 * NCH + 2] = pmax;
+        combine_waves<WAVES>(w, 3 * NCH + 3, 2 * NCH + 2, red);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) { cn[c] = w[c]; csum[c] = w[NCH + c]; cmx[c] = w[2 * NCH + 2 + c]; }
+        pn = w[2 * NCH];
+        psum = w[2 * NCH + 1];
+        pmax = w[3 * NCH + 2];
+    }
     const double pmean = psum / pn;
     const double scale = pmax > 0.0 ? pmax : 1.0;    // Eq. (5) normalisation
     // (the divisions below are taken only where the metric or a later pass uses them)
@@ -160,7 +201,7 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
 #pragma unroll
     for (int c = 0; c < NCH; ++c) { cm2[c] = 0.0; cnsum[c] = 0.0; }
     if (need2) {
-        for (LatticeCursor cur(L, lane, 64); cur.kz < L.cnt[2]; cur.advance()) {
+        for (LatticeCursor cur(L, first, stride); cur.kz < L.cnt[2]; cur.advance()) {
             const int p = (cur.kz * L.cnt[1] + cur.ky) * L.cnt[0] + cur.kx;
             int x, y, z;
             cur.coord(L, x, y, z);
@@ -177,6 +218,18 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
         pnsum = wave_sum(pnsum);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) { cm2[c] = wave_sum(cm2[c]); cnsum[c] = wave_sum(cnsum[c]); }
+        if constexpr (WAVES > 1) {
+            double w[2 * NCH + 2];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) { w[c] = cm2[c]; w[NCH + c] = cnsum[c]; }
+            w[2 * NCH] = pm2;
+            w[2 * NCH + 1] = pnsum;
+            combine_waves<WAVES>(w, 2 * NCH + 2, 2 * NCH + 2, red);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) { cm2[c] = w[c]; cnsum[c] = w[NCH + c]; }
+            pm2 = w[2 * NCH];
+            pnsum = w[2 * NCH + 1];
+        }
     }
     const double pnmean = need2 ? pnsum / pn : 0.0;
     double cnmean[NCH];
@@ -187,7 +240,7 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
 #pragma unroll
     for (int c = 0; c < NCH; ++c) cv[c] = 0.0;
     if (need3) {
-        for (LatticeCursor cur(L, lane, 64); cur.kz < L.cnt[2]; cur.advance()) {
+        for (LatticeCursor cur(L, first, stride); cur.kz < L.cnt[2]; cur.advance()) {
             const int p = (cur.kz * L.cnt[1] + cur.ky) * L.cnt[0] + cur.kx;
             int x, y, z;
             cur.coord(L, x, y, z);
@@ -201,6 +254,16 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
         pv = wave_sum(pv);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) cv[c] = wave_sum(cv[c]);
+        if constexpr (WAVES > 1) {
+            double w[NCH + 1];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) w[c] = cv[c];
+            w[NCH] = pv;
+            combine_waves<WAVES>(w, NCH + 1, NCH + 1, red);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) cv[c] = w[c];
+            pv = w[NCH];
+        }
     }
     LevelStats out;
     out.pn = pn;
@@ -223,11 +286,14 @@ __device__ LevelStats wave_level_stats(const WalkArgs &a, const Lattice &L, cons
 // carrying the previous level's figures in st.  box holds the level's box and receives
 // the chosen child's.  Every lane computes the same state; lane 0 writes the result
 // record (child, scores, W/B, next box), which nothing in the walk reads back.
-template <int NACT>
-__device__ void pl_level_core(const WalkArgs &a, int lev, int scan, PLState &st, const double *src, int (&box)[6]) {
+// With WAVES = 4 the whole workgroup takes the statistics (red: LDS for their combine) and
+// thread 0 writes the record.
+template <int NACT, int WAVES = 1>
+__device__ void pl_level_core(const WalkArgs &a, int lev, int scan, PLState &st, const double *src, int (&box)[6],
+                              double *red = nullptr) {
     constexpr int NCH = 1 << NACT;
     uwb_segment_result &R = a.out[scan];
-    const bool writer = (threadIdx.x & 63) == 0;
+    const bool writer = WAVES > 1 ? threadIdx.x == 0 : (threadIdx.x & 63) == 0;
     const int side = a.g.dims[0] >> lev;
     const int step = side / a.coarse;
     Lattice L;
@@ -239,7 +305,7 @@ __device__ void pl_level_core(const WalkArgs &a, int lev, int scan, PLState &st,
     const int P = L.count();
     int cbox[8][6];
     double sc8[8];
-    const LevelStats ls = wave_level_stats<NACT>(a, L, src, box, side, false, cbox, sc8);
+    const LevelStats ls = wave_level_stats<NACT, WAVES>(a, L, src, box, side, false, cbox, sc8, red);
     st.nvox += P;
     bool stop = false;
     if (a.term == UWB_TERM_WB && lev >= 1) {

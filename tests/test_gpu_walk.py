@@ -153,6 +153,19 @@ def test_frame_level_and_depth_limits():
         _compare(uwb().segment_refine(uwb().DeviceScan.from_host(s), s.grid, gp), oracle.walk(s, op))
 
 
+@pytest.mark.parametrize("term", ["fixed", "wb"])
+@pytest.mark.parametrize("bf", [0, 1])
+def test_walk_without_levels(term, bf):
+    """A lattice as fine as the grid (g = 16 on 16 x 16) leaves no level to split: the walk keeps the whole grid
+    as its box and ROI.  With the W/B stop the one-workgroup walk runs its single level and stops there; with
+    a fixed depth there is no level and the set-up and record kernels run alone."""
+    s = synth.c1_scan(3, n_grid=16)
+    op, gp = _params(beamformer=bf, coarse=16, term=term, frame_final=0.25)
+    g = uwb().segment_refine(uwb().DeviceScan.from_host(s), s.grid, gp)
+    _compare(g, oracle.walk(s, op))
+    assert g.n_levels == 0 and g.child == [] and tuple(g.roi) == (0, 16, 0, 16, 0, 1)
+
+
 @pytest.mark.parametrize("walk,kw", [("paper", dict(min_tumour=0.01, frame_final=0.25)),
                                      ("per_level", dict(coarse=8, frame_final=0.25)),
                                      ("paper", dict(min_tumour=0.01, frame_final=1.0))])
