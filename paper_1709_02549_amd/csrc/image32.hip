@@ -73,8 +73,10 @@ struct Args {
 // Voxels per lane of a beamformer: MVDR keeps a W x W Gram matrix per voxel, one voxel per lane.
 template <int BF> constexpr int image_vpl() { return BF == UWB_MVDR ? 1 : kImageVpl; }
 
+// Waves per SIMD asked of the register allocator: DMAS three (168 VGPRs), DAS four (the
+// multistatic DAS kernel otherwise settles at three, 9 % slower), MVDR two.
 template <int BF, int W, bool D3, bool MS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BF == UWB_MVDR ? 2 : 3)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(BF == UWB_MVDR ? 2 : BF == UWB_DAS ? 4 : 3)))
 void k_image32(const Args a) {
     constexpr int VPL = image_vpl<BF>();
     extern __shared__ __align__(16) float smem[];
