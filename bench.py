@@ -51,7 +51,7 @@ PEAK_FP32 = 157.3e12
 # batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a 256 MiB copy); valid only for the kernel
 # sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
-TRAFFIC = {"source_hash": "5de47146d8ba55e0", "batch": 256, "bytes": 590500000,
+TRAFFIC = {"source_hash": "078a80f1acdae062", "batch": 256, "bytes": 613200000,
            "valu_per_va": 45.56}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of that launch
 # LDS bytes the DMAS kernel reads per voxel·antenna at W = 11: six 16-byte records of (sample, difference)
 LDS_BYTES_DMAS = 96
