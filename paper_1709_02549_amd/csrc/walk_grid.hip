@@ -178,11 +178,11 @@ __global__ __launch_bounds__(kBlock) void k_pl_fused(const Grid64Args a, const W
     PLState st;                                                          // first wavefront
     int box[6] = {0, w.g.dims[0], 0, w.g.dims[1], 0, w.g.dims[2]};      // first wavefront
     if (threadIdx.x < 64) pl_init_state(w, st);
-    if (threadIdx.x < 6) {
-        sbox[threadIdx.x] = box[threadIdx.x];
-        R.box[0][threadIdx.x] = box[threadIdx.x];
+    if (threadIdx.x < 6) sbox[threadIdx.x] = box[threadIdx.x];
+    if (threadIdx.x == 0) {   // every record field the finishing step reads back is written by this thread
+        for (int i = 0; i < 6; ++i) R.box[0][i] = box[i];
+        sactive = 1;
     }
-    if (threadIdx.x == 0) sactive = 1;
     __syncthreads();
     for (int lev = 0; lev < levels; ++lev) {
         if (!sactive) break;   // uniform: published by the barrier closing the previous level
