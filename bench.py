@@ -7,7 +7,8 @@ step processes the whole batch, inputs already resident in HBM:
   full-resolution DAS and DMAS images (one gather feeds both)  -> FP64-decided
   argmax of each; coarse-to-fine quadtree walks (g = 16 down to 16 x 16 boxes,
   metric = max) with DAS and with DMAS, each ending in a full-resolution ROI and
-  its argmax.
+  its argmax.  The two argmaxes and the two walks are independent of each other
+  and run at once on four streams after the imaging launch.
 value = full-resolution voxel*antenna pairs per second over the whole step (walks
 and argmax included in the time), each pair counted once although it feeds both
 the DAS and the DMAS image.
@@ -131,9 +132,11 @@ def main():
     walk_out = {}
     ws_argmax = {bf: torch.empty(int(uwb.lib().uwb_argmax_tilemax_workspace_bytes(
         __import__("ctypes").byref(uwb.grid_c(grid)), B)), dtype=torch.uint8, device=dev) for bf in (0, 1)}
-    # the DAS and DMAS detections, and the two walks, are independent and latency-bound: each pair runs
-    # on two streams (default priority), the DMAS one on `side`, forked from and joined to the main stream
+    # the DAS and DMAS detections and the two walks are independent of each other and latency-bound: after
+    # the imaging launch the four run at once on four streams (default priority), forked from and joined to
+    # the main stream -- the DAS detection on main, the DMAS one on `side`, the walks on `walk_s`
     side = torch.cuda.Stream(device=dev)
+    walk_s = {bf: torch.cuda.Stream(device=dev) for bf in (0, 1)}
     ws_walk = {bf: uwb.Workspace() for bf in (0, 1)}
     walk_bufs = {}
     for bf in (0, 1):
@@ -161,20 +164,21 @@ def main():
         mark("img", 1)
         main = torch.cuda.current_stream(dev)
         mark("arg", 0)
-        side.wait_stream(main)
+        mark("walk", 0)
+        for st in (side, walk_s[0], walk_s[1]):
+            st.wait_stream(main)
+        for bf in (1, 0):
+            out, ws = walk_bufs[bf]
+            with torch.cuda.stream(walk_s[bf]):
+                uwb.segment_refine_batch_async(batch, grid, trees[bf], W, out=out, workspace=ws, bc=bc)
         with torch.cuda.stream(side):
             uwb.argmax_batch_tilemax_async(batch, grid, img_dmas, tm_dmas, 1, W, pk_dmas, ws_argmax[1], bc=bc)
         uwb.argmax_batch_tilemax_async(batch, grid, img_das, tm_das, 0, W, pk_das, ws_argmax[0], bc=bc)
         main.wait_stream(side)
         mark("arg", 1)
-        mark("walk", 0)
-        side.wait_stream(main)
-        for bf in (1, 0):
-            out, ws = walk_bufs[bf]
-            with torch.cuda.stream(side if bf == 1 else main):
-                uwb.segment_refine_batch_async(batch, grid, trees[bf], W, out=out, workspace=ws, bc=bc)
-        main.wait_stream(side)
-        mark("walk", 1)
+        main.wait_stream(walk_s[0])
+        main.wait_stream(walk_s[1])
+        mark("walk", 1)   # from the fork: the detections and the walks together
 
     if args.copy_ref_mib > 0:
         src = torch.ones(args.copy_ref_mib * 262144, dtype=torch.float32, device=dev)
@@ -221,7 +225,7 @@ def main():
         sep["dmas"] = launch_ms(lambda: uwb.image_batch(batch, grid, 1, W, img_dmas, bc=bc))
     dmas_ms = sep.get("dmas", med["img"])
 
-    # each walk on its own (the step runs the DAS and the DMAS walk on two streams at once)
+    # each walk on its own (the step runs both walks and both detections at once, each on a stream of its own)
     def walk_once(bf):
         out, ws = walk_bufs[bf]
         uwb.segment_refine_batch_async(batch, grid, trees[bf], W, out=out, workspace=ws, bc=bc)
@@ -238,7 +242,7 @@ def main():
     # same calls replayed as one HIP graph (kernels only: no memsets, no host synchronisation)
     wg = torch.cuda.CUDAGraph()
     with torch.cuda.graph(wg):
-        cap = torch.cuda.current_stream(dev)       # the two walks forked onto two streams, as in the step
+        cap = torch.cuda.current_stream(dev)       # the two walks forked onto two streams
         side.wait_stream(cap)
         for bf in (1, 0):
             out, ws = walk_bufs[bf]
@@ -309,7 +313,10 @@ def main():
                      "valu_issue_frac": round(va_rate * TRAFFIC["valu_per_va"] / 64 / VALU_ISSUE_PEAK, 4)
                      if counters_valid else None},
         "value_counts": "each full-resolution voxel·antenna once; one gather feeds both the DAS and the DMAS image",
-        "components_ms": {k: round(v, 5) for k, v in med.items()},
+        # per step (medians): the imaging launch; then, from the fork after it, the two detections done, and the
+        # two detections and the two walks done (the four run at once on four streams)
+        "components_ms": {"img": round(med["img"], 5), "detections": round(med["arg"], 5),
+                          "detections_and_walks": round(med["walk"], 5)},
         "detection_ms": {"dmas_from_tile_maxima": round(arg_alone[1], 5), "das_from_tile_maxima": round(arg_alone[0], 5),
                          "dmas_with_its_own_image_pass": round(arg_pass, 5)},
         "das_dmas_one_launch_gvas_per_image": round(va / (med["img"] * 1e-3) / 1e9, 2),
@@ -323,7 +330,6 @@ def main():
             "dmas_walk_scans_per_s": round(B / (walk_alone[1] * 1e-3), 1),
             "das_walk_scans_per_s": round(B / (walk_alone[0] * 1e-3), 1),
             "walk_ms": {"dmas": round(walk_alone[1], 5), "das": round(walk_alone[0], 5),
-                        "both_on_two_streams": round(med["walk"], 5),
                         "both_on_two_streams_hip_graph": round(walk_graph_ms, 5)},
             # full-resolution DMAS imaging plus its detection, timed on their own
             "full_dmas_scans_per_s": round(B / ((dmas_ms + arg_alone[1]) * 1e-3), 1),
