@@ -245,6 +245,16 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
     // voxel v of the lane: y = vy0 + 16 v (2D) or z = vz0 + 4 v (3D)
     auto VY = [&](int v) { return D3 ? vy0 : vy0 + 16 * v; };
     auto VZ = [&](int v) { return D3 ? vz0 + 4 * v : vz0; };
+    // the coordinate in which the lane's voxels differ, as FP32, converted once for all channels
+    // (DMAS and MVDR up to W = 11: 1.5-2 % faster); the DAS kernel, at four waves, and the wider
+    // windows, whose accumulators already spill, keep converting it per channel
+    constexpr bool kHoistCoord = BF != UWB_DAS && W <= 11;
+    float fvv[VPL];
+    if constexpr (kHoistCoord) {
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) fvv[v] = (float)(D3 ? VZ(v) : VY(v));
+    }
+    auto FV = [&](int v) { return kHoistCoord ? fvv[v] : (float)(D3 ? VZ(v) : VY(v)); };
 
     // per sub-tile and wavefront: the maxima of the image and of the DAS image (tile maxima)
     __shared__ float tile_red[kMaxSubtiles][2][kBlock / 64];
@@ -352,8 +362,8 @@ __device__ __forceinline__ void image_tile(const TileJob &j, float *smem) {
                 else { const float dy = fmaf((float)vy0, qy, t.y); part = fmaf(dy, dy, dx * dx); }
             };
             auto leg_v = [&](const float4 &t, float part, int v) {
-                if (!D3) { const float dy = fmaf((float)VY(v), qy, t.y); return fmaf(dy, dy, part); }
-                const float dz = fmaf((float)VZ(v), qz, t.z);
+                if (!D3) { const float dy = fmaf(FV(v), qy, t.y); return fmaf(dy, dy, part); }
+                const float dz = fmaf(FV(v), qz, t.z);
                 return fmaf(dz, dz, part);
             };
             float part, partr = 0.f;
