@@ -52,10 +52,12 @@ PEAK_FP32 = 157.3e12
 # batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a 256 MiB copy); valid only for the kernel
 # sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
-TRAFFIC = {"source_hash": "078a80f1acdae062", "batch": 256, "bytes": 613200000,
-           "valu_per_va": 45.56}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of that launch
-# LDS bytes the DMAS kernel reads per voxel·antenna at W = 11: six 16-byte records of (sample, difference)
-LDS_BYTES_DMAS = 96
+TRAFFIC = {"source_hash": "b83de0123ea7e0ee", "batch": 256, "bytes": 632400000,
+           "valu_per_va": 44.84}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of that launch
+# LDS bytes the DMAS kernel reads per lane and voxel·antenna at W = 11: the 11 taps' (sample, difference)
+# pairs as five 16-byte reads and one 8-byte read (the channel's table entry, read once per four voxels at
+# one address for the whole wavefront, is not counted)
+LDS_BYTES_DMAS = 88
 VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 2   # wave64 FP32 VALU instructions/s (two cycles each)
 
 
@@ -305,7 +307,7 @@ def main():
                      "hbm_frac": round(traffic / (med["img"] * 1e-3) / 8e12, 4) if traffic else None,
                      # the gather's other on-chip bounds: LDS reads against the LDS read bandwidth measured on
                      # this device -- the kernel reads W + 1 = 12 samples (48 B) of algorithmic data per
-                     # voxel·antenna, as six 16-byte records of (sample, difference) pairs (96 B) -- and VALU
+                     # voxel·antenna, as eleven 8-byte (sample, difference) pairs (88 B) -- and VALU
                      # issue (counted instructions, while the sources match the counters)
                      "lds_bytes_per_voxel_antenna": LDS_BYTES_DMAS,
                      "lds_frac": round(va_rate * LDS_BYTES_DMAS / lds["bytes_per_s"], 4),
