@@ -85,7 +85,7 @@ def test_ragged_grids(bf, dims):
     assert uwb().argmax(ds, g, img, bf).index == oracle.argmax_grid(want)[0]
 
 
-@pytest.mark.parametrize("window", [1, 3, 5, 31])
+@pytest.mark.parametrize("window", [1, 3, 5, 9, 13, 31])
 @pytest.mark.parametrize("bf", [0, 1])
 def test_windows(window, bf):
     s = synth.c1_scan(5, n_grid=48)
