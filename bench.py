@@ -99,7 +99,7 @@ def main():
                     help="before timing, run one plain device copy of this many MiB (HBM counter reference)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only (--gpus 1); multi-GPU sharding is not part of this build",
+        print("bench.py runs on one GPU only (--gpus 1); multi-GPU sharding is not implemented",
               file=sys.stderr)
         sys.exit(2)
 

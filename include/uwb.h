@@ -35,7 +35,7 @@ enum uwb_status {
     UWB_ERANGE = -2,        /* output or workspace too small, too many levels */
     UWB_ENOMEM = -3,        /* allocation inside a plan failed */
     UWB_EHIP = -4,          /* HIP launch or runtime error */
-    UWB_EUNSUPPORTED = -5   /* valid request outside what this build handles */
+    UWB_EUNSUPPORTED = -5   /* valid request outside what the library handles */
 };
 
 enum uwb_beamformer { UWB_DAS = 0, UWB_DMAS = 1, UWB_MVDR = 2 };
