@@ -52,7 +52,7 @@ PEAK_FP32 = 157.3e12
 # batch, from two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a 256 MiB copy); valid only for the kernel
 # sources they were taken on (profiles/k_image32_c2_batch256_pmc.md).
-TRAFFIC = {"source_hash": "b83de0123ea7e0ee", "batch": 256, "bytes": 632400000,
+TRAFFIC = {"source_hash": "b83de0123ea7e0ee", "batch": 256, "bytes": 640500000,
            "valu_per_va": 44.84}   # SQ_INSTS_VALU per voxel·antenna (64-lane wave slot) of that launch
 # LDS bytes the DMAS kernel reads per lane and voxel·antenna at W = 11: the 11 taps' (sample, difference)
 # pairs as five 16-byte reads and one 8-byte read (the channel's table entry, read once per four voxels at
@@ -73,8 +73,8 @@ def _kernel_source_hash() -> str:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--distinct", type=int, default=0, help="distinct seeded scans in the batch (0: all)")
     ap.add_argument("--coarse", type=int, default=16, help="walk lattice points per side (g)")
@@ -208,7 +208,7 @@ def main():
     med = {k: float(np.median(v)) for k, v in times.items()}
 
     # the two beamformers as separate launches (after the timed steps), for their own rates
-    def launch_ms(fn, reps=7):
+    def launch_ms(fn, reps=51):
         fn()
         torch.cuda.synchronize()
         ts = []
@@ -232,12 +232,12 @@ def main():
         out, ws = walk_bufs[bf]
         uwb.segment_refine_batch_async(batch, grid, trees[bf], W, out=out, workspace=ws, bc=bc)
 
-    walk_alone = {bf: launch_ms(lambda bf=bf: walk_once(bf), reps=21) for bf in (0, 1)}
+    walk_alone = {bf: launch_ms(lambda bf=bf: walk_once(bf)) for bf in (0, 1)}
     arg_alone = {bf: launch_ms(lambda bf=bf: uwb.argmax_batch_tilemax_async(
         batch, grid, img_dmas if bf else img_das, tm_dmas if bf else tm_das, bf, W, pk_dmas if bf else pk_das,
-        ws_argmax[bf], bc=bc), reps=21) for bf in (0, 1)}
+        ws_argmax[bf], bc=bc)) for bf in (0, 1)}
     # the same detection making its own pass over the image (uwb_argmax_batch), for comparison
-    arg_pass = launch_ms(lambda: uwb.argmax_batch_async(batch, grid, img_dmas, 1, W, bc=bc), reps=21)
+    arg_pass = launch_ms(lambda: uwb.argmax_batch_async(batch, grid, img_dmas, 1, W, bc=bc))
     # the last launches above leave the step's detections and walk results in place for the accuracy checks
 
     # the two walks of a step are launch-bound at this batch (about a dozen small kernels each): the
@@ -449,9 +449,9 @@ def mvdr_block(args, uwb, synth, dev):
     b = uwb.DeviceBatch.from_host(scans, dev)
     bc = b.c()
     img = torch.empty((n, nz, ny, nx), dtype=torch.float32, device=dev)
-    t_img = _event_ms(lambda: uwb.image_batch(b, g, 2, out=img, bc=bc), reps=11)
+    t_img = _event_ms(lambda: uwb.image_batch(b, g, 2, out=img, bc=bc), )
     pk = uwb.argmax_batch_async(b, g, img, 2, bc=bc)
-    t_arg = _event_ms(lambda: uwb.argmax_batch_async(b, g, img, 2, out=pk, bc=bc), reps=11)
+    t_arg = _event_ms(lambda: uwb.argmax_batch_async(b, g, img, 2, out=pk, bc=bc), )
     full = uwb._peaks(pk, n)
     va = n * nx * ny * nz * M
     res = {}
@@ -462,7 +462,7 @@ def mvdr_block(args, uwb, synth, dev):
                          dtype=torch.uint8, device=dev)
         rb = torch.empty(ctypes.sizeof(uwb.UwbSegmentResult) * n, dtype=torch.uint8, device=dev)
         t_w = _event_ms(lambda tree=tree, ws=ws, rb=rb: uwb.segment_refine_batch_async(
-            b, g, tree, out=rb, workspace=ws, bc=bc), reps=11)
+            b, g, tree, out=rb, workspace=ws, bc=bc), )
         rr = uwb._results(rb, n, 4)
         w1 = float(np.mean([abs(r.argmax % nx - f.index % nx) <= 1 and abs(r.argmax // nx - f.index // nx) <= 1
                             for r, f in zip(rr, full)]))
@@ -519,10 +519,10 @@ def c3_block(args, uwb, synth, dev):
     ds = uwb.DeviceScan.from_host(scans[0], dev)
     das = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
     dmas = torch.empty_like(das)
-    t = {"das_ms": _event_ms(lambda: uwb.image(ds, g, 0, out=das), reps=11),
-         "dmas_ms": _event_ms(lambda: uwb.image(ds, g, 1, out=dmas), reps=11),
-         "das_dmas_one_launch_ms": _event_ms(lambda: uwb.das_dmas(ds, g, out_das=das, out_dmas=dmas), reps=11),
-         "argmax_dmas_ms": _event_ms(lambda: uwb.argmax_async(ds, g, dmas, 1), reps=11)}
+    t = {"das_ms": _event_ms(lambda: uwb.image(ds, g, 0, out=das), ),
+         "dmas_ms": _event_ms(lambda: uwb.image(ds, g, 1, out=dmas), ),
+         "das_dmas_one_launch_ms": _event_ms(lambda: uwb.das_dmas(ds, g, out_das=das, out_dmas=dmas), ),
+         "argmax_dmas_ms": _event_ms(lambda: uwb.argmax_async(ds, g, dmas, 1), )}
     del das
     # full-resolution DMAS detection of every scan (the reference of the walks' localisation error)
     full = []
@@ -551,7 +551,7 @@ def c3_block(args, uwb, synth, dev):
             ws = torch.empty(need, dtype=torch.uint8, device=dev)
             res_buf = torch.empty(ctypes.sizeof(uwb.UwbSegmentResult) * n, dtype=torch.uint8, device=dev)
             ms = _event_ms(lambda tree=tree, ws=ws, res_buf=res_buf: uwb.segment_refine_batch_async(
-                b, g, tree, out=res_buf, workspace=ws, bc=bc), reps=11)
+                b, g, tree, out=res_buf, workspace=ws, bc=bc), )
             res = uwb._results(res_buf, n, 8)
             w1 = float(np.mean([within1(r.argmax, f) for r, f in zip(res, full)]))
             vox = float(np.mean([r.voxels_evaluated for r in res]))
@@ -571,7 +571,7 @@ def c3_block(args, uwb, synth, dev):
             "walk_scans": n, "octree_walks": walks}
 
 
-def _timed(fn, reps=5):
+def _timed(fn, reps=50):
     import torch
     fn()
     torch.cuda.synchronize()
@@ -600,7 +600,7 @@ def c4_block(args, uwb, synth, dev):
     for bf, name in ((0, "das"), (1, "dmas")):
         plan = uwb.BatchPlan([(d, s.grid, o) for d, s, o in zip(devs, scans, outs)], bf)
         cfg = plan.autotune(3)
-        ms = _timed(plan.run, reps=10)
+        ms = _timed(plan.run)
         plan.run()
         ts = plan.timestamps_ns() / 1e6
         res[name] = {"scans_per_s": round(n / (ms * 1e-3), 1), "ms_per_launch": round(ms, 4),
